@@ -1,0 +1,433 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test fixes part of the oracle by mathematics or by an independent
+computation, so that a dropped term, a wrong sign or index, or a transposed
+operand fails at least one of them:
+
+* the literal operator-by-operator Hamiltonian (brute-force checker), itself
+  pinned by textbook facts (one-electron spectrum = eig(h), a doubly occupied
+  single orbital, invariance of the FCI energy under orbital rotations);
+* a hand-worked two-orbital example;
+* closed-form contribution counts;
+* identities the paper states (duplicate removal for an eigenvector
+  reference, Section V) and invariances of the Epstein-Nesbet sum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def system(norb, na, nb, seed, nchol=8):
+    h, eri, _ = synth.make_integrals(norb, nchol, seed)
+    return h, eri
+
+
+def all_dets(norb, na, nb):
+    B = oracle.Brute(*system(norb, na, nb, 0), norb, na, nb)
+    return B.keys_of(np.arange(B.dim()))
+
+
+# --------------------------------------------------------------------------
+# Pins of the brute-force checker (textbook facts)
+
+def test_one_electron_spectrum_is_eig_h():
+    norb = 5
+    h, eri = system(norb, 1, 0, 11)
+    B = oracle.Brute(h, eri, norb, 1, 0)
+    H = B.dense()
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(H)), np.sort(np.linalg.eigvalsh(h)),
+                               atol=1e-13)
+
+
+def test_doubly_occupied_single_orbital():
+    h = np.array([[-1.25]])
+    eri = np.array([0.7])
+    B = oracle.Brute(h, eri, 1, 1, 1)
+    assert B.dense()[0, 0] == pytest.approx(2 * -1.25 + 0.7, abs=1e-15)
+
+
+def _rotate(h, eri, U):
+    n = h.shape[0]
+    g = eri.reshape(n, n, n, n)
+    g = np.einsum("pa,qb,rc,sd,abcd->pqrs", U, U, U, U, g, optimize=True)
+    return U @ h @ U.T, g.reshape(-1)
+
+
+@pytest.mark.parametrize("norb,na,nb", [(4, 2, 1), (5, 2, 2), (4, 3, 0)])
+def test_fci_energy_invariant_under_orbital_rotation(norb, na, nb):
+    h, eri = system(norb, na, nb, 21)
+    U, _ = np.linalg.qr(np.random.default_rng(3).normal(size=(norb, norb)))
+    h2, eri2 = _rotate(h, eri, U)
+    e1 = np.linalg.eigvalsh(oracle.Brute(h, eri, norb, na, nb).dense())
+    e2 = np.linalg.eigvalsh(oracle.Brute(h2, eri2, norb, na, nb).dense())
+    np.testing.assert_allclose(e1, e2, atol=1e-11)
+
+
+def test_brute_hamiltonian_is_symmetric():
+    h, eri = system(6, 2, 2, 5)
+    H = oracle.Brute(h, eri, 6, 2, 2).dense()
+    np.testing.assert_allclose(H, H.T, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Hand-worked example: one alpha and one beta electron in two orbitals,
+# reference = {HF}.  Slater-Condon by hand:
+#   single (either spin):  F_01 = h01 + (01|00)          = 0.15
+#   double (alpha and beta 0->1): (01|01)                = 0.15
+#   H_00 = 2 h00 + (00|00) = -1.4 ; H_single = h00 + h11 + (00|11) = -1.1
+#   H_double = 2 h11 + (11|11) = -0.5
+#   E_PT2 = 2 * 0.15^2/(-0.3) + 0.15^2/(-0.9) = -0.175
+
+def two_orbital_example():
+    h = np.array([[-1.0, 0.1], [0.1, -0.5]])
+    g = np.zeros((2, 2, 2, 2))
+    vals = {(0, 0, 0, 0): 0.6, (1, 1, 1, 1): 0.5, (0, 0, 1, 1): 0.4, (0, 1, 0, 1): 0.15,
+            (0, 0, 0, 1): 0.05, (0, 1, 1, 1): 0.03}
+    for (p, q, r, s), v in vals.items():
+        for a, b, c, d in {(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
+                           (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)}:
+            g[a, b, c, d] = v
+    return h, g.reshape(-1)
+
+
+def test_hand_worked_two_orbital_example():
+    h, eri = two_orbital_example()
+    O = oracle.Oracle(h, eri, 2, 1, 1)
+    hf = synth.hf_key(2, 1, 1)[None]
+    assert O.diag(hf)[0] == pytest.approx(-1.4, abs=1e-15)
+    res, _ = O.pt2(hf, [1.0], -1.4)
+    assert res["e_pt2"] == pytest.approx(-0.175, abs=1e-15)
+    assert res["n_contrib"] == 3 and res["n_external"] == 3
+    B = oracle.Brute(h, eri, 2, 1, 1)
+    e, n = B.pt2(hf, [1.0], -1.4)
+    assert e == pytest.approx(-0.175, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Oracle against the brute-force checker
+
+@pytest.mark.parametrize("norb,na,nb,nref,seed", [
+    (6, 2, 2, 20, 1), (7, 3, 2, 40, 2), (5, 1, 0, 2, 3), (8, 3, 3, 60, 4), (7, 2, 3, 30, 5),
+    (5, 2, 0, 3, 6), (6, 0, 2, 4, 7)])
+def test_oracle_matches_brute_force_tiny(norb, na, nb, nref, seed):
+    h, eri = system(norb, na, nb, seed)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    rng = np.random.default_rng(seed)
+    keys = B.keys_of(np.arange(B.dim()))
+    pick = rng.choice(len(keys), size=min(nref, len(keys)), replace=False)
+    R = keys[pick]
+    c = rng.normal(size=len(R))
+    c /= np.linalg.norm(c)
+    e0 = float(rng.uniform(-30, -10))
+    res, _ = O.pt2(R, c, e0)
+    e_b, n_b = B.pt2(R, c, e0)
+    assert res["e_pt2"] == pytest.approx(e_b, abs=1e-12)
+    assert res["n_contrib"] == len(R) * synth.n_excitations_per_det(norb, na, nb)
+
+
+def test_oracle_matches_dense_complement_formula():
+    """PT2 = sum over the complement of (H_PR c)^2 / (E0 - H_aa) from a dense FCI H."""
+    norb, na, nb = 6, 2, 2
+    h, eri = system(norb, na, nb, 31)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    H = B.dense()
+    keys = B.keys_of(np.arange(B.dim()))
+    R_idx = np.arange(0, B.dim(), 7)
+    Hrr = H[np.ix_(R_idx, R_idx)]
+    w, V = np.linalg.eigh(Hrr)
+    c, e0 = V[:, 0], w[0]
+    P_idx = np.setdiff1d(np.arange(B.dim()), R_idx)
+    v = H[np.ix_(P_idx, R_idx)] @ c
+    expect = float(np.sum(v ** 2 / (e0 - np.diag(H)[P_idx])))
+    res, _ = oracle.Oracle(h, eri, norb, na, nb).pt2(keys[R_idx], c, e0)
+    assert res["e_pt2"] == pytest.approx(expect, abs=1e-12)
+
+
+def test_matrix_elements_match_brute_force():
+    """Every emitted payload of a single reference equals <a|H|D> of the dense H."""
+    norb, na, nb = 7, 3, 2
+    h, eri = system(norb, na, nb, 41)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    H = B.dense()
+    keys = B.keys_of(np.arange(B.dim()))
+    for j in np.random.default_rng(1).choice(len(keys), 12, replace=False):
+        ek, ev = O.emit(keys[j][None], [1.0])
+        idx = B.index_of(ek)
+        np.testing.assert_allclose(ev, H[idx, j], atol=1e-13)
+        # every determinant connected to D is emitted exactly once
+        connected = np.nonzero(np.abs(H[:, j]) > 0)[0]
+        connected = connected[connected != j]
+        assert set(connected.tolist()) <= set(idx.tolist())
+        assert len(set(idx.tolist())) == len(idx)
+        # the general pairwise rule agrees too
+        for i in idx[:40]:
+            assert O.hij(keys[i], keys[j]) == pytest.approx(H[i, j], abs=1e-13)
+
+
+def test_diagonal_matches_brute_force():
+    norb, na, nb = 8, 3, 3
+    h, eri = system(norb, na, nb, 51)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    idx = np.random.default_rng(2).choice(B.dim(), 300, replace=False)
+    np.testing.assert_allclose(O.diag(B.keys_of(idx)), B.diag(idx), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Workload C1: brute force over the 245,025-determinant FCI space
+
+def load_c1():
+    w = synth.WORKLOADS["c1"]
+    h, eri, _ = synth.make_integrals(w.norb, w.n_chol, w.seed)
+    f = np.load(synth_path("inputs_c1.npz"))
+    return w, h, eri, f["dets"], f["c"], float(f["e0"])
+
+
+def synth_path(name):
+    import os
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
+def test_c1_oracle_matches_brute_force_fci():
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    B = oracle.Brute(h, eri, w.norb, w.nalpha, w.nbeta)
+    assert B.dim() == 245_025
+    res, _ = O.pt2(dets, c, e0)
+    e_b, n_ext = B.pt2(dets, c, e0)
+    assert res["e_pt2"] == pytest.approx(e_b, abs=1e-12)
+    assert res["n_contrib"] == 284_800
+    assert res["n_external"] >= n_ext  # brute force skips exact zeros only
+
+
+def test_c1_reference_is_eigenvector_and_subtraction_identity():
+    """Duplicate removal by subtraction (Section V) holds for an eigenvector:
+    every in-reference numerator equals c_i (E0 - H_ii), so the in-reference
+    PT2-like terms are c_i^2 (E0 - H_ii)."""
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    H = O.hrr(dets)
+    np.testing.assert_allclose(H @ c, e0 * c, atol=1e-12)
+    keys, nums = O.numerators(dets, c)
+    haa = O.diag(keys)
+    allterms = float(np.sum(nums ** 2 / (e0 - haa)))
+    hii = O.diag(dets)
+    res, _ = O.pt2(dets, c, e0)
+    assert allterms - float(np.sum(c ** 2 * (e0 - hii))) == pytest.approx(res["e_pt2"], abs=1e-11)
+
+
+def test_expectation_identity_from_in_reference_numerators():
+    """sum_i c_i (N_i + H_ii c_i) = <c|H|c> for any coefficients."""
+    w, h, eri, dets, _, _ = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    c = np.random.default_rng(5).normal(size=len(dets))
+    c /= np.linalg.norm(c)
+    res, _ = O.pt2(dets, c, -20.0)
+    hii = O.diag(dets)
+    H = O.hrr(dets)
+    assert res["ref_cross"] + float(np.sum(c * c * hii)) == pytest.approx(float(c @ H @ c), abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Special cases
+
+@pytest.mark.parametrize("norb,na,nb", [(6, 2, 2), (8, 3, 3), (7, 3, 2)])
+def test_full_fci_reference_gives_zero(norb, na, nb):
+    h, eri = system(norb, na, nb, 61)
+    keys = all_dets(norb, na, nb)
+    c = np.random.default_rng(0).normal(size=len(keys))
+    res, _ = oracle.Oracle(h, eri, norb, na, nb).pt2(keys, c, -5.0)
+    assert res["e_pt2"] == 0.0
+    assert res["n_external"] == 0
+
+
+def test_hf_only_reference_closed_form():
+    norb, na, nb = 8, 3, 3
+    h, eri = system(norb, na, nb, 71)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    hf = synth.hf_key(norb, na, nb)[None]
+    H = B.dense()
+    j = B.index_of(hf)[0]
+    e0 = H[j, j]
+    col = H[:, j].copy()
+    col[j] = 0.0
+    nz = np.nonzero(col)[0]
+    expect = float(np.sum(col[nz] ** 2 / (e0 - np.diag(H)[nz])))
+    res, _ = O.pt2(hf, [1.0], e0)
+    assert res["e_pt2"] == pytest.approx(expect, abs=1e-13)
+    assert res["n_unique"] == res["n_contrib"] == synth.n_excitations_per_det(norb, na, nb)
+
+
+@pytest.mark.parametrize("norb,na,nb,expect", [
+    (12, 4, 4, 1424), (40, 10, 10, 129_750), (76, 14, 14, 1_099_322), (100, 18, 18, 3_197_754)])
+def test_closed_form_counts(norb, na, nb, expect):
+    assert synth.n_excitations_per_det(norb, na, nb) == expect
+
+
+def test_counts_equal_closed_form_enumeration():
+    norb, na, nb = 9, 3, 2
+    h, eri = system(norb, na, nb, 81)
+    keys = all_dets(norb, na, nb)[:17]
+    res, _ = oracle.Oracle(h, eri, norb, na, nb).pt2(keys, np.ones(17), -3.0)
+    assert res["n_contrib"] == 17 * synth.n_excitations_per_det(norb, na, nb)
+    # brute-force count of singles+doubles of one determinant
+    occ = lambda k: set(np.nonzero(np.unpackbits(k.view(np.uint8), bitorder="little"))[0])
+    o0 = occ(keys[0].copy())
+    alld = all_dets(norb, na, nb)
+    cnt = sum(1 for k in alld if 1 <= len(occ(k.copy()) - o0) <= 2)
+    assert cnt == synth.n_excitations_per_det(norb, na, nb)
+
+
+# --------------------------------------------------------------------------
+# Invariances of the Epstein-Nesbet sum
+
+def _perm_parity(seq):
+    inv = sum(1 for i in range(len(seq)) for j in range(i + 1, len(seq)) if seq[i] > seq[j])
+    return -1.0 if inv & 1 else 1.0
+
+
+def test_invariant_under_orbital_relabelling():
+    norb, na, nb = 7, 3, 2
+    h, eri = system(norb, na, nb, 91)
+    keys = all_dets(norb, na, nb)
+    rng = np.random.default_rng(9)
+    R = keys[rng.choice(len(keys), 50, replace=False)]
+    c = rng.normal(size=50)
+    e0 = float(oracle.Oracle(h, eri, norb, na, nb).diag(keys).min()) - 1.0
+    ref, _ = oracle.Oracle(h, eri, norb, na, nb).pt2(R, c, e0)
+
+    perm = rng.permutation(norb)
+    h2 = np.empty_like(h)
+    h2[np.ix_(perm, perm)] = h
+    g = eri.reshape(norb, norb, norb, norb)
+    g2 = np.empty_like(g)
+    g2[np.ix_(perm, perm, perm, perm)] = g
+    A, Bo = synth.unpack_keys(R, norb)
+    A2 = np.zeros_like(A)
+    B2 = np.zeros_like(Bo)
+    c2 = c.copy()
+    for i in range(len(R)):
+        oa = np.nonzero(A[i])[0]
+        ob = np.nonzero(Bo[i])[0]
+        A2[i, perm[oa]] = True
+        B2[i, perm[ob]] = True
+        c2[i] *= _perm_parity(list(perm[ob])) * _perm_parity(list(perm[oa]))
+    R2 = synth.pack_keys(A2, B2, norb)
+    res, _ = oracle.Oracle(h2, g2.reshape(-1), norb, na, nb).pt2(R2, c2, e0)
+    assert res["e_pt2"] == pytest.approx(ref["e_pt2"], abs=1e-12)
+
+
+def test_invariant_under_spin_swap():
+    norb, na, nb = 7, 3, 3
+    h, eri = system(norb, na, nb, 101)
+    keys = all_dets(norb, na, nb)
+    rng = np.random.default_rng(10)
+    R = keys[rng.choice(len(keys), 60, replace=False)]
+    c = rng.normal(size=60)
+    A, Bo = synth.unpack_keys(R, norb)
+    R2 = synth.pack_keys(Bo, A, norb)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    e0 = float(O.diag(keys).min()) - 1.0   # below every diagonal, as for a ground state
+    a, _ = O.pt2(R, c, e0)
+    b, _ = O.pt2(R2, c * (-1.0) ** (na * nb), e0)
+    assert a["e_pt2"] == pytest.approx(b["e_pt2"], abs=1e-12)
+
+
+def test_shift_and_scale():
+    norb, na, nb = 7, 2, 3
+    h, eri = system(norb, na, nb, 111)
+    keys = all_dets(norb, na, nb)
+    rng = np.random.default_rng(11)
+    R = keys[rng.choice(len(keys), 30, replace=False)]
+    c = rng.normal(size=30)
+    e0 = float(oracle.Oracle(h, eri, norb, na, nb).diag(keys).min()) - 1.0
+    base, _ = oracle.Oracle(h, eri, norb, na, nb).pt2(R, c, e0)
+    s = 0.37
+    shifted, _ = oracle.Oracle(h + s * np.eye(norb), eri, norb, na, nb).pt2(R, c, e0 + (na + nb) * s)
+    assert shifted["e_pt2"] == pytest.approx(base["e_pt2"], abs=1e-12)
+    lam = 1.7
+    scaled, _ = oracle.Oracle(lam * h, lam * eri, norb, na, nb).pt2(R, c, lam * e0)
+    assert scaled["e_pt2"] == pytest.approx(lam * base["e_pt2"], abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# The hash split of the external space (Algorithm 2 with a hash constraint)
+
+def test_splitmix64_published_outputs():
+    out = oracle.splitmix64_stream(0, 3)
+    assert [int(x) for x in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_zobrist_is_xor_of_set_bits():
+    norb = 40
+    R = oracle.zobrist_table(norb)
+    assert len(set(int(x) for x in R)) == 2 * norb
+    keys = synth.random_determinants(norb, 10, 10, 50, 3)
+    A, Bo = synth.unpack_keys(keys, norb)
+    for k in range(3, 7):
+        parts = oracle.parts_of(norb, keys, k)
+        for i in range(len(keys)):
+            z = 0
+            for p in np.nonzero(Bo[i])[0]:
+                z ^= int(R[p])
+            for p in np.nonzero(A[i])[0]:
+                z ^= int(R[norb + p])
+            assert parts[i] == z >> (64 - k)
+
+
+@pytest.mark.parametrize("log2p", [1, 3, 5])
+def test_subsets_are_complete_and_disjoint(log2p):
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    full, _ = O.pt2(dets, c, e0)
+    split, ep = O.pt2(dets, c, e0, log2p=log2p)
+    assert split["e_pt2"] == pytest.approx(full["e_pt2"], abs=1e-12)
+    assert float(np.sum(ep)) == pytest.approx(full["e_pt2"], abs=1e-12)
+    for f in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
+        assert split[f] == full[f]
+    # records of each subset belong to it, and together they are all records
+    k_all, v_all = O.emit(dets[:5], c[:5])
+    seen = 0
+    for p in range(1 << log2p):
+        k, v = O.emit(dets[:5], c[:5], log2p=log2p, part=p)
+        assert np.all(oracle.parts_of(w.norb, k, log2p) == p)
+        seen += len(k)
+    assert seen == len(k_all)
+
+
+def test_selected_subsets_match_full_split():
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    _, ep = O.pt2(dets, c, e0, log2p=4)
+    _, sel = O.pt2(dets, c, e0, log2p=4, parts=[3, 11, 0])
+    np.testing.assert_allclose(sel, ep[[3, 11, 0]], atol=1e-15)
+
+
+def test_cutoff_drops_small_terms_strictly():
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    k, v = O.emit(dets, c)
+    cut = float(np.quantile(np.abs(v), 0.3))
+    k2, v2 = O.emit(dets, c, cutoff=cut)
+    assert len(v2) == int(np.sum(np.abs(v) >= cut))
+    res, _ = O.pt2(dets, c, e0, cutoff=cut)
+    assert res["n_kept"] == len(v2) and res["n_contrib"] == len(v)
+
+
+def test_duplicate_reference_rejected():
+    w, h, eri, dets, c, e0 = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    d = np.concatenate([dets[:5], dets[2:3]])
+    with pytest.raises(ValueError):
+        O.pt2(d, np.ones(6), e0)
+
+
+def test_empty_reference():
+    w, h, eri, dets, c, e0 = load_c1()
+    res, _ = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta).pt2(dets[:0], c[:0], e0)
+    assert res["e_pt2"] == 0.0 and res["n_contrib"] == 0
