@@ -1,0 +1,222 @@
+/*
+ * pt2.h -- C-ABI of the MI355X (gfx950) Epstein-Nesbet PT2 engine.
+ *
+ * The engine evaluates, for a selected-CI reference psi = sum_i c_i |D_i>,
+ *
+ *     E_PT2 = sum_{a not in psi} N_a^2 / (E0 - H_aa),   N_a = sum_i H_ai c_i
+ *
+ * (Tubman et al., arXiv:1808.02049, Section II, the Epstein-Nesbet equation),
+ * by the sort-based method of Section III: generate every single and double
+ * excitation of every reference determinant together with its numerator term
+ * H_ai c_i (Algorithm 1, generation step), sort the terms by determinant
+ * bitstring (Algorithm 1, sort step), and make one pass over the sorted terms
+ * to form N_a, drop determinants that are in the reference, and accumulate the
+ * energy (Algorithm 1, single pass).  When the terms do not fit in device
+ * memory the external space is split into non-overlapping, complete subsets
+ * that are processed one after another (Algorithm 2, constraint PT2); here the
+ * subset of a determinant is the top k bits of a Zobrist hash of its
+ * bitstring, so the split has 2^k subsets.
+ *
+ * Conventions (the paper fixes only that alpha orbitals are the most
+ * significant digits of the bitstring, Section III, triplet constraints):
+ *   - determinant bitstring: 2*norb bits in W = pt2_key_words(norb) uint64
+ *     words, word 0 least significant; beta orbital p is bit p, alpha orbital
+ *     p is bit norb + p; bits at or above 2*norb are zero;
+ *   - |D> = product of creators of the occupied spin-orbitals in ascending bit
+ *     order acting on the vacuum; coefficients c_i refer to this ordering;
+ *   - integrals are real, chemists' notation (pq|rs), no constant term:
+ *     H = sum h_pq a+_p a_q + 1/2 sum (pq|rs) a+_p a+_r a_s a_q.
+ *
+ * Memory ownership: the caller owns every pointer it passes.  Host inputs are
+ * copied before the call returns.  The library owns the device memory it
+ * allocates (through the optional allocator hook, else hipMalloc) and frees
+ * it in pt2_destroy.
+ *
+ * Errors: every entry point returns a PT2_* code; no exception crosses the
+ * boundary.  pt2_last_error() gives a message for the calling thread.
+ *
+ * Threading: pt2_submit and pt2_poll may be called from any thread.  The
+ * pt2_evaluate* entry points serialise per context.
+ */
+#ifndef PT2_H
+#define PT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pt2_ctx pt2_ctx;
+typedef int64_t pt2_req;
+
+enum {
+    PT2_OK = 0,
+    PT2_NOT_READY = 1,      /* pt2_poll: request still running                   */
+    PT2_E_INVALID = -1,     /* bad argument or input (see pt2_last_error)        */
+    PT2_E_NOMEM = -2,       /* device or host allocation failed / budget too low */
+    PT2_E_DEVICE = -3,      /* HIP runtime error or a device-side bound tripped  */
+    PT2_E_BUSY = -4,        /* pt2_destroy with requests in flight               */
+    PT2_E_SINGULAR = -5,    /* an external E0 - H_aa is exactly zero             */
+    PT2_E_UNKNOWN_REQ = -6  /* pt2_poll: no such request                         */
+};
+
+enum {
+    PT2_FP64 = 0,          /* FP64 integrals and numerator terms                 */
+    PT2_FP32_PAYLOAD = 1   /* FP32 integrals and H_ai c_i terms; N_a, H_aa,
+                              denominators and sums stay FP64                    */
+};
+
+typedef struct {
+    uint32_t struct_size;          /* sizeof(pt2_options)                            */
+    int precision;                 /* PT2_FP64 or PT2_FP32_PAYLOAD                   */
+    double cutoff;                 /* drop a term when |H_ai c_i| < cutoff (strict;
+                                      Section IV uses 1e-8); 0 keeps every term      */
+    uint64_t device_budget_bytes;  /* device memory the engine may hold for
+                                      record buffers; 0 = 80% of free memory         */
+    uint64_t max_partition_bytes;  /* cap on the record buffers of one subset;
+                                      0 = the budget                                 */
+    int log2_partitions;           /* -1: the planner picks the split; 0 <= k <= 12
+                                      forces 2^k subsets                             */
+    int device;                    /* HIP device ordinal                             */
+    int n_streams;                 /* requests that may run at once (pt2_submit)     */
+    void *(*alloc)(size_t bytes, void *user);        /* optional device allocator   */
+    void (*free)(void *ptr, size_t bytes, void *user);
+    void *alloc_user;
+    void *stream;                  /* hipStream_t for pt2_evaluate*; NULL = own      */
+    int timing;                    /* nonzero: time phases with HIP events            */
+} pt2_options;
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(pt2_result), set by the caller               */
+    double e_pt2;             /* the energy (FP64)                                   */
+    uint64_t n_contrib;       /* structural single+double terms, duplicates and
+                                 reference hits included, before the cutoff          */
+    uint64_t n_after_cutoff;  /* terms stored and sorted                             */
+    uint64_t n_unique;        /* distinct bitstrings among stored terms              */
+    uint64_t n_external;      /* distinct bitstrings outside the reference           */
+    uint64_t n_in_ref_hit;    /* distinct bitstrings found in the reference          */
+    uint32_t n_partitions;    /* subsets evaluated                                   */
+    uint32_t n_sort_passes;   /* 8-bit digit passes launched, all subsets            */
+    double min_abs_denom;     /* min |E0 - H_aa| over external bitstrings            */
+    uint64_t n_nonneg_denom;  /* external bitstrings with E0 - H_aa >= 0             */
+    double ref_cross;         /* sum over reference hits of c_i * N_i                */
+    uint64_t key_xor;         /* XOR of a 64-bit mix of every external bitstring     */
+    uint64_t key_sum;         /* sum (mod 2^64) of the same mix                      */
+    double ms_total;          /* wall time of the call (host clock)                  */
+    double ms_gen;            /* device time (timing != 0): generation kernels       */
+    double ms_sort;           /*   onesweep digit passes only                        */
+    double ms_reduce;         /*   single pass and final sum                         */
+    double ms_hist;           /*   digit histograms, count pass, reference sort      */
+    double ms_sort_pass_max;  /*   slowest single digit pass                         */
+    double bytes_gen, bytes_sort, bytes_reduce; /* algorithmic bytes per phase       */
+} pt2_result;
+
+/* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */
+void pt2_default_options(pt2_options *opt);
+
+/* W = ceil(2*norb/64), the number of uint64 words of a determinant bitstring. */
+int pt2_key_words(int norb);
+
+/*
+ * Create a context for one Hamiltonian; integrals stay resident on the device.
+ *   h    host, norb*norb FP64, row-major, symmetric
+ *   eri  host, norb^4 FP64, row-major (pq|rs) at ((p*norb+q)*norb+r)*norb+s,
+ *        8-fold symmetric to 1e-12
+ *   1 <= norb <= 128, 0 <= nalpha, nbeta <= norb
+ *   opt  may be NULL (defaults)
+ * Errors: PT2_E_INVALID (sizes, symmetry), PT2_E_NOMEM, PT2_E_DEVICE.
+ */
+int pt2_create(const double *h, const double *eri, int norb, int nalpha, int nbeta,
+               const pt2_options *opt, pt2_ctx **out);
+
+/*
+ * Synchronous evaluation from host arrays (Algorithm 2 over the planner's
+ * split, Algorithm 1 within each subset).
+ *   dets    host, ndets x W uint64 (row i = determinant i)
+ *   coeffs  host, ndets FP64 (used as given; the library never normalises)
+ *   e0      the variational energy E_ASCI of the Epstein-Nesbet equation
+ *   out     result; out->struct_size must be sizeof(pt2_result)
+ * Every determinant must have nalpha alpha and nbeta beta electrons, no bits
+ * at or above 2*norb, and no determinant may repeat (PT2_E_INVALID).
+ * Returns PT2_E_SINGULAR if an external E0 - H_aa is exactly zero.
+ */
+int pt2_evaluate(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs, int64_t ndets,
+                 double e0, pt2_result *out);
+
+/*
+ * As pt2_evaluate, but dets and coeffs are device pointers already resident
+ * in HBM (same layout).  Work is queued on opt->stream (or the context's
+ * stream); the call returns after the result has been copied to the host.
+ * Input checks run on the device; a violation returns PT2_E_INVALID.
+ */
+int pt2_evaluate_device(pt2_ctx *ctx, const uint64_t *d_dets, const double *d_coeffs,
+                        int64_t ndets, double e0, pt2_result *out);
+
+/*
+ * Evaluate only the listed subsets of a 2^log2p split (0 <= log2p <= 12) of the external space
+ * (Algorithm 2; each subset on its own), from host arrays.
+ *   parts   host, nparts subset indices in [0, 2^log2p)
+ *   e_parts host, nparts FP64 outputs, the energy of each listed subset
+ * out holds the totals over the listed subsets.  Used to check sampled
+ * subsets of large workloads, and to shard a workload over devices.
+ */
+int pt2_evaluate_parts(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs, int64_t ndets,
+                       double e0, int log2p, const uint32_t *parts, int nparts, double *e_parts,
+                       pt2_result *out);
+
+/*
+ * Serving form.  pt2_submit copies dets and coeffs (host arrays) and queues
+ * the request; it returns at once with a request id.  Requests of every
+ * context share one device scheduler: a request starts when a stream is free
+ * and its projected record-buffer bytes fit in the device budget, and runs
+ * concurrently with the others.  pt2_poll returns PT2_NOT_READY until the
+ * request is done, then fills *out once and forgets the id (a second poll
+ * returns PT2_E_UNKNOWN_REQ).  A request that fails reports its error code
+ * from pt2_poll.  pt2_wait blocks until the request is done.
+ */
+int pt2_submit(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs, int64_t ndets,
+               double e0, pt2_req *out);
+int pt2_poll(pt2_ctx *ctx, pt2_req req, pt2_result *out);
+int pt2_wait(pt2_ctx *ctx, pt2_req req, pt2_result *out);
+
+/* Free the context; PT2_E_BUSY (and nothing freed) while requests are in flight. */
+int pt2_destroy(pt2_ctx *ctx);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *pt2_last_error(void);
+
+/*
+ * Inspection entry points (small inputs; single subset, 2^0 split).
+ *
+ * pt2_dump_records: the generated terms in generation order (sorted == 0) or
+ * after the radix sort (sorted != 0).  keys_out: cap x W uint64 (row-major);
+ * payload_out: cap FP64 (FP32 terms are widened).  *n_out = number of terms
+ * (only the first cap are written).
+ *
+ * pt2_dump_numerators: every distinct bitstring with its numerator N_a,
+ * ascending, and in_ref_out[k] = 1 if it is in the reference.
+ */
+int pt2_dump_records(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs, int64_t ndets,
+                     int sorted, uint64_t *keys_out, double *payload_out, int64_t cap,
+                     int64_t *n_out);
+int pt2_dump_numerators(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs, int64_t ndets,
+                        uint64_t *keys_out, double *num_out, uint8_t *in_ref_out, int64_t cap,
+                        int64_t *n_out);
+
+/*
+ * The engine's stable LSD radix sort on its own (Algorithm 1, sort step):
+ * sorts n records by the low key_bits bits of their W-word keys, ascending,
+ * equal keys keeping their input order.  keys: host, n x W uint64 row-major
+ * (sorted in place); payload: host, n elements of payload_bytes (4 or 8),
+ * permuted alongside.  device selects the GPU.
+ */
+int pt2_sort_records(int device, int W, int key_bits, uint64_t *keys, void *payload,
+                     int payload_bytes, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT2_H */

@@ -274,20 +274,23 @@ typedef struct {
     uint64_t n_candidates; /* candidates whose subset is kept */
 } orc_emit_ctx;
 
-/* Emit one candidate if its subset is kept and it passes the cutoff. */
-static int emit(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double hval, double ci, uint64_t seq)
+/* Emit one candidate if its subset is kept and it passes the cutoff.  z is
+ * the Zobrist hash of the candidate: the parent's hash XOR the words of the
+ * flipped bits (XOR hashing is incremental by construction). */
+static int emit(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, uint64_t z, double hval, double ci,
+                uint64_t seq)
 {
-    if (E->log2p > 0) {
-        uint32_t p = part_of(zobrist(E->R, key, 2 * E->s->norb), E->log2p);
-        if (!E->keep[p])
-            return 0;
-    }
+    if (E->log2p > 0 && !E->keep[part_of(z, E->log2p)])
+        return 0;
     E->n_candidates++;
     double v = hval * ci;
     if (E->cutoff > 0.0 && fabs(v) < E->cutoff)
         return 0;
     return vec_push(out, key, E->W, v, seq);
 }
+
+/* Subset test done before the matrix element is evaluated. */
+static int kept(const orc_emit_ctx *E, uint64_t z) { return E->log2p == 0 || E->keep[part_of(z, E->log2p)]; }
 
 /* All singles and doubles of one reference determinant, in a fixed order:
  * alpha singles, beta singles, alpha-alpha doubles, beta-beta doubles,
@@ -298,6 +301,8 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
     int n = s->norb, W = E->W;
     uint64_t k1[ORC_MAXW], k2[ORC_MAXW];
     uint64_t seq = seq0;
+    const uint64_t zp = zobrist(E->R, key, 2 * n);
+    const uint64_t *R = E->R;
 
     for (int spin = 0; spin < 2; spin++)
         for (int r = 0; r < n; r++) {
@@ -309,8 +314,13 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                 memcpy(k1, key, sizeof(uint64_t) * W);
                 flip_bit(k1, spin_bit(s, spin, r));
                 flip_bit(k1, spin_bit(s, spin, a));
+                uint64_t z = zp ^ R[spin_bit(s, spin, r)] ^ R[spin_bit(s, spin, a)];
+                if (!kept(E, z)) {
+                    seq++;
+                    continue;
+                }
                 double hv = phase_move(s, key, spin, r, a) * single_value(s, key, spin, r, a);
-                if (emit(E, out, k1, hv, ci, seq++))
+                if (emit(E, out, k1, z, hv, ci, seq++))
                     return -1;
             }
         }
@@ -333,8 +343,14 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                         flip_bit(k2, spin_bit(s, spin, t));
                         flip_bit(k2, spin_bit(s, spin, a));
                         flip_bit(k2, spin_bit(s, spin, b));
+                        uint64_t z = zp ^ R[spin_bit(s, spin, r)] ^ R[spin_bit(s, spin, t)] ^
+                                     R[spin_bit(s, spin, a)] ^ R[spin_bit(s, spin, b)];
+                        if (!kept(E, z)) {
+                            seq++;
+                            continue;
+                        }
                         double hv = double_same(s, key, spin, r, t, a, b);
-                        if (emit(E, out, k2, hv, ci, seq++))
+                        if (emit(E, out, k2, z, hv, ci, seq++))
                             return -1;
                     }
                 }
@@ -353,13 +369,19 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                 for (int b = 0; b < n; b++) {
                     if (get_bit(key, spin_bit(s, 1, b)))
                         continue;
+                    uint64_t z = zp ^ R[spin_bit(s, 0, r)] ^ R[spin_bit(s, 0, a)] ^ R[spin_bit(s, 1, t)] ^
+                                 R[spin_bit(s, 1, b)];
+                    if (!kept(E, z)) {
+                        seq++;
+                        continue;
+                    }
                     memcpy(k2, key, sizeof(uint64_t) * W);
                     flip_bit(k2, spin_bit(s, 0, r));
                     flip_bit(k2, spin_bit(s, 0, a));
                     flip_bit(k2, spin_bit(s, 1, t));
                     flip_bit(k2, spin_bit(s, 1, b));
                     double hv = double_opp(s, key, r, a, t, b);
-                    if (emit(E, out, k2, hv, ci, seq++))
+                    if (emit(E, out, k2, z, hv, ci, seq++))
                         return -1;
                 }
             }

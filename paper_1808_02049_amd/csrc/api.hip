@@ -1,0 +1,1306 @@
+// Host runtime of the PT2 engine: the C-ABI of include/pt2.h.
+//
+// A context holds one Hamiltonian resident in HBM.  An evaluation
+//   1. copies / checks the reference determinants and sorts them (the sorted
+//      list is what the single pass merges against);
+//   2. plans the split of the external space (Algorithm 2): the record buffers
+//      of one subset, two ping-pong copies of W key planes and a payload plane,
+//      must fit the device budget; a count pass (the work list of Section V)
+//      gives each subset's exact size when the split has more than one subset
+//      or a cutoff drops terms;
+//   3. per subset: generation -> LSD onesweep radix sort -> single pass;
+//   4. sums the subsets in index order.
+// The serving form queues requests from any context into one scheduler whose
+// worker threads each own a stream and a workspace; a request starts when a
+// worker is free and its projected record bytes fit the remaining budget.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pt2_internal.h"
+#include "../../include/pt2.h"
+
+#define PT2_API extern "C" __attribute__((visibility("default")))
+
+using namespace pt2;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(PT2_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t splitmix_next(uint64_t &st)
+{
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// device memory through the optional hook
+
+struct Alloc {
+    void *(*fa)(size_t, void *) = nullptr;
+    void (*ff)(void *, size_t, void *) = nullptr;
+    void *user = nullptr;
+    int device = 0;
+};
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
+{
+    b.p = nullptr;
+    b.bytes = 0;
+    if (bytes == 0)
+        return PT2_OK;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (A.fa) {
+        p = A.fa(bytes, A.user);
+        if (!p)
+            return fail(PT2_E_NOMEM, "allocator hook failed for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(PT2_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return PT2_OK;
+}
+
+void buf_free(const Alloc &A, Buf &b)
+{
+    if (b.p) {
+        if (A.ff)
+            A.ff(b.p, b.bytes, A.user);
+        else
+            (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+int buf_ensure(const Alloc &A, Buf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p)
+        return PT2_OK;
+    buf_free(A, b);
+    return buf_alloc(A, b, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// per-stream workspace
+
+constexpr int MAX_DIG = 32;
+constexpr int MAX_LOG2P = 12;  // the count pass keeps one LDS counter per subset
+constexpr int MAX_PASS_CTR = 64;
+
+struct Small {  // one device block for small control data
+    Flags flags;
+    uint32_t tile_ctr[MAX_PASS_CTR];
+    uint64_t hist[MAX_DIG * 256];
+    uint64_t bucket[MAX_DIG * 256];
+    Partial partials[RED_GRID];
+    Partial result;
+    unsigned long long n_out;
+};
+
+struct Workspace {
+    Alloc A;
+    Buf dets, coef;          // device copies of host inputs
+    Buf refA, refB;          // reference planes (W keys + FP64 coefficient)
+    int64_t ref_cap = 0;
+    Buf recA, recB;          // record planes
+    int64_t rec_cap = 0;
+    int rec_W = 0, rec_pb = 0;
+    Buf status;              // look-back status words
+    int64_t status_tiles = 0;
+    uint32_t epoch = 0;
+    Buf small;
+    Buf cnt, off, tot, parts_dev;
+    Small *host_small = nullptr;  // pinned mirror
+    std::vector<hipEvent_t> evpool;
+    size_t ev_used = 0;
+
+    ~Workspace() { release(); }
+
+    void release()
+    {
+        buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB);
+        buf_free(A, recA), buf_free(A, recB), buf_free(A, status), buf_free(A, small);
+        buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
+        ref_cap = rec_cap = status_tiles = 0;
+        if (host_small) {
+            (void)hipHostFree(host_small);
+            host_small = nullptr;
+        }
+        for (auto e : evpool)
+            (void)hipEventDestroy(e);
+        evpool.clear();
+    }
+
+    size_t record_bytes() const { return recA.bytes + recB.bytes + status.bytes; }
+
+    Small *dsmall() { return (Small *)small.p; }
+
+    hipEvent_t event()
+    {
+        if (ev_used == evpool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess)
+                return nullptr;
+            evpool.push_back(e);
+        }
+        return evpool[ev_used++];
+    }
+};
+
+Planes planes_of(const Buf &b, int W, int64_t cap, int pb)
+{
+    Planes p;
+    char *base = (char *)b.p;
+    for (int w = 0; w < MAXW; w++)
+        p.key[w] = w < W ? (uint64_t *)(base + (size_t)w * cap * 8) : nullptr;
+    p.pay = base + (size_t)W * cap * 8;
+    (void)pb;
+    return p;
+}
+
+size_t planes_bytes(int W, int64_t cap, int pb) { return (size_t)cap * (8 * (size_t)W + pb); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+
+struct pt2_ctx {
+    pt2_options opt;
+    int norb, na, nb, W;
+    Alloc A;
+    Buf h, V, h32, V32, T, R;
+    DevSys sys;
+    ExcLayout L;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    std::mutex mu;  // serialises pt2_evaluate* on this context
+    Workspace ws;
+    int inflight = 0;  // serving requests not yet polled out (guarded by the scheduler lock)
+};
+
+namespace {
+
+struct Timing {
+    bool on = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int kind;  // 0 gen, 1 sort pass, 2 reduce, 3 hist/other
+    };
+    std::vector<Ev> evs;
+};
+
+int timed_begin(Workspace &ws, Timing &t, hipStream_t st, hipEvent_t &a)
+{
+    a = nullptr;
+    if (!t.on)
+        return PT2_OK;
+    a = ws.event();
+    if (!a)
+        return fail(PT2_E_DEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(a, st));
+    return PT2_OK;
+}
+
+int timed_end(Workspace &ws, Timing &t, hipStream_t st, hipEvent_t a, int kind)
+{
+    if (!t.on)
+        return PT2_OK;
+    hipEvent_t b = ws.event();
+    if (!b)
+        return fail(PT2_E_DEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(b, st));
+    t.evs.push_back({a, b, kind});
+    return PT2_OK;
+}
+
+int ensure_small(Workspace &ws)
+{
+    if (!ws.small.p) {
+        int rc = buf_alloc(ws.A, ws.small, sizeof(Small));
+        if (rc)
+            return rc;
+        HIPCHK(hipMemset(ws.small.p, 0, sizeof(Small)));
+    }
+    if (!ws.host_small)
+        HIPCHK(hipHostMalloc((void **)&ws.host_small, sizeof(Small), hipHostMallocDefault));
+    return PT2_OK;
+}
+
+int ensure_status(Workspace &ws, int64_t n, hipStream_t st)
+{
+    int64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if (tiles < 1)
+        tiles = 1;
+    if (ws.status_tiles < tiles) {
+        buf_free(ws.A, ws.status);
+        int rc = buf_alloc(ws.A, ws.status, (size_t)tiles * 256 * 8);
+        if (rc)
+            return rc;
+        ws.status_tiles = tiles;
+        HIPCHK(launch_zero_u64((uint64_t *)ws.status.p, tiles * 256, st));
+        ws.epoch = 0;
+    }
+    return PT2_OK;
+}
+
+uint32_t next_epoch(Workspace &ws, hipStream_t st)
+{
+    ws.epoch++;
+    if (ws.epoch >= 0xFFFFu) {
+        (void)launch_zero_u64((uint64_t *)ws.status.p, ws.status_tiles * 256, st);
+        ws.epoch = 1;
+    }
+    return ws.epoch;
+}
+
+// Stable LSD sort of n records held in *src (ping-pong with *dst) on key bits
+// [0, nbits).  On return *src holds the sorted records.
+int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n, int nbits, hipStream_t st,
+               Timing &tm, uint32_t *passes_out, double *bytes_out)
+{
+    if (n <= 1)
+        return PT2_OK;
+    const int ndig = (nbits + 7) / 8;
+    if (ndig > MAX_DIG)
+        return fail(PT2_E_INVALID, "key too long");
+    int rc = ensure_status(ws, n, st);
+    if (rc)
+        return rc;
+    Small *ds = ws.dsmall();
+    hipEvent_t a;
+    if ((rc = timed_begin(ws, tm, st, a)))
+        return rc;
+    HIPCHK(launch_zero_u64(ds->hist, ndig * 256, st));
+    HIPCHK(launch_zero_u32(ds->tile_ctr, MAX_PASS_CTR, st));
+    HIPCHK(launch_hist(W, src, n, ndig, ds->hist, st));
+    HIPCHK(launch_hist_scan(ds->hist, ndig, ds->bucket, st));
+    HIPCHK(hipMemcpyAsync(ws.host_small->hist, ds->hist, sizeof(uint64_t) * ndig * 256, hipMemcpyDeviceToHost, st));
+    if ((rc = timed_end(ws, tm, st, a, 3)))
+        return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    for (int d = 0; d < ndig; d++) {
+        const uint64_t *h = ws.host_small->hist + d * 256;
+        bool trivial = false;
+        for (int v = 0; v < 256; v++)
+            if (h[v] == (uint64_t)n)
+                trivial = true;
+        if (trivial)
+            continue;
+        const uint32_t ep = next_epoch(ws, st);
+        if ((rc = timed_begin(ws, tm, st, a)))
+            return rc;
+        HIPCHK(launch_onesweep(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint64_t *)ws.status.p,
+                               ds->tile_ctr + (d % MAX_PASS_CTR), ep, &ds->flags, st));
+        if ((rc = timed_end(ws, tm, st, a, 1)))
+            return rc;
+        std::swap(src, dst);
+        if (passes_out)
+            (*passes_out)++;
+        if (bytes_out)
+            *bytes_out += 2.0 * (double)n * (8.0 * W + pb);
+    }
+    return PT2_OK;
+}
+
+// Upload (if host), check and sort the reference list.  On success refs holds
+// the sorted reference planes (keys + FP64 coefficients).
+int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *coeffs, int64_t n, bool host,
+                 hipStream_t st, Timing &tm, Planes &refs)
+{
+    const int W = c->W;
+    int rc;
+    if ((rc = ensure_small(ws)))
+        return rc;
+    if (host) {
+        if ((rc = buf_ensure(ws.A, ws.dets, (size_t)n * W * 8)) || (rc = buf_ensure(ws.A, ws.coef, (size_t)n * 8)))
+            return rc;
+        HIPCHK(hipMemcpyAsync(ws.dets.p, dets, (size_t)n * W * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(ws.coef.p, coeffs, (size_t)n * 8, hipMemcpyHostToDevice, st));
+        dets = (const uint64_t *)ws.dets.p;
+        coeffs = (const double *)ws.coef.p;
+    }
+    if (ws.ref_cap < n) {
+        buf_free(ws.A, ws.refA), buf_free(ws.A, ws.refB);
+        if ((rc = buf_alloc(ws.A, ws.refA, planes_bytes(W, n, 8))) ||
+            (rc = buf_alloc(ws.A, ws.refB, planes_bytes(W, n, 8))))
+            return rc;
+        ws.ref_cap = n;
+    }
+    Small *ds = ws.dsmall();
+    HIPCHK(launch_zero_u32(&ds->flags.err, 2, st));
+    Planes ra = planes_of(ws.refA, W, ws.ref_cap, 8), rb = planes_of(ws.refB, W, ws.ref_cap, 8);
+    HIPCHK(launch_refs_split(W, c->norb, c->na, c->nb, dets, coeffs, n, ra, &ds->flags, st));
+    Timing none;
+    if ((rc = radix_sort(ws, W, 8, ra, rb, n, 2 * c->norb, st, none, nullptr, nullptr)))
+        return rc;
+    HIPCHK(launch_dup_check(W, ra, n, &ds->flags, st));
+    HIPCHK(hipMemcpyAsync(&ws.host_small->flags, &ds->flags, sizeof(Flags), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t err = ws.host_small->flags.err;
+    if (err & ERR_POPCOUNT)
+        return fail(PT2_E_INVALID, "a reference determinant does not have %d alpha and %d beta electrons", c->na,
+                    c->nb);
+    if (err & ERR_STRAY_BITS)
+        return fail(PT2_E_INVALID, "a reference determinant has bits at or above 2*norb");
+    if (err & ERR_DUPLICATE)
+        return fail(PT2_E_INVALID, "duplicate reference determinants");
+    if (err & ERR_LOOKBACK)
+        return fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+    refs = ra;
+    (void)tm;
+    return PT2_OK;
+}
+
+int ensure_records(Workspace &ws, int W, int pb, int64_t cap)
+{
+    if (ws.rec_cap >= cap && ws.rec_W == W && ws.rec_pb == pb)
+        return PT2_OK;
+    buf_free(ws.A, ws.recA), buf_free(ws.A, ws.recB);
+    ws.rec_cap = 0;
+    int rc;
+    if ((rc = buf_alloc(ws.A, ws.recA, planes_bytes(W, cap, pb))) ||
+        (rc = buf_alloc(ws.A, ws.recB, planes_bytes(W, cap, pb)))) {
+        buf_free(ws.A, ws.recA), buf_free(ws.A, ws.recB);
+        return rc;
+    }
+    ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb;
+    return PT2_OK;
+}
+
+// projected device bytes for one subset of n records
+double subset_bytes(int W, int pb, double n) { return n * (2.0 * (8.0 * W + pb) + 0.5) + 4096.0 * 16; }
+
+struct Plan {
+    int log2p = 0;
+    bool compact = false;
+    int64_t chunk = 0, nchunks = 0;
+    std::vector<uint32_t> parts;
+    std::vector<uint64_t> sizes;  // records per listed subset
+    std::vector<uint64_t> structural;  // structural candidates per listed subset
+};
+
+struct Job {
+    const uint64_t *dets;
+    const double *coeffs;
+    int64_t n;
+    bool host;
+    double e0;
+    int forced_log2p;              // -1 planner
+    const uint32_t *parts = nullptr;
+    int nparts = 0;
+    double *e_parts = nullptr;
+    // inspection
+    int dump = 0;                  // 1 records (generation order), 2 records sorted, 3 numerators
+    uint64_t *keys_out = nullptr;
+    double *vals_out = nullptr;
+    uint8_t *inref_out = nullptr;
+    int64_t cap = 0;
+    int64_t *n_out = nullptr;
+};
+
+int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan &P, double cutoff, hipStream_t st,
+               std::vector<uint64_t> &tot_out)
+{
+    int rc;
+    const int Pn = 1 << P.log2p;
+    const int fp32 = c->opt.precision == PT2_FP32_PAYLOAD;
+    if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * Pn * 4)))
+        return rc;
+    if ((rc = buf_ensure(ws.A, ws.off, (size_t)P.nchunks * P.parts.size() * 8)) ||
+        (rc = buf_ensure(ws.A, ws.tot, P.parts.size() * 8)) ||
+        (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_count(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, nref, P.chunk, P.log2p, cutoff,
+                        (uint32_t *)ws.cnt.p, P.nchunks, st));
+    HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
+                             (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
+    tot_out.assign(P.parts.size(), 0);
+    HIPCHK(hipMemcpyAsync(tot_out.data(), ws.tot.p, P.parts.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PT2_OK;
+}
+
+int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
+{
+    const int W = c->W;
+    const int pb = c->opt.precision == PT2_FP32_PAYLOAD ? 4 : 8;
+    const double total = (double)nref * (double)c->L.nper;
+    const double cap_bytes =
+        (double)(c->opt.max_partition_bytes && c->opt.max_partition_bytes < c->budget ? c->opt.max_partition_bytes
+                                                                                      : c->budget);
+    const double cutoff = c->opt.cutoff;
+    int k;
+    if (J.forced_log2p >= 0)
+        k = J.forced_log2p;
+    else if (c->opt.log2_partitions >= 0)
+        k = c->opt.log2_partitions;
+    else {
+        k = 0;
+        while (k < MAX_LOG2P && subset_bytes(W, pb, total / (double)(1 << k) * 1.02 + 4096.0) > cap_bytes)
+            k++;
+    }
+    for (int attempt = 0; attempt < 4; attempt++) {
+        if (k > MAX_LOG2P)
+            return fail(PT2_E_NOMEM, "no split of at most 2^%d subsets fits the device budget", MAX_LOG2P);
+        P.log2p = k;
+        P.compact = k > 0 || cutoff > 0.0;
+        P.parts.clear();
+        if (J.parts) {
+            for (int i = 0; i < J.nparts; i++) {
+                if (J.parts[i] >= (1u << k))
+                    return fail(PT2_E_INVALID, "subset index %u out of range", J.parts[i]);
+                P.parts.push_back(J.parts[i]);
+            }
+        } else {
+            for (uint32_t p = 0; p < (1u << k); p++)
+                P.parts.push_back(p);
+        }
+        if (!P.compact) {
+            P.chunk = gen_chunk(c->L, nref, (int64_t)1 << 23);
+            P.nchunks = gen_nchunks(c->L, nref, P.chunk);
+            P.sizes.assign(1, (uint64_t)nref * (uint64_t)c->L.nper);
+            P.structural = P.sizes;
+            return PT2_OK;
+        }
+        const int64_t max_chunks = std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 23, ((int64_t)1 << 27) >> k));
+        P.chunk = gen_chunk(c->L, nref, max_chunks);
+        P.nchunks = gen_nchunks(c->L, nref, P.chunk);
+        int rc;
+        std::vector<uint64_t> tot;
+        if (cutoff > 0.0) {
+            if ((rc = count_pass(c, ws, refs, nref, P, 0.0, st, tot)))
+                return rc;
+            P.structural = tot;
+        }
+        if ((rc = count_pass(c, ws, refs, nref, P, cutoff, st, tot)))
+            return rc;
+        P.sizes = tot;
+        if (cutoff <= 0.0)
+            P.structural = tot;
+        uint64_t mx = 0;
+        for (auto t : tot)
+            mx = std::max(mx, t);
+        if (subset_bytes(W, pb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
+            return PT2_OK;
+        k++;
+    }
+    return fail(PT2_E_NOMEM, "planner could not fit a subset into the device budget");
+}
+
+void fill_result(pt2_result *out, const Partial &p)
+{
+    out->e_pt2 = p.e_sum + p.e_comp;
+    out->n_unique = p.n_unique;
+    out->n_external = p.n_external;
+    out->n_in_ref_hit = p.n_hit;
+    out->min_abs_denom = p.min_abs_denom;
+    out->n_nonneg_denom = p.n_nonneg;
+    out->ref_cross = p.ref_cross;
+    out->key_xor = p.key_xor;
+    out->key_sum = p.key_sum;
+}
+
+int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result *out)
+{
+    const double t0 = now_ms();
+    const int W = c->W;
+    const int fp32 = c->opt.precision == PT2_FP32_PAYLOAD;
+    const int pb = fp32 ? 4 : 8;
+    int rc;
+    Timing tm;
+    tm.on = c->opt.timing != 0;
+    ws.ev_used = 0;
+    pt2_result res;
+    memset(&res, 0, sizeof res);
+    res.struct_size = sizeof(pt2_result);
+    res.min_abs_denom = __builtin_inf();
+    if (J.n == 0) {
+        if (J.e_parts)
+            for (int i = 0; i < J.nparts; i++)
+                J.e_parts[i] = 0.0;
+        if (J.n_out)
+            *J.n_out = 0;
+        res.ms_total = now_ms() - t0;
+        memcpy(out, &res, sizeof res);
+        return PT2_OK;
+    }
+    Planes refs;
+    if ((rc = prepare_refs(c, ws, J.dets, J.coeffs, J.n, J.host, st, tm, refs)))
+        return rc;
+    Plan P;
+    Job JJ = J;
+    if (J.dump)
+        JJ.forced_log2p = 0;
+    if ((rc = plan_job(c, ws, refs, J.n, JJ, st, P)))
+        return rc;
+    uint64_t mx = 0;
+    for (auto s : P.sizes)
+        mx = std::max(mx, s);
+    if ((rc = ensure_records(ws, W, pb, (int64_t)std::max<uint64_t>(mx, 1))))
+        return rc;
+    Small *ds = ws.dsmall();
+    std::vector<Partial> part_res(P.parts.size());
+    for (size_t q = 0; q < P.parts.size(); q++) {
+        const int64_t n = (int64_t)P.sizes[q];
+        res.n_contrib += P.structural[q];
+        res.n_after_cutoff += (uint64_t)n;
+        Planes A = planes_of(ws.recA, W, ws.rec_cap, pb), B = planes_of(ws.recB, W, ws.rec_cap, pb);
+        hipEvent_t a;
+        if ((rc = timed_begin(ws, tm, st, a)))
+            return rc;
+        if (!P.compact)
+            HIPCHK(launch_gen_direct(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, J.n, P.chunk, A, st));
+        else
+            HIPCHK(launch_gen_compact(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, J.n, P.chunk,
+                                      P.log2p, P.parts[q], c->opt.cutoff,
+                                      (const uint64_t *)ws.off.p + (size_t)q * P.nchunks, P.nchunks,
+                                      (uint64_t)ws.rec_cap, A, &ds->flags, st));
+        if ((rc = timed_end(ws, tm, st, a, 0)))
+            return rc;
+        res.bytes_gen += (double)n * (8.0 * W + pb);
+        if (J.dump == 1)
+            break;  // generation order: the records are in recA
+        if ((rc = radix_sort(ws, W, pb, A, B, n, 2 * c->norb, st, tm, &res.n_sort_passes, &res.bytes_sort)))
+            return rc;
+        if (J.dump == 2 || J.dump == 3) {
+            // hand the sorted planes to the inspection copy below (it reads recA)
+            if (ws.recA.p != (void *)A.key[0])
+                std::swap(ws.recA, ws.recB);
+            break;
+        }
+        if ((rc = timed_begin(ws, tm, st, a)))
+            return rc;
+        HIPCHK(launch_reduce(c->sys, fp32, A, n, refs, J.n, J.e0, ds->partials, &ds->flags, st));
+        HIPCHK(launch_final(ds->partials, &ds->result, st));
+        if ((rc = timed_end(ws, tm, st, a, 2)))
+            return rc;
+        res.bytes_reduce += (double)n * (8.0 * W + pb);
+        HIPCHK(hipMemcpyAsync(&part_res[q], &ds->result, sizeof(Partial), hipMemcpyDeviceToHost, st));
+    }
+    if (J.dump) {
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t n = (int64_t)P.sizes[0];
+        if (J.n_out)
+            *J.n_out = n;
+        if (J.dump == 1 || J.dump == 2) {
+            const int64_t m = std::min<int64_t>(n, J.cap);
+            Buf kb, vb;
+            if ((rc = buf_alloc(ws.A, kb, (size_t)std::max<int64_t>(m, 1) * W * 8)) ||
+                (rc = buf_alloc(ws.A, vb, (size_t)std::max<int64_t>(m, 1) * 8)))
+                return rc;
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb);
+            HIPCHK(launch_planes_to_aos(W, pb, S, m, (uint64_t *)kb.p, (double *)vb.p, st));
+            if (m > 0) {
+                HIPCHK(hipMemcpyAsync(J.keys_out, kb.p, (size_t)m * W * 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(J.vals_out, vb.p, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            buf_free(ws.A, kb), buf_free(ws.A, vb);
+        } else {
+            Buf kb, vb, ib;
+            const int64_t m = std::max<int64_t>(J.cap, 1);
+            if ((rc = buf_alloc(ws.A, kb, (size_t)m * W * 8)) || (rc = buf_alloc(ws.A, vb, (size_t)m * 8)) ||
+                (rc = buf_alloc(ws.A, ib, (size_t)m)))
+                return rc;
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb);
+            HIPCHK(launch_zero_u64((uint64_t *)&ds->n_out, 1, st));
+            HIPCHK(launch_numerators(W, fp32, S, n, refs, J.n, (uint64_t *)kb.p, (double *)vb.p, (uint8_t *)ib.p,
+                                     &ds->n_out, J.cap, st));
+            unsigned long long cnt = 0;
+            HIPCHK(hipMemcpyAsync(&cnt, &ds->n_out, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int64_t mm = std::min<int64_t>((int64_t)cnt, J.cap);
+            std::vector<uint64_t> keys((size_t)mm * W);
+            std::vector<double> vals(mm);
+            std::vector<uint8_t> inr(mm);
+            if (mm > 0) {
+                HIPCHK(hipMemcpy(keys.data(), kb.p, (size_t)mm * W * 8, hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(vals.data(), vb.p, (size_t)mm * 8, hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(inr.data(), ib.p, (size_t)mm, hipMemcpyDeviceToHost));
+            }
+            buf_free(ws.A, kb), buf_free(ws.A, vb), buf_free(ws.A, ib);
+            // ascending key order (slots were taken in arbitrary order)
+            std::vector<int64_t> idx(mm);
+            for (int64_t i = 0; i < mm; i++)
+                idx[i] = i;
+            std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+                for (int w = W - 1; w >= 0; w--) {
+                    uint64_t a = keys[x * W + w], b = keys[y * W + w];
+                    if (a != b)
+                        return a < b;
+                }
+                return false;
+            });
+            for (int64_t i = 0; i < mm; i++) {
+                memcpy(J.keys_out + i * W, &keys[idx[i] * W], (size_t)W * 8);
+                J.vals_out[i] = vals[idx[i]];
+                J.inref_out[i] = inr[idx[i]];
+            }
+            *J.n_out = (int64_t)cnt;
+        }
+        return PT2_OK;
+    }
+    HIPCHK(hipMemcpyAsync(&ws.host_small->flags, &ds->flags, sizeof(Flags), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t err = ws.host_small->flags.err;
+    if (err & ERR_LOOKBACK)
+        return fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+    if (err & ERR_OVERFLOW)
+        return fail(PT2_E_DEVICE, "compacted generation exceeded its planned range");
+    // combine subsets in index order
+    double sum = 0.0, comp = 0.0;
+    for (size_t q = 0; q < P.parts.size(); q++) {
+        const Partial &p = part_res[q];
+        const double e = p.e_sum + p.e_comp;
+        if (J.e_parts)
+            J.e_parts[q] = e;
+        double t = sum + e;
+        if (fabs(sum) >= fabs(e))
+            comp += (sum - t) + e;
+        else
+            comp += (e - t) + sum;
+        sum = t;
+        res.n_unique += p.n_unique;
+        res.n_external += p.n_external;
+        res.n_in_ref_hit += p.n_hit;
+        res.n_nonneg_denom += p.n_nonneg;
+        res.ref_cross += p.ref_cross;
+        res.key_xor ^= p.key_xor;
+        res.key_sum += p.key_sum;
+        res.min_abs_denom = std::min(res.min_abs_denom, p.min_abs_denom);
+    }
+    res.e_pt2 = sum + comp;
+    res.n_partitions = (uint32_t)P.parts.size();
+    for (auto &e : tm.evs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+        if (e.kind == 0)
+            res.ms_gen += ms;
+        else if (e.kind == 1) {
+            res.ms_sort += ms;
+            res.ms_sort_pass_max = std::max(res.ms_sort_pass_max, (double)ms);
+        } else if (e.kind == 2)
+            res.ms_reduce += ms;
+        else
+            res.ms_hist += ms;
+    }
+    res.ms_total = now_ms() - t0;
+    memcpy(out, &res, sizeof res);
+    if (err & ERR_SINGULAR)
+        return fail(PT2_E_SINGULAR, "an external determinant has E0 - H_aa == 0");
+    return PT2_OK;
+}
+
+bool result_ok(const pt2_result *out) { return out && out->struct_size == sizeof(pt2_result); }
+
+// ---------------------------------------------------------------------------
+// serving scheduler (process-wide)
+
+struct Request {
+    int64_t id;
+    pt2_ctx *ctx;
+    std::vector<uint64_t> dets;
+    std::vector<double> c;
+    int64_t n;
+    double e0;
+    double projected;
+    bool done = false;
+    int rc = PT2_OK;
+    std::string err;
+    pt2_result res;
+};
+
+struct Worker {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Workspace> ws;
+};
+
+class Scheduler {
+  public:
+    static Scheduler &get()
+    {
+        static Scheduler *s = new Scheduler();  // never destroyed; workers stopped at exit
+        return *s;
+    }
+
+    int submit(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0, pt2_req *out)
+    {
+        auto r = std::make_unique<Request>();
+        r->ctx = c;
+        r->dets.assign(dets, dets + (size_t)n * c->W);
+        r->c.assign(coeffs, coeffs + n);
+        r->n = n;
+        r->e0 = e0;
+        const int pb = c->opt.precision == PT2_FP32_PAYLOAD ? 4 : 8;
+        const double total = (double)n * (double)c->L.nper;
+        double cap = (double)(c->opt.max_partition_bytes ? std::min<uint64_t>(c->opt.max_partition_bytes, c->budget)
+                                                         : c->budget);
+        double per = subset_bytes(c->W, pb, total * 1.02 + 4096.0);
+        int k = 0;
+        while (k < MAX_LOG2P && per > cap) {
+            k++;
+            per = subset_bytes(c->W, pb, total / (double)(1 << k) * 1.02 + 4096.0);
+        }
+        r->projected = per;
+        std::unique_lock<std::mutex> lk(mu_);
+        start_workers_locked(c);
+        r->id = next_id_++;
+        *out = r->id;
+        c->inflight++;
+        queue_.push_back(r.get());
+        all_[r->id] = std::move(r);
+        cv_.notify_all();
+        return PT2_OK;
+    }
+
+    int poll(pt2_ctx *c, pt2_req id, pt2_result *out, bool wait)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = all_.find(id);
+        if (it == all_.end() || it->second->ctx != c)
+            return fail(PT2_E_UNKNOWN_REQ, "unknown request id %lld", (long long)id);
+        if (wait)
+            done_cv_.wait(lk, [&] { return it->second->done; });
+        if (!it->second->done)
+            return PT2_NOT_READY;
+        Request *r = it->second.get();
+        int rc = r->rc;
+        memcpy(out, &r->res, sizeof(pt2_result));
+        if (rc != PT2_OK && rc != PT2_E_SINGULAR)
+            g_err = r->err;
+        c->inflight--;
+        all_.erase(it);
+        return rc;
+    }
+
+    int inflight(pt2_ctx *c)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return c->inflight;
+    }
+
+    void stop()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stopping_ = true;
+            cv_.notify_all();
+        }
+        for (auto &w : workers_)
+            if (w->th.joinable())
+                w->th.join();
+        for (auto &w : workers_) {
+            w->ws.reset();
+            if (w->stream)
+                (void)hipStreamDestroy(w->stream);
+        }
+        workers_.clear();
+    }
+
+  private:
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Request *> queue_;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> all_;
+    std::vector<std::unique_ptr<Worker>> workers_;
+    int64_t next_id_ = 1;
+    double in_use_ = 0.0;
+    double budget_ = 0.0;
+    int running_ = 0;
+    bool stopping_ = false;
+    bool atexit_ = false;
+
+    void start_workers_locked(pt2_ctx *c)
+    {
+        if (budget_ == 0.0 || (double)c->budget > budget_)
+            budget_ = (double)c->budget;
+        const int want = std::max(1, c->opt.n_streams);
+        if (!atexit_) {
+            atexit_ = true;
+            atexit([] { Scheduler::get().stop(); });
+        }
+        while ((int)workers_.size() < want) {
+            auto w = std::make_unique<Worker>();
+            w->ws = std::make_unique<Workspace>();
+            w->ws->A = c->A;
+            Worker *wp = w.get();
+            const int dev = c->opt.device;
+            w->th = std::thread([this, wp, dev] { loop(wp, dev); });
+            workers_.push_back(std::move(w));
+        }
+    }
+
+    // first queued request that fits; a request bypassed too often blocks the rest
+    Request *pick_locked()
+    {
+        for (size_t i = 0; i < queue_.size(); i++) {
+            Request *r = queue_[i];
+            if (running_ == 0 || in_use_ + r->projected <= budget_) {
+                queue_.erase(queue_.begin() + (long)i);
+                return r;
+            }
+            if (i == 0 && bypass_ >= 16)
+                return nullptr;
+        }
+        return nullptr;
+    }
+    int bypass_ = 0;
+
+    void loop(Worker *w, int dev)
+    {
+        (void)hipSetDevice(dev);
+        if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess)
+            w->stream = nullptr;
+        std::unique_lock<std::mutex> lk(mu_);
+        while (true) {
+            Request *r = nullptr;
+            cv_.wait(lk, [&] { return stopping_ || (!queue_.empty() && (r = pick_locked()) != nullptr); });
+            if (stopping_ && !r)
+                return;
+            if (!queue_.empty() && r != queue_.front())
+                bypass_++;
+            else
+                bypass_ = 0;
+            in_use_ += r->projected;
+            running_++;
+            lk.unlock();
+            pt2_ctx *c = r->ctx;
+            w->ws->A = c->A;
+            Job J{};
+            J.dets = r->dets.data();
+            J.coeffs = r->c.data();
+            J.n = r->n;
+            J.host = true;
+            J.e0 = r->e0;
+            J.forced_log2p = -1;
+            pt2_result res;
+            memset(&res, 0, sizeof res);
+            res.struct_size = sizeof res;
+            int rc = w->stream ? run_job(c, *w->ws, w->stream, J, &res)
+                               : fail(PT2_E_DEVICE, "worker stream creation failed");
+            // release record buffers so the budget accounting stays truthful
+            buf_free(w->ws->A, w->ws->recA), buf_free(w->ws->A, w->ws->recB);
+            w->ws->rec_cap = 0;
+            lk.lock();
+            r->rc = rc;
+            r->err = rc != PT2_OK ? g_err : std::string();
+            r->res = res;
+            r->done = true;
+            in_use_ -= r->projected;
+            running_--;
+            done_cv_.notify_all();
+            cv_.notify_all();
+        }
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+
+PT2_API void pt2_default_options(pt2_options *o)
+{
+    if (!o)
+        return;
+    memset(o, 0, sizeof *o);
+    o->struct_size = sizeof *o;
+    o->precision = PT2_FP64;
+    o->cutoff = 0.0;
+    o->log2_partitions = -1;
+    o->device = 0;
+    o->n_streams = 4;
+}
+
+PT2_API int pt2_key_words(int norb) { return (2 * norb + 63) / 64; }
+
+PT2_API const char *pt2_last_error(void) { return g_err.c_str(); }
+
+PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha, int nbeta, const pt2_options *opt,
+                       pt2_ctx **out)
+{
+    g_err.clear();
+    if (!out)
+        return fail(PT2_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!h || !eri)
+        return fail(PT2_E_INVALID, "h or eri is NULL");
+    if (norb < 1 || norb > MAXORB)
+        return fail(PT2_E_INVALID, "norb must be in [1, %d]", MAXORB);
+    if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb)
+        return fail(PT2_E_INVALID, "electron counts out of range");
+    pt2_options o;
+    pt2_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(pt2_options))
+            return fail(PT2_E_INVALID, "pt2_options.struct_size mismatch");
+        o = *opt;
+    }
+    if (o.precision != PT2_FP64 && o.precision != PT2_FP32_PAYLOAD)
+        return fail(PT2_E_INVALID, "unknown precision %d", o.precision);
+    if (!(o.cutoff >= 0.0))
+        return fail(PT2_E_INVALID, "cutoff must be >= 0");
+    if (o.log2_partitions > MAX_LOG2P)
+        return fail(PT2_E_INVALID, "log2_partitions must be <= %d", MAX_LOG2P);
+    if ((o.alloc == nullptr) != (o.free == nullptr))
+        return fail(PT2_E_INVALID, "alloc and free hooks must be given together");
+    const size_t n = (size_t)norb;
+    for (size_t p = 0; p < n; p++)
+        for (size_t q = 0; q < n; q++) {
+            if (!std::isfinite(h[p * n + q]))
+                return fail(PT2_E_INVALID, "h has a non-finite entry");
+            if (std::fabs(h[p * n + q] - h[q * n + p]) > 1e-12)
+                return fail(PT2_E_INVALID, "h is not symmetric");
+        }
+    auto E = [&](size_t p, size_t q, size_t r, size_t s) { return eri[((p * n + q) * n + r) * n + s]; };
+    for (size_t p = 0; p < n; p++)
+        for (size_t q = 0; q < n; q++)
+            for (size_t r = 0; r < n; r++)
+                for (size_t s = 0; s < n; s++) {
+                    const double v = E(p, q, r, s);
+                    if (!std::isfinite(v))
+                        return fail(PT2_E_INVALID, "eri has a non-finite entry");
+                    if (std::fabs(v - E(q, p, r, s)) > 1e-12 || std::fabs(v - E(p, q, s, r)) > 1e-12 ||
+                        std::fabs(v - E(r, s, p, q)) > 1e-12)
+                        return fail(PT2_E_INVALID, "eri is not 8-fold symmetric at (%zu %zu|%zu %zu)", p, q, r, s);
+                }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(PT2_E_DEVICE, "no HIP device available");
+    }
+    if (o.device < 0 || o.device >= ndev)
+        return fail(PT2_E_INVALID, "device %d out of range", o.device);
+    HIPCHK(hipSetDevice(o.device));
+
+    auto c = std::make_unique<pt2_ctx>();
+    c->opt = o;
+    c->norb = norb, c->na = nalpha, c->nb = nbeta, c->W = pt2_key_words(norb);
+    c->A.fa = o.alloc, c->A.ff = o.free, c->A.user = o.alloc_user, c->A.device = o.device;
+    c->ws.A = c->A;
+    c->L = make_layout(norb, nalpha, nbeta);
+    if (c->L.nper >= ((int64_t)1 << 26))
+        return fail(PT2_E_INVALID, "excitation space per determinant too large");
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    c->budget = o.device_budget_bytes ? o.device_budget_bytes : (uint64_t)(0.8 * (double)freeb);
+
+    // resident Hamiltonian
+    const size_t n2 = n * n, n4 = n2 * n2, nso = 2 * n;
+    std::vector<double> T(nso * nso, 0.0);
+    for (size_t b1 = 0; b1 < nso; b1++) {
+        const size_t p = b1 < n ? b1 : b1 - n;
+        T[b1 * nso + b1] = h[p * n + p];
+        for (size_t b2 = b1 + 1; b2 < nso; b2++) {
+            const size_t q = b2 < n ? b2 : b2 - n;
+            const bool same = (b1 < n) == (b2 < n);
+            T[b1 * nso + b2] = E(p, p, q, q) - (same ? E(p, q, q, p) : 0.0);
+        }
+    }
+    std::vector<uint64_t> R(nso);
+    uint64_t st = 0x5054325F5A4F4252ull;
+    for (size_t b = 0; b < nso; b++)
+        R[b] = splitmix_next(st);
+    int rc;
+    if ((rc = buf_alloc(c->A, c->h, n2 * 8)) || (rc = buf_alloc(c->A, c->V, n4 * 8)) ||
+        (rc = buf_alloc(c->A, c->T, nso * nso * 8)) || (rc = buf_alloc(c->A, c->R, nso * 8)))
+        return rc;
+    HIPCHK(hipMemcpy(c->h.p, h, n2 * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->V.p, eri, n4 * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->T.p, T.data(), nso * nso * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->R.p, R.data(), nso * 8, hipMemcpyHostToDevice));
+    if (o.precision == PT2_FP32_PAYLOAD) {
+        std::vector<float> h32(n2), V32(n4);
+        for (size_t i = 0; i < n2; i++)
+            h32[i] = (float)h[i];
+        for (size_t i = 0; i < n4; i++)
+            V32[i] = (float)eri[i];
+        if ((rc = buf_alloc(c->A, c->h32, n2 * 4)) || (rc = buf_alloc(c->A, c->V32, n4 * 4)))
+            return rc;
+        HIPCHK(hipMemcpy(c->h32.p, h32.data(), n2 * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->V32.p, V32.data(), n4 * 4, hipMemcpyHostToDevice));
+    }
+    c->sys.norb = norb, c->sys.na = nalpha, c->sys.nb = nbeta, c->sys.W = c->W;
+    c->sys.h = (const double *)c->h.p;
+    c->sys.V = (const double *)c->V.p;
+    c->sys.h32 = (const float *)c->h32.p;
+    c->sys.V32 = (const float *)c->V32.p;
+    c->sys.T = (const double *)c->T.p;
+    c->sys.R = (const uint64_t *)c->R.p;
+    *out = c.release();
+    return PT2_OK;
+}
+
+namespace {
+int check_eval_args(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, pt2_result *out)
+{
+    g_err.clear();
+    if (!c)
+        return fail(PT2_E_INVALID, "context is NULL");
+    if (!result_ok(out))
+        return fail(PT2_E_INVALID, "pt2_result is NULL or struct_size mismatch");
+    if (n < 0)
+        return fail(PT2_E_INVALID, "ndets < 0");
+    if (n > 0 && (!dets || !coeffs))
+        return fail(PT2_E_INVALID, "dets or coeffs is NULL");
+    if (n >= ((int64_t)1 << 31))
+        return fail(PT2_E_INVALID, "too many reference determinants");
+    return PT2_OK;
+}
+
+int eval_common(pt2_ctx *c, Job &J, pt2_result *out)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->opt.device) != hipSuccess)
+        return fail(PT2_E_DEVICE, "hipSetDevice failed");
+    return run_job(c, c->ws, c->stream, J, out);
+}
+}  // namespace
+
+PT2_API int pt2_evaluate(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0,
+                         pt2_result *out)
+{
+    int rc = check_eval_args(c, dets, coeffs, n, out);
+    if (rc)
+        return rc;
+    Job J{};
+    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = e0, J.forced_log2p = -1;
+    return eval_common(c, J, out);
+}
+
+PT2_API int pt2_evaluate_device(pt2_ctx *c, const uint64_t *d_dets, const double *d_coeffs, int64_t n, double e0,
+                                pt2_result *out)
+{
+    int rc = check_eval_args(c, d_dets, d_coeffs, n, out);
+    if (rc)
+        return rc;
+    Job J{};
+    J.dets = d_dets, J.coeffs = d_coeffs, J.n = n, J.host = false, J.e0 = e0, J.forced_log2p = -1;
+    return eval_common(c, J, out);
+}
+
+PT2_API int pt2_evaluate_parts(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0,
+                               int log2p, const uint32_t *parts, int nparts, double *e_parts, pt2_result *out)
+{
+    int rc = check_eval_args(c, dets, coeffs, n, out);
+    if (rc)
+        return rc;
+    if (log2p < 0 || log2p > MAX_LOG2P)
+        return fail(PT2_E_INVALID, "log2p must be in [0, %d]", MAX_LOG2P);
+    if (nparts < 0 || (nparts > 0 && (!parts || !e_parts)))
+        return fail(PT2_E_INVALID, "parts / e_parts invalid");
+    for (int i = 0; i < nparts; i++)
+        if (parts[i] >= (1u << log2p))
+            return fail(PT2_E_INVALID, "subset index out of range");
+    Job J{};
+    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = e0, J.forced_log2p = log2p;
+    J.parts = parts, J.nparts = nparts, J.e_parts = e_parts;
+    if (nparts == 0) {
+        memset(out, 0, sizeof *out);
+        out->struct_size = sizeof *out;
+        return PT2_OK;
+    }
+    return eval_common(c, J, out);
+}
+
+PT2_API int pt2_dump_records(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, int sorted,
+                             uint64_t *keys_out, double *payload_out, int64_t cap, int64_t *n_out)
+{
+    pt2_result tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.struct_size = sizeof tmp;
+    int rc = check_eval_args(c, dets, coeffs, n, &tmp);
+    if (rc)
+        return rc;
+    if (!n_out || cap < 0 || (cap > 0 && (!keys_out || !payload_out)))
+        return fail(PT2_E_INVALID, "output buffers invalid");
+    Job J{};
+    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = 0.0, J.forced_log2p = 0;
+    J.dump = sorted ? 2 : 1, J.keys_out = keys_out, J.vals_out = payload_out, J.cap = cap, J.n_out = n_out;
+    return eval_common(c, J, &tmp);
+}
+
+PT2_API int pt2_dump_numerators(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, uint64_t *keys_out,
+                                double *num_out, uint8_t *in_ref_out, int64_t cap, int64_t *n_out)
+{
+    pt2_result tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.struct_size = sizeof tmp;
+    int rc = check_eval_args(c, dets, coeffs, n, &tmp);
+    if (rc)
+        return rc;
+    if (!n_out || cap < 0 || (cap > 0 && (!keys_out || !num_out || !in_ref_out)))
+        return fail(PT2_E_INVALID, "output buffers invalid");
+    Job J{};
+    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = 0.0, J.forced_log2p = 0;
+    J.dump = 3, J.keys_out = keys_out, J.vals_out = num_out, J.inref_out = in_ref_out, J.cap = cap, J.n_out = n_out;
+    return eval_common(c, J, &tmp);
+}
+
+PT2_API int pt2_submit(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0, pt2_req *out)
+{
+    pt2_result tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.struct_size = sizeof tmp;
+    int rc = check_eval_args(c, dets, coeffs, n, &tmp);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(PT2_E_INVALID, "request id pointer is NULL");
+    return Scheduler::get().submit(c, dets, coeffs, n, e0, out);
+}
+
+PT2_API int pt2_poll(pt2_ctx *c, pt2_req req, pt2_result *out)
+{
+    g_err.clear();
+    if (!c || !result_ok(out))
+        return fail(PT2_E_INVALID, "invalid arguments");
+    return Scheduler::get().poll(c, req, out, false);
+}
+
+PT2_API int pt2_wait(pt2_ctx *c, pt2_req req, pt2_result *out)
+{
+    g_err.clear();
+    if (!c || !result_ok(out))
+        return fail(PT2_E_INVALID, "invalid arguments");
+    return Scheduler::get().poll(c, req, out, true);
+}
+
+PT2_API int pt2_destroy(pt2_ctx *c)
+{
+    g_err.clear();
+    if (!c)
+        return PT2_OK;
+    if (Scheduler::get().inflight(c) > 0)
+        return fail(PT2_E_BUSY, "requests in flight");
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        (void)hipSetDevice(c->opt.device);
+        if (c->stream)
+            (void)hipStreamSynchronize(c->stream);
+        c->ws.release();
+        buf_free(c->A, c->h), buf_free(c->A, c->V), buf_free(c->A, c->h32), buf_free(c->A, c->V32);
+        buf_free(c->A, c->T), buf_free(c->A, c->R);
+        if (c->own_stream && c->stream)
+            (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+    return PT2_OK;
+}
+
+PT2_API int pt2_sort_records(int device, int W, int key_bits, uint64_t *keys, void *payload, int payload_bytes,
+                             int64_t n)
+{
+    g_err.clear();
+    if (W < 1 || W > MAXW || key_bits < 0 || key_bits > 64 * W || (payload_bytes != 4 && payload_bytes != 8) ||
+        n < 0 || (n > 0 && (!keys || !payload)))
+        return fail(PT2_E_INVALID, "invalid arguments");
+    if (n <= 1)
+        return PT2_OK;
+    HIPCHK(hipSetDevice(device));
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    Workspace ws;
+    int rc;
+    const size_t pbytes = planes_bytes(W, n, payload_bytes);
+    if ((rc = ensure_small(ws)) || (rc = buf_alloc(ws.A, ws.recA, pbytes)) || (rc = buf_alloc(ws.A, ws.recB, pbytes))) {
+        (void)hipStreamDestroy(st);
+        return rc;
+    }
+    std::vector<uint64_t> planes((size_t)n * W);
+    for (int64_t i = 0; i < n; i++)
+        for (int w = 0; w < W; w++)
+            planes[(size_t)w * n + i] = keys[i * W + w];
+    Planes A = planes_of(ws.recA, W, n, payload_bytes), B = planes_of(ws.recB, W, n, payload_bytes);
+    Timing none;
+    rc = PT2_OK;
+    if (hipMemcpy(ws.recA.p, planes.data(), (size_t)n * W * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(A.pay, payload, (size_t)n * payload_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(PT2_E_DEVICE, "upload failed");
+    if (!rc)
+        rc = radix_sort(ws, W, payload_bytes, A, B, n, key_bits, st, none, nullptr, nullptr);
+    if (!rc) {
+        Flags f;
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(&f, &ws.dsmall()->flags, sizeof f, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(PT2_E_DEVICE, "sort failed");
+        else if (f.err & ERR_LOOKBACK)
+            rc = fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+    }
+    if (!rc) {
+        for (int w = 0; w < W; w++)
+            if (hipMemcpy(planes.data() + (size_t)w * n, A.key[w], (size_t)n * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = fail(PT2_E_DEVICE, "download failed");
+        if (!rc && hipMemcpy(payload, A.pay, (size_t)n * payload_bytes, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(PT2_E_DEVICE, "download failed");
+        if (!rc)
+            for (int64_t i = 0; i < n; i++)
+                for (int w = 0; w < W; w++)
+                    keys[i * W + w] = planes[(size_t)w * n + i];
+    }
+    ws.release();
+    (void)hipStreamDestroy(st);
+    return rc;
+}

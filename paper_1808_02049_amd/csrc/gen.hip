@@ -1,0 +1,618 @@
+// Excitation generation and Slater-Condon numerator terms (Algorithm 1,
+// generation step: act with H on every reference determinant and store each
+// connected determinant's bitstring with H_ai * c_i), plus the count pass
+// that sizes every subset of the hash split (the work list of the
+// parallelisation subsection of Section V).
+//
+// One workgroup handles a contiguous chunk of one reference determinant's
+// excitation index space.  The index space of a determinant with n_s occupied
+// and v_s virtual orbitals per spin s is laid out as
+//   [alpha singles | beta singles | alpha-alpha doubles | beta-beta doubles |
+//    alpha-beta doubles]
+// and a term is decoded from its index arithmetically, so every term has a
+// fixed position and the output needs no atomics.  Per-determinant tables
+// (occupied/virtual lists, single-excitation phases, orbital pairs) live in
+// LDS; integrals are read from HBM through the caches (the (ra|..) slice used
+// by consecutive alpha-beta terms is contiguous).
+//
+// Matrix elements (real orbitals, chemists' notation), with ph(x->y) the
+// parity of occupied same-spin orbitals strictly between x and y:
+//   single r->a, spin s:  ph * [h_ra + sum_{j occ} (ra|jj) - sum_{j occ, spin s} (rj|ja)]
+//   same-spin r<s->a<b:   ph(r->a) ph'(s->b) [(ra|sb) - (rb|sa)], ph' taken on the
+//                         determinant after r->a
+//   alpha r->a, beta s->b: ph_alpha(r->a) ph_beta(s->b) (ra|sb)
+#include "pt2_internal.h"
+
+namespace pt2 {
+namespace {
+
+struct GenHead {
+    uint64_t key[MAXW];
+    uint64_t z;
+    double c;
+    uint64_t R[2 * MAXORB];
+    uint8_t occ[2][MAXORB];   // [spin][k]: spin 0 = alpha, 1 = beta
+    uint8_t vir[2][MAXORB];
+};
+
+struct GenLds {
+    GenHead *head;
+    int8_t *ph[2];      // [spin][occ_idx * v + vir_idx]
+    uint16_t *op[2];    // occupied pairs (i | j << 8), i < j, indices into occ
+    uint16_t *vp[2];    // virtual pairs, indices into vir
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, size_t *o_ph1, size_t *o_op0,
+                                             size_t *o_vp0, size_t *o_op1, size_t *o_vp1)
+{
+    size_t o = align16(sizeof(GenHead));
+    *o_ph0 = o;
+    o = align16(o + (size_t)L.na * L.va);
+    *o_ph1 = o;
+    o = align16(o + (size_t)L.nb * L.vb);
+    *o_op0 = o;
+    o = align16(o + 2 * (size_t)L.nopa);
+    *o_vp0 = o;
+    o = align16(o + 2 * (size_t)L.nvpa);
+    *o_op1 = o;
+    o = align16(o + 2 * (size_t)L.nopb);
+    *o_vp1 = o;
+    o = align16(o + 2 * (size_t)L.nvpb);
+    return o;
+}
+
+__device__ inline GenLds carve(char *base, const ExcLayout &L)
+{
+    size_t a, b, c, d, e, f;
+    lds_layout(L, &a, &b, &c, &d, &e, &f);
+    GenLds g;
+    g.head = (GenHead *)base;
+    g.ph[0] = (int8_t *)(base + a);
+    g.ph[1] = (int8_t *)(base + b);
+    g.op[0] = (uint16_t *)(base + c);
+    g.vp[0] = (uint16_t *)(base + d);
+    g.op[1] = (uint16_t *)(base + e);
+    g.vp[1] = (uint16_t *)(base + f);
+    return g;
+}
+
+__device__ inline int get_bit(const uint64_t *k, int b) { return (int)((k[b >> 6] >> (b & 63)) & 1ull); }
+
+// parity (as +1/-1) of set bits of the spin string strictly between orbitals x and y
+__device__ inline int between_sign(const uint64_t *key, int norb, int spin, int x, int y)
+{
+    int lo = x < y ? x : y, hi = x < y ? y : x;
+    int off = spin == 0 ? norb : 0;
+    int cnt = 0;
+    // bits (off+lo+1) .. (off+hi-1)
+    int b0 = off + lo + 1, b1 = off + hi;  // half-open
+    for (int w = b0 >> 6; w <= ((b1 - 1) >> 6) && b0 < b1; w++) {
+        int s = w * 64;
+        uint64_t m = ~0ull;
+        if (b0 > s)
+            m &= ~0ull << (b0 - s);
+        if (b1 < s + 64)
+            m &= (1ull << (b1 - s)) - 1ull;
+        cnt += __popcll(key[w] & m);
+    }
+    return (cnt & 1) ? -1 : 1;
+}
+
+// pair index k of n items -> (i, j), i < j, lexicographic
+__device__ inline void pair_decode(int k, int n, int &i, int &j)
+{
+    i = 0;
+    while (k >= n - 1 - i) {
+        k -= n - 1 - i;
+        i++;
+    }
+    j = i + 1 + k;
+}
+
+template <int W>
+__device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, const uint64_t *refkeys,
+                          const double *refc, int64_t nref, int64_t det)
+{
+    GenHead *H = g.head;
+    const int tid = threadIdx.x;
+    if (tid < W)
+        H->key[tid] = refkeys[(int64_t)tid * nref + det];
+    if (tid == 0)
+        H->c = refc[det];
+    for (int b = tid; b < 2 * s.norb; b += blockDim.x)
+        H->R[b] = s.R[b];
+    __syncthreads();
+    if (tid < 2) {
+        // occupied / virtual lists of one spin
+        int spin = tid, off = spin == 0 ? s.norb : 0, no = 0, nv = 0;
+        for (int p = 0; p < s.norb; p++) {
+            if (get_bit(H->key, off + p))
+                H->occ[spin][no++] = (uint8_t)p;
+            else
+                H->vir[spin][nv++] = (uint8_t)p;
+        }
+    } else if (tid == 64) {
+        uint64_t z = 0;
+        for (int b = 0; b < 2 * s.norb; b++)
+            if (get_bit(H->key, b))
+                z ^= H->R[b];
+        H->z = z;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < L.na * L.va; idx += blockDim.x) {
+        int oi = idx / L.va, vi = idx - oi * L.va;
+        g.ph[0][idx] = (int8_t)between_sign(H->key, s.norb, 0, H->occ[0][oi], H->vir[0][vi]);
+    }
+    for (int idx = tid; idx < L.nb * L.vb; idx += blockDim.x) {
+        int oi = idx / L.vb, vi = idx - oi * L.vb;
+        g.ph[1][idx] = (int8_t)between_sign(H->key, s.norb, 1, H->occ[1][oi], H->vir[1][vi]);
+    }
+    for (int idx = tid; idx < L.nopa; idx += blockDim.x) {
+        int i, j;
+        pair_decode(idx, L.na, i, j);
+        g.op[0][idx] = (uint16_t)(i | (j << 8));
+    }
+    for (int idx = tid; idx < L.nvpa; idx += blockDim.x) {
+        int i, j;
+        pair_decode(idx, L.va, i, j);
+        g.vp[0][idx] = (uint16_t)(i | (j << 8));
+    }
+    for (int idx = tid; idx < L.nopb; idx += blockDim.x) {
+        int i, j;
+        pair_decode(idx, L.nb, i, j);
+        g.op[1][idx] = (uint16_t)(i | (j << 8));
+    }
+    for (int idx = tid; idx < L.nvpb; idx += blockDim.x) {
+        int i, j;
+        pair_decode(idx, L.vb, i, j);
+        g.vp[1][idx] = (uint16_t)(i | (j << 8));
+    }
+    __syncthreads();
+}
+
+// q = x / d for 0 <= x < 2^26, d >= 1, via a float reciprocal and exact fix-up
+__device__ inline uint32_t udiv(uint32_t x, uint32_t d, float inv)
+{
+    uint32_t q = (uint32_t)((float)x * inv);
+    while ((uint64_t)q * d > x)
+        q--;
+    while ((uint64_t)(q + 1) * d <= x)
+        q++;
+    return q;
+}
+
+// A decoded excitation: kind 0/1 single alpha/beta, 2/3 double alpha-alpha /
+// beta-beta, 4 alpha-beta; indices into the occupied / virtual lists.
+struct Exc {
+    int kind;
+    int oi, vi, oj, vj;   // (oi -> vi) and, for doubles, (oj -> vj)
+};
+
+struct DivConsts {
+    float inv_va, inv_vb, inv_nvpa, inv_nvpb, inv_nSb;
+};
+
+__device__ inline Exc decode(const GenLds &g, const ExcLayout &L, const DivConsts &D, int64_t k)
+{
+    Exc e;
+    if (k < L.o1) {
+        uint32_t x = (uint32_t)k;
+        e.kind = 0;
+        e.oi = (int)udiv(x, L.va, D.inv_va);
+        e.vi = (int)(x - (uint32_t)e.oi * L.va);
+    } else if (k < L.o2) {
+        uint32_t x = (uint32_t)(k - L.o1);
+        e.kind = 1;
+        e.oi = (int)udiv(x, L.vb, D.inv_vb);
+        e.vi = (int)(x - (uint32_t)e.oi * L.vb);
+    } else if (k < L.o3) {
+        uint32_t x = (uint32_t)(k - L.o2);
+        uint32_t pi = udiv(x, L.nvpa, D.inv_nvpa), qi = x - pi * L.nvpa;
+        uint16_t op = g.op[0][pi], vp = g.vp[0][qi];
+        e.kind = 2;
+        e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
+    } else if (k < L.o4) {
+        uint32_t x = (uint32_t)(k - L.o3);
+        uint32_t pi = udiv(x, L.nvpb, D.inv_nvpb), qi = x - pi * L.nvpb;
+        uint16_t op = g.op[1][pi], vp = g.vp[1][qi];
+        e.kind = 3;
+        e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
+    } else {
+        uint32_t x = (uint32_t)(k - L.o4);
+        uint32_t ra = udiv(x, (uint32_t)L.nSb, D.inv_nSb), sb = x - ra * (uint32_t)L.nSb;
+        e.kind = 4;
+        e.oi = (int)udiv(ra, L.va, D.inv_va);
+        e.vi = (int)(ra - (uint32_t)e.oi * L.va);
+        e.oj = (int)udiv(sb, L.vb, D.inv_vb);
+        e.vj = (int)(sb - (uint32_t)e.oj * L.vb);
+    }
+    return e;
+}
+
+template <int W>
+__device__ inline void flip(uint64_t (&k)[W], int bit)
+{
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        k[w] ^= ((bit >> 6) == w) ? (1ull << (bit & 63)) : 0ull;
+}
+
+// Bits flipped by an excitation (spin-orbital indices) -> key and Zobrist hash.
+template <int W>
+__device__ inline void exc_key(const GenLds &g, int norb, const Exc &e, uint64_t (&key)[W], uint64_t &z)
+{
+    const GenHead *H = g.head;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        key[w] = H->key[w];
+    z = H->z;
+    int bits[4], nb;
+    if (e.kind == 0 || e.kind == 1) {
+        int off = e.kind == 0 ? norb : 0, sp = e.kind;
+        bits[0] = off + H->occ[sp][e.oi];
+        bits[1] = off + H->vir[sp][e.vi];
+        nb = 2;
+    } else if (e.kind == 2 || e.kind == 3) {
+        int sp = e.kind - 2, off = sp == 0 ? norb : 0;
+        bits[0] = off + H->occ[sp][e.oi];
+        bits[1] = off + H->occ[sp][e.oj];
+        bits[2] = off + H->vir[sp][e.vi];
+        bits[3] = off + H->vir[sp][e.vj];
+        nb = 4;
+    } else {
+        bits[0] = norb + H->occ[0][e.oi];
+        bits[1] = norb + H->vir[0][e.vi];
+        bits[2] = H->occ[1][e.oj];
+        bits[3] = H->vir[1][e.vj];
+        nb = 4;
+    }
+    for (int t = 0; t < nb; t++) {
+        flip<W>(key, bits[t]);
+        z ^= H->R[bits[t]];
+    }
+}
+
+__device__ inline int64_t eidx(int n, int p, int q, int r, int t)
+{
+    return (((int64_t)p * n + q) * n + r) * n + t;
+}
+
+// H_ai (without c_i) in the working precision F (double or float).
+template <typename F>
+__device__ inline F exc_value(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
+                              const F *V, const F *h)
+{
+    const GenHead *H = g.head;
+    const int n = s.norb;
+    if (e.kind <= 1) {
+        int sp = e.kind;
+        int r = H->occ[sp][e.oi], a = H->vir[sp][e.vi];
+        int vcount = sp == 0 ? L.va : L.vb;
+        F f = h[r * n + a];
+        const F *Vra = V + eidx(n, r, a, 0, 0);
+        for (int t = 0; t < 2; t++) {
+            int no = t == 0 ? L.na : L.nb;
+            for (int jj = 0; jj < no; jj++) {
+                int j = H->occ[t][jj];
+                f += Vra[j * n + j];
+                if (t == sp)
+                    f -= V[eidx(n, r, j, j, a)];
+            }
+        }
+        return (F)g.ph[sp][e.oi * vcount + e.vi] * f;
+    }
+    if (e.kind <= 3) {
+        int sp = e.kind - 2;
+        int vcount = sp == 0 ? L.va : L.vb;
+        int r = H->occ[sp][e.oi], q = H->occ[sp][e.oj];
+        int a = H->vir[sp][e.vi], b = H->vir[sp][e.vj];
+        int ph1 = g.ph[sp][e.oi * vcount + e.vi];
+        int ph2 = g.ph[sp][e.oj * vcount + e.vj];
+        int lo = q < b ? q : b, hi = q < b ? b : q;
+        if (r > lo && r < hi)
+            ph2 = -ph2;
+        if (a > lo && a < hi)
+            ph2 = -ph2;
+        F v = V[eidx(n, r, a, q, b)] - V[eidx(n, r, b, q, a)];
+        return (F)(ph1 * ph2) * v;
+    }
+    int r = H->occ[0][e.oi], a = H->vir[0][e.vi];
+    int q = H->occ[1][e.oj], b = H->vir[1][e.vj];
+    int ph = g.ph[0][e.oi * L.va + e.vi] * g.ph[1][e.oj * L.vb + e.vj];
+    return (F)ph * V[eidx(n, r, a, q, b)];
+}
+
+__device__ inline DivConsts div_consts(const ExcLayout &L)
+{
+    DivConsts D;
+    D.inv_va = L.va ? 1.0f / (float)L.va : 0.f;
+    D.inv_vb = L.vb ? 1.0f / (float)L.vb : 0.f;
+    D.inv_nvpa = L.nvpa ? 1.0f / (float)L.nvpa : 0.f;
+    D.inv_nvpb = L.nvpb ? 1.0f / (float)L.nvpb : 0.f;
+    D.inv_nSb = L.nSb ? 1.0f / (float)L.nSb : 0.f;
+    return D;
+}
+
+template <int W>
+__device__ inline void store_keys(const Planes &out, int64_t pos, const uint64_t (&key)[W])
+{
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        out.key[w][pos] = key[w];
+}
+
+// ---------------------------------------------------------------------------
+template <int W, bool F32>
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout L, const uint64_t *refkeys,
+                                                            const double *refc, int64_t nref, int64_t chunk,
+                                                            int cpd, Planes out)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    const int64_t det = blockIdx.x / cpd;
+    const int64_t ch = blockIdx.x - det * cpd;
+    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    const DivConsts D = div_consts(L);
+    const int64_t lo = ch * chunk;
+    const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
+    const int64_t base = det * L.nper;
+    const double c = g.head->c;
+    const float c32 = (float)c;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += GEN_THREADS) {
+        Exc e = decode(g, L, D, k);
+        uint64_t key[W], z;
+        exc_key<W>(g, s.norb, e, key, z);
+        store_keys<W>(out, base + k, key);
+        if (F32) {
+            float v = exc_value<float>(g, s, L, e, s.V32, s.h32) * c32;
+            ((float *)out.pay)[base + k] = v;
+        } else {
+            double v = exc_value<double>(g, s, L, e, s.V, s.h) * c;
+            ((double *)out.pay)[base + k] = v;
+        }
+    }
+}
+
+template <int W, bool F32>
+__device__ inline bool keep_term(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
+                                 double cutoff)
+{
+    if (cutoff <= 0.0)
+        return true;
+    if (F32) {
+        float v = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)g.head->c;
+        return fabsf(v) >= (float)cutoff;
+    }
+    double v = exc_value<double>(g, s, L, e, s.V, s.h) * g.head->c;
+    return fabs(v) >= cutoff;
+}
+
+__device__ inline uint32_t part_of(uint64_t z, int log2p) { return log2p == 0 ? 0u : (uint32_t)(z >> (64 - log2p)); }
+
+template <int W, bool F32>
+__global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, const uint64_t *refkeys,
+                                                       const double *refc, int64_t nref, int64_t chunk,
+                                                       int cpd, int log2p, double cutoff, uint32_t *cnt,
+                                                       int64_t nchunks)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    size_t a, b, c2, d, e2, f;
+    uint32_t *hist = (uint32_t *)(lds + lds_layout(L, &a, &b, &c2, &d, &e2, &f));
+    const int P = 1 << log2p;
+    for (int p = threadIdx.x; p < P; p += GEN_THREADS)
+        hist[p] = 0;
+    const int64_t det = blockIdx.x / cpd;
+    const int64_t ch = blockIdx.x - det * cpd;
+    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    const DivConsts D = div_consts(L);
+    const int64_t lo = ch * chunk;
+    const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += GEN_THREADS) {
+        Exc e = decode(g, L, D, k);
+        uint64_t key[W], z;
+        exc_key<W>(g, s.norb, e, key, z);
+        if (keep_term<W, F32>(g, s, L, e, cutoff))
+            atomicAdd(&hist[part_of(z, log2p)], 1u);
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += GEN_THREADS)
+        cnt[(int64_t)p * nchunks + blockIdx.x] = hist[p];
+}
+
+template <int W, bool F32>
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout L, const uint64_t *refkeys,
+                                                             const double *refc, int64_t nref, int64_t chunk,
+                                                             int cpd, int log2p, uint32_t part, double cutoff,
+                                                             const uint64_t *off, uint64_t cap, Planes out,
+                                                             Flags *flags)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    size_t a, b, c2, d, e2, f;
+    uint32_t *wtot = (uint32_t *)(lds + lds_layout(L, &a, &b, &c2, &d, &e2, &f));
+    const int64_t det = blockIdx.x / cpd;
+    const int64_t ch = blockIdx.x - det * cpd;
+    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    const DivConsts D = div_consts(L);
+    const int64_t lo = ch * chunk;
+    const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t pos = off[blockIdx.x];
+    const double c = g.head->c;
+    const float c32 = (float)c;
+    for (int64_t k0 = lo; k0 < hi; k0 += GEN_THREADS) {
+        const int64_t k = k0 + threadIdx.x;
+        bool keep = false;
+        Exc e;
+        uint64_t key[W], z = 0;
+        if (k < hi) {
+            e = decode(g, L, D, k);
+            exc_key<W>(g, s.norb, e, key, z);
+            keep = part_of(z, log2p) == part && keep_term<W, F32>(g, s, L, e, cutoff);
+        }
+        uint64_t m = __ballot(keep);
+        if (lane == 0)
+            wtot[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t woff = 0, btot = 0;
+        for (int w = 0; w < GEN_THREADS / 64; w++) {
+            uint32_t t = wtot[w];
+            woff += w < wave ? t : 0u;
+            btot += t;
+        }
+        if (keep) {
+            uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
+            if (p < cap) {
+                store_keys<W>(out, (int64_t)p, key);
+                if (F32)
+                    ((float *)out.pay)[p] = exc_value<float>(g, s, L, e, s.V32, s.h32) * c32;
+                else
+                    ((double *)out.pay)[p] = exc_value<double>(g, s, L, e, s.V, s.h) * c;
+            } else {
+                atomicOr(&flags->err, ERR_OVERFLOW);
+            }
+        }
+        pos += btot;
+        __syncthreads();
+    }
+}
+
+// Exclusive scan over chunks of one subset's counts; one workgroup per subset.
+__global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts,
+                                                     uint64_t *off, uint64_t *tot)
+{
+    __shared__ uint64_t sh[1024];
+    const uint32_t p = parts[blockIdx.x];
+    const uint32_t *src = cnt + (int64_t)p * nchunks;
+    uint64_t *dst = off + (int64_t)blockIdx.x * nchunks;
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < nchunks; b += 1024) {
+        int64_t i = b + threadIdx.x;
+        uint64_t v = i < nchunks ? src[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            uint64_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nchunks)
+            dst[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        tot[blockIdx.x] = carry;
+}
+
+template <int W, bool F32>
+hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc,
+                        int64_t nref, int64_t chunk, Planes out, hipStream_t st)
+{
+    int cpd = (int)((L.nper + chunk - 1) / chunk);
+    int64_t blocks = nref * cpd;
+    if (blocks == 0 || L.nper == 0)
+        return hipSuccess;
+    size_t lds = gen_lds_bytes(L);
+    hipLaunchKernelGGL((k_gen_direct<W, F32>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refkeys,
+                       refc, nref, chunk, cpd, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gen_lds_bytes(const ExcLayout &L)
+{
+    size_t a, b, c, d, e, f;
+    return lds_layout(L, &a, &b, &c, &d, &e, &f);
+}
+
+#define PT2_DISPATCH(W_, F32_, CALL)                                                                   \
+    switch ((W_) * 2 + ((F32_) ? 1 : 0)) {                                                             \
+    case 2: return CALL(1, false);                                                                     \
+    case 3: return CALL(1, true);                                                                      \
+    case 4: return CALL(2, false);                                                                     \
+    case 5: return CALL(2, true);                                                                      \
+    case 6: return CALL(3, false);                                                                     \
+    case 7: return CALL(3, true);                                                                      \
+    case 8: return CALL(4, false);                                                                     \
+    case 9: return CALL(4, true);                                                                      \
+    default: return hipErrorInvalidValue;                                                              \
+    }
+
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
+                             const double *refc, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
+{
+#define CALL(W, F) gen_direct_t<W, F>(s, L, refkeys, refc, nref, chunk, out, st)
+    PT2_DISPATCH(s.W, fp32, CALL)
+#undef CALL
+}
+
+namespace {
+template <int W, bool F32>
+hipError_t count_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc, int64_t nref,
+                   int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st)
+{
+    int cpd = (int)((L.nper + chunk - 1) / chunk);
+    if (nchunks != nref * cpd)
+        return hipErrorInvalidValue;
+    if (nchunks == 0)
+        return hipSuccess;
+    size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * ((size_t)1 << log2p);
+    hipLaunchKernelGGL((k_count<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refkeys, refc,
+                       nref, chunk, cpd, log2p, cutoff, cnt, nchunks);
+    return hipGetLastError();
+}
+
+template <int W, bool F32>
+hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc,
+                         int64_t nref, int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
+                         int64_t nchunks, uint64_t cap, Planes out, Flags *flags, hipStream_t st)
+{
+    int cpd = (int)((L.nper + chunk - 1) / chunk);
+    if (nchunks != nref * cpd)
+        return hipErrorInvalidValue;
+    if (nchunks == 0)
+        return hipSuccess;
+    size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * (GEN_THREADS / 64);
+    hipLaunchKernelGGL((k_gen_compact<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refkeys,
+                       refc, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys, const double *refc,
+                        int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
+                        hipStream_t st)
+{
+#define CALL(W, F) count_t<W, F>(s, L, refkeys, refc, nref, chunk, log2p, cutoff, cnt, nchunks, st)
+    PT2_DISPATCH(s.W, fp32, CALL)
+#undef CALL
+}
+
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
+                              const double *refc, int64_t nref, int64_t chunk, int log2p, uint32_t part,
+                              double cutoff, const uint64_t *off, int64_t nchunks, uint64_t cap, Planes out,
+                              Flags *flags, hipStream_t st)
+{
+#define CALL(W, F) \
+    gen_compact_t<W, F>(s, L, refkeys, refc, nref, chunk, log2p, part, cutoff, off, nchunks, cap, out, flags, st)
+    PT2_DISPATCH(s.W, fp32, CALL)
+#undef CALL
+}
+
+hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts, uint64_t *off,
+                             uint64_t *tot, hipStream_t st)
+{
+    if (nparts == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_scan, dim3(nparts), dim3(1024), 0, st, cnt, nchunks, parts, off, tot);
+    return hipGetLastError();
+}
+
+}  // namespace pt2

@@ -1,0 +1,162 @@
+// Internal declarations shared by the HIP translation units of the PT2 engine.
+// Nothing here is part of the C-ABI (include/pt2.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pt2 {
+
+constexpr int MAXW = 4;        // 2*norb <= 256 bits
+constexpr int MAXORB = 128;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // records per onesweep tile
+constexpr int RED_THREADS = 256;
+constexpr int RED_ITEMS = 8;
+constexpr int RED_TILE = RED_THREADS * RED_ITEMS;     // records per reduce tile
+constexpr int RED_GRID = 4096;                        // fixed -> bit-reproducible sums
+constexpr int RED_LDS_REFS = 256;                     // reference keys staged per tile
+constexpr int GEN_THREADS = 256;
+
+// Device-side error flags (bitmask in Flags::err).
+enum : uint32_t {
+    ERR_POPCOUNT = 1u,      // a reference has the wrong electron count
+    ERR_STRAY_BITS = 2u,    // bits at or above 2*norb
+    ERR_DUPLICATE = 4u,     // two equal reference determinants
+    ERR_LOOKBACK = 8u,      // a look-back wait exceeded its bound
+    ERR_SINGULAR = 16u,     // E0 - H_aa == 0 for an external determinant
+    ERR_OVERFLOW = 32u      // a compacted write ran past its planned range
+};
+
+struct Flags {
+    uint32_t err;
+    uint32_t pad;
+};
+
+// Device view of the Hamiltonian (all pointers are device memory).
+struct DevSys {
+    int norb, na, nb, W;
+    const double *h;    // norb x norb
+    const double *V;    // norb^4, (pq|rs) row-major
+    const float *h32;   // FP32 copies (precision form), else null
+    const float *V32;
+    const double *T;    // (2 norb)^2 spin-orbital pair table for the diagonal:
+                        // T[b][b] = h_pp; T[b1][b2] (b1<b2) = (pp|qq) - [same spin](pq|qp)
+    const uint64_t *R;  // Zobrist words, one per bit (2 norb)
+};
+
+// Structure-of-arrays record buffer: W key planes then one payload plane.
+struct Planes {
+    uint64_t *key[MAXW];
+    void *pay;
+};
+
+// Per-block partial of the single pass; summed in block order.
+struct Partial {
+    double e_sum, e_comp;     // Neumaier pair
+    double ref_cross;
+    double min_abs_denom;
+    uint64_t n_unique, n_external, n_hit, n_nonneg;
+    uint64_t key_xor, key_sum;
+};
+
+// Layout of one reference determinant's excitation space (closed form).
+struct ExcLayout {
+    int na, nb, va, vb;
+    int64_t nSa, nSb, nDaa, nDbb, nDab;   // block sizes
+    int64_t o1, o2, o3, o4, nper;         // block offsets; nper = total
+    int nvpa, nvpb, nopa, nopb;           // virtual / occupied pair counts
+};
+
+inline ExcLayout make_layout(int norb, int na, int nb)
+{
+    ExcLayout L;
+    L.na = na, L.nb = nb, L.va = norb - na, L.vb = norb - nb;
+    auto c2 = [](int64_t n) { return n * (n - 1) / 2; };
+    L.nSa = (int64_t)na * L.va;
+    L.nSb = (int64_t)nb * L.vb;
+    L.nopa = (int)c2(na), L.nopb = (int)c2(nb), L.nvpa = (int)c2(L.va), L.nvpb = (int)c2(L.vb);
+    L.nDaa = (int64_t)L.nopa * L.nvpa;
+    L.nDbb = (int64_t)L.nopb * L.nvpb;
+    L.nDab = L.nSa * L.nSb;
+    L.o1 = L.nSa;
+    L.o2 = L.o1 + L.nSb;
+    L.o3 = L.o2 + L.nDaa;
+    L.o4 = L.o3 + L.nDbb;
+    L.nper = L.o4 + L.nDab;
+    return L;
+}
+
+// Excitation-index chunk handled by one generation workgroup: a multiple of
+// 16384 (or the whole determinant) such that the grid stays below
+// max_chunks workgroups (and 2^32 work-items).
+inline int64_t gen_chunk(const ExcLayout &L, int64_t nref, int64_t max_chunks)
+{
+    int64_t chunk = 16384;
+    if (max_chunks > (int64_t)1 << 24)
+        max_chunks = (int64_t)1 << 24;
+    while (chunk < L.nper && nref * ((L.nper + chunk - 1) / chunk) > max_chunks)
+        chunk *= 2;
+    if (chunk > L.nper)
+        chunk = L.nper > 0 ? L.nper : 1;
+    return chunk;
+}
+
+inline int64_t gen_nchunks(const ExcLayout &L, int64_t nref, int64_t chunk)
+{
+    return nref * ((L.nper + chunk - 1) / chunk);
+}
+
+// ---- launch wrappers (runtime dispatch over W and payload precision) ----
+
+// gen.hip
+size_t gen_lds_bytes(const ExcLayout &L);
+// Direct generation: every term of every reference, record index
+// det*nper + k.  Requires no cutoff and a single subset.
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
+                             const double *refc, int64_t nref, int64_t chunk, Planes out, hipStream_t st);
+// Count pass: cnt[p * nchunks + chunk] = kept terms of chunk in subset p.
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
+                        const double *refc, int64_t nref, int64_t chunk, int log2p, double cutoff,
+                        uint32_t *cnt, int64_t nchunks, hipStream_t st);
+// Exclusive scan of cnt[p][*] into off[p][*] for each listed subset; tot[k] = N of parts[k].
+hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
+                             uint64_t *off, uint64_t *tot, hipStream_t st);
+// Compacting generation of subset `part` (offsets from launch_chunk_scan).
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
+                              const double *refc, int64_t nref, int64_t chunk, int log2p,
+                              uint32_t part, double cutoff, const uint64_t *off, int64_t nchunks,
+                              uint64_t cap, Planes out, Flags *flags, hipStream_t st);
+
+// sort.hip
+// hist[d*256 + v] += count of digit value v at digit position d (d < ndig).
+hipError_t launch_hist(int W, const Planes &in, int64_t n, int ndig, uint64_t *hist, hipStream_t st);
+// bucket[d*256 + v] = exclusive scan of hist[d][*].
+hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hipStream_t st);
+// One stable LSD digit pass (onesweep): scatter in -> out by digit `dig`.
+hipError_t launch_onesweep(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n,
+                           int dig, const uint64_t *bucket, uint64_t *status, uint32_t *tile_ctr,
+                           uint32_t epoch, Flags *flags, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
+hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t st);
+// AoS dets + coeffs -> SoA planes, with input checks.
+hipError_t launch_refs_split(int W, int norb, int na, int nb, const uint64_t *dets, const double *c,
+                             int64_t n, Planes out, Flags *flags, hipStream_t st);
+hipError_t launch_dup_check(int W, const Planes &sorted, int64_t n, Flags *flags, hipStream_t st);
+// SoA planes -> AoS keys (for inspection)
+hipError_t launch_planes_to_aos(int W, int pay_bytes, const Planes &in, int64_t n, uint64_t *keys,
+                                double *pay, hipStream_t st);
+
+// reduce.hip
+hipError_t launch_reduce(const DevSys &s, int fp32, const Planes &sorted, int64_t n,
+                         const Planes &refs, int64_t nref, double e0, Partial *partials, Flags *flags,
+                         hipStream_t st);
+// Sum RED_GRID partials in order into *out (device).
+hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
+// Inspection: unique keys and numerators (n_out on device).
+hipError_t launch_numerators(int W, int fp32, const Planes &sorted, int64_t n, const Planes &refs,
+                             int64_t nref, uint64_t *keys_aos, double *num, uint8_t *in_ref,
+                             unsigned long long *n_out, int64_t cap, hipStream_t st);
+
+}  // namespace pt2

@@ -1,0 +1,120 @@
+"""The C-ABI library: it loads, exports every entry point of include/pt2.h,
+and rejects bad arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "pt2.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt2_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    import paper_1808_02049_amd as pt2
+    lib = C.CDLL(pt2.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pt2.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout():
+    import paper_1808_02049_amd as pt2
+    o = pt2.default_options()
+    assert o.struct_size == C.sizeof(pt2.Options)
+    assert o.log2_partitions == -1 and o.precision == pt2.PT2_FP64 and o.cutoff == 0.0
+
+
+def test_key_words():
+    import paper_1808_02049_amd as pt2
+    assert [pt2.key_words(n) for n in (1, 12, 32, 33, 40, 64, 76, 100, 128)] == [1, 1, 1, 2, 2, 2, 3, 4, 4]
+
+
+def _sys(norb=4):
+    import synth
+    h, eri, _ = synth.make_integrals(norb, 4, 1)
+    return h, eri
+
+
+@pytest.mark.parametrize("kw,match", [
+    (dict(norb=0), "norb"), (dict(norb=129), "norb"), (dict(nalpha=5), "electron"),
+    (dict(nbeta=-1), "electron")])
+def test_create_rejects_bad_sizes(kw, match):
+    import paper_1808_02049_amd as pt2
+    args = dict(norb=4, nalpha=2, nbeta=2)
+    args.update(kw)
+    n = max(args["norb"], 1)
+    h = np.eye(n)
+    eri = np.zeros(n ** 4)
+    o = pt2.default_options()
+    ctx = C.c_void_p()
+    rc = pt2._lib.pt2_create(h.ctypes.data_as(C.POINTER(C.c_double)),
+                             eri.ctypes.data_as(C.POINTER(C.c_double)), args["norb"],
+                             args["nalpha"], args["nbeta"], C.byref(o), C.byref(ctx))
+    assert rc == pt2.PT2_E_INVALID
+    assert match in pt2._lib.pt2_last_error().decode()
+
+
+def test_create_rejects_asymmetric_integrals():
+    import paper_1808_02049_amd as pt2
+    h, eri = _sys()
+    bad = eri.copy().reshape(4, 4, 4, 4)
+    bad[0, 1, 2, 3] += 1e-6
+    with pytest.raises(pt2.PT2Error) as e:
+        pt2.Context(h, bad, 4, 2, 2)
+    assert e.value.code == pt2.PT2_E_INVALID and "symmetric" in str(e.value)
+    hb = h.copy()
+    hb[0, 1] += 1e-3
+    with pytest.raises(pt2.PT2Error) as e:
+        pt2.Context(hb, eri, 4, 2, 2)
+    assert e.value.code == pt2.PT2_E_INVALID
+
+
+def test_bad_options_rejected():
+    import paper_1808_02049_amd as pt2
+    h, eri = _sys()
+    with pytest.raises(pt2.PT2Error):
+        pt2.Context(h, eri, 4, 2, 2, cutoff=-1.0)
+    with pytest.raises(pt2.PT2Error):
+        pt2.Context(h, eri, 4, 2, 2, log2_partitions=13)
+
+
+def test_evaluate_null_context_rejected():
+    import paper_1808_02049_amd as pt2
+    r = pt2.Result()
+    r.struct_size = C.sizeof(pt2.Result)
+    assert pt2._lib.pt2_evaluate(None, None, None, 0, 0.0, C.byref(r)) == pt2.PT2_E_INVALID
+    r.struct_size = 3
+    assert pt2._lib.pt2_poll(None, 1, C.byref(r)) == pt2.PT2_E_INVALID
+
+
+def test_sort_records_argument_checks():
+    import paper_1808_02049_amd as pt2
+    k = np.zeros(4, dtype=np.uint64)
+    p = np.zeros(4, dtype=np.float64)
+    assert pt2._lib.pt2_sort_records(0, 5, 8, k.ctypes.data_as(C.POINTER(C.c_uint64)), p.ctypes.data, 8, 4) \
+        == pt2.PT2_E_INVALID
+    assert pt2._lib.pt2_sort_records(0, 1, 8, k.ctypes.data_as(C.POINTER(C.c_uint64)), p.ctypes.data, 2, 4) \
+        == pt2.PT2_E_INVALID
+    # n <= 1 is a no-op and needs no device
+    assert pt2._lib.pt2_sort_records(0, 1, 8, k.ctypes.data_as(C.POINTER(C.c_uint64)), p.ctypes.data, 8, 1) \
+        == pt2.PT2_OK
+
+
+def test_no_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_1808_02049_amd as pt2
+    h, eri = _sys()
+    with pytest.raises(pt2.PT2Error) as e:
+        pt2.Context(h, eri, 4, 2, 2)
+    assert e.value.code == pt2.PT2_E_DEVICE

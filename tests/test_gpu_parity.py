@@ -1,0 +1,326 @@
+"""Parity of the HIP engine with the FP64 CPU oracle, through the C-ABI.
+
+Keys and counts must match bit for bit; FP64 energies within 1e-9 Eh and
+FP32-payload energies within 1e-6 Eh of the FP64 oracle (the stated bars);
+per-term payloads within a few ulp.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def pt2():
+    _need_gpu()
+    import paper_1808_02049_amd as m
+    return m
+
+
+def load(name):
+    w = synth.WORKLOADS[name]
+    h, eri, rng = synth.make_integrals(w.norb, w.n_chol, w.seed)
+    f = np.load(os.path.join(HERE, "golden", f"inputs_{name}.npz"))
+    dets, e0 = f["dets"], float(f["e0"])
+    if "c" in f:
+        c = f["c"]
+    else:
+        c = synth.decaying_coefficients(w.n_ref, w.decay, synth.draw_signs(rng, w.n_ref))
+    return w, h, eri, dets, c, e0
+
+
+@pytest.fixture(scope="module")
+def c1(pt2):
+    w, h, eri, dets, c, e0 = load("c1")
+    ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, timing=True)
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    ref, _ = O.pt2(dets, c, e0)
+    yield dict(w=w, h=h, eri=eri, dets=dets, c=c, e0=e0, ctx=ctx, O=O, ref=ref)
+    ctx.close()
+
+
+COUNT_KEYS = ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum",
+              "n_nonneg_denom")
+
+
+def assert_matches(got, ref, tol=1e-9):
+    print(f"E gpu={got['e_pt2']:.15f} oracle={ref['e_pt2']:.15f} dE={got['e_pt2'] - ref['e_pt2']:.2e}",
+          flush=True)
+    assert abs(got["e_pt2"] - ref["e_pt2"]) <= tol
+    for k in COUNT_KEYS:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    assert got["ref_cross"] == pytest.approx(ref["ref_cross"], abs=1e-11)
+    if ref["n_external"]:
+        assert got["min_abs_denom"] == pytest.approx(ref["min_abs_denom"], rel=1e-12)
+
+
+def sort_by_key(dets):
+    W = dets.shape[1]
+    return np.lexsort(tuple(dets[:, w] for w in range(W)))
+
+
+# ---------------------------------------------------------------------------
+# C1: (4a,4b)/12, 200 reference determinants, eigenvector reference
+
+def test_c1_energy_host_inputs(c1):
+    got = c1["ctx"].evaluate(c1["dets"], c1["c"], c1["e0"])
+    assert_matches(got, c1["ref"])
+    assert got["n_contrib"] == 284_800 and got["n_partitions"] == 1
+
+
+def test_c1_energy_device_inputs(c1):
+    import torch
+    d = torch.from_numpy(c1["dets"].view(np.int64)).cuda()
+    cc = torch.from_numpy(c1["c"]).cuda()
+    got = c1["ctx"].evaluate(d, cc, c1["e0"])
+    assert_matches(got, c1["ref"])
+
+
+def test_c1_generated_records_match_oracle(c1):
+    order = sort_by_key(c1["dets"])
+    dets, c = c1["dets"][order], c1["c"][order]
+    gk, gv = c1["ctx"].dump_records(dets, c, sorted=False)
+    ok, ov = c1["O"].emit(dets, c)
+    assert gk.shape == ok.shape
+    assert np.array_equal(gk, ok)
+    np.testing.assert_allclose(gv, ov, rtol=0, atol=4 * np.finfo(float).eps * np.abs(ov).max())
+
+
+def test_c1_sorted_records_are_stable_sort(c1):
+    order = sort_by_key(c1["dets"])
+    dets, c = c1["dets"][order], c1["c"][order]
+    gk, gv = c1["ctx"].dump_records(dets, c, sorted=False)
+    sk, sv = c1["ctx"].dump_records(dets, c, sorted=True)
+    idx = np.lexsort(tuple(gk[:, w] for w in range(gk.shape[1])))  # stable
+    assert np.array_equal(sk, gk[idx])
+    assert np.array_equal(sv, gv[idx])
+
+
+def test_c1_numerators_match_oracle(c1):
+    gk, gn, gin = c1["ctx"].dump_numerators(c1["dets"], c1["c"])
+    ok, on = c1["O"].numerators(c1["dets"], c1["c"])
+    assert np.array_equal(gk, ok)
+    np.testing.assert_allclose(gn, on, rtol=0, atol=1e-14)
+    refset = {tuple(r) for r in c1["dets"]}
+    assert np.array_equal(gin, np.array([tuple(k) in refset for k in ok]))
+
+
+def test_c1_input_order_does_not_matter(c1):
+    perm = np.random.default_rng(0).permutation(len(c1["dets"]))
+    a = c1["ctx"].evaluate(c1["dets"], c1["c"], c1["e0"])
+    b = c1["ctx"].evaluate(c1["dets"][perm], c1["c"][perm], c1["e0"])
+    assert a["e_pt2"] == b["e_pt2"]
+
+
+def test_c1_deterministic(c1):
+    a = c1["ctx"].evaluate(c1["dets"], c1["c"], c1["e0"])
+    b = c1["ctx"].evaluate(c1["dets"], c1["c"], c1["e0"])
+    assert a["e_pt2"] == b["e_pt2"] and a["key_sum"] == b["key_sum"]
+
+
+@pytest.mark.parametrize("log2p", [1, 3, 6])
+def test_c1_forced_split(pt2, c1, log2p):
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, log2_partitions=log2p)
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    assert got["n_partitions"] == 1 << log2p
+    assert_matches(got, c1["ref"])
+    ctx.close()
+
+
+def test_c1_small_budget_makes_planner_split(pt2, c1):
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, max_partition_bytes=2_000_000)
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    assert got["n_partitions"] > 1
+    assert_matches(got, c1["ref"])
+    ctx.close()
+
+
+def test_c1_listed_subsets_match_oracle(c1):
+    parts = [0, 5, 17, 31]
+    got, ep = c1["ctx"].evaluate_parts(c1["dets"], c1["c"], c1["e0"], 5, parts)
+    ref, rp = c1["O"].pt2(c1["dets"], c1["c"], c1["e0"], log2p=5, parts=parts)
+    np.testing.assert_allclose(ep, rp, rtol=0, atol=1e-11)
+    assert_matches(got, ref)
+
+
+def test_c1_fp32_payload_form(pt2, c1):
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, precision="fp32")
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    print("fp32 dE", got["e_pt2"] - c1["ref"]["e_pt2"], flush=True)
+    assert abs(got["e_pt2"] - c1["ref"]["e_pt2"]) <= 1e-6
+    for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
+        assert got[k] == c1["ref"][k]
+    ctx.close()
+
+
+def test_c1_cutoff(pt2, c1):
+    k, v = c1["O"].emit(c1["dets"], c1["c"])
+    cut = float(np.quantile(np.abs(v), 0.4))
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, cutoff=cut)
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    ref, _ = c1["O"].pt2(c1["dets"], c1["c"], c1["e0"], cutoff=cut)
+    assert got["n_after_cutoff"] == ref["n_kept"]
+    assert got["n_contrib"] == ref["n_contrib"]
+    assert abs(got["e_pt2"] - ref["e_pt2"]) <= 1e-9
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Word-straddling keys and every key width
+
+@pytest.mark.parametrize("norb,na,nb,nref,log2p", [
+    (6, 2, 2, 30, -1), (33, 3, 2, 25, -1), (40, 4, 4, 12, 2), (64, 3, 3, 10, -1),
+    (65, 3, 2, 10, -1), (76, 4, 3, 6, 1), (100, 3, 3, 5, -1), (128, 2, 2, 5, -1), (9, 0, 3, 20, -1),
+    (7, 4, 0, 15, -1)])
+def test_random_systems_all_widths(pt2, norb, na, nb, nref, log2p):
+    h, eri, _ = synth.make_integrals(norb, 6, 7000 + norb)
+    dets = synth.random_determinants(norb, na, nb, nref, norb)
+    c = np.random.default_rng(norb).normal(size=nref)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    e0 = float(O.diag(dets).min()) - 2.0
+    ref, _ = O.pt2(dets, c, e0)
+    ctx = pt2.Context(h, eri, norb, na, nb, log2_partitions=log2p)
+    got = ctx.evaluate(dets, c, e0)
+    assert_matches(got, ref)
+    order = sort_by_key(dets)
+    gk, gv = ctx.dump_records(dets[order], c[order])
+    ok, ov = O.emit(dets[order], c[order])
+    assert np.array_equal(gk, ok)
+    np.testing.assert_allclose(gv, ov, rtol=0, atol=1e-14)
+    ctx.close()
+
+
+def test_full_fci_reference_gives_zero(pt2):
+    norb, na, nb = 7, 3, 2
+    h, eri, _ = synth.make_integrals(norb, 6, 5)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    keys = B.keys_of(np.arange(B.dim()))
+    c = np.random.default_rng(1).normal(size=len(keys))
+    ctx = pt2.Context(h, eri, norb, na, nb)
+    got = ctx.evaluate(keys, c, -10.0)
+    assert got["e_pt2"] == 0.0 and got["n_external"] == 0
+    assert got["n_in_ref_hit"] == len(keys)
+    ctx.close()
+
+
+def test_hf_only_and_empty_reference(pt2, c1):
+    hf = synth.hf_key(12, 4, 4)[None]
+    e0 = float(c1["O"].diag(hf)[0])
+    got = c1["ctx"].evaluate(hf, [1.0], e0)
+    ref, _ = c1["O"].pt2(hf, [1.0], e0)
+    assert_matches(got, ref)
+    assert got["n_unique"] == got["n_contrib"] == 1424
+    empty = c1["ctx"].evaluate(np.zeros((0, 1), np.uint64), np.zeros(0), e0)
+    assert empty["e_pt2"] == 0.0 and empty["n_contrib"] == 0
+
+
+def test_invalid_references_rejected(pt2, c1):
+    ctx = c1["ctx"]
+    d = c1["dets"][:10].copy()
+    with pytest.raises(pt2.PT2Error) as e:
+        ctx.evaluate(np.concatenate([d, d[3:4]]), np.ones(11), -1.0)
+    assert e.value.code == pt2.PT2_E_INVALID and "duplicate" in str(e.value)
+    bad = d.copy()
+    bad[0, 0] ^= np.uint64(1 << 11)  # flips one beta bit: wrong electron count
+    with pytest.raises(pt2.PT2Error) as e:
+        ctx.evaluate(bad, np.ones(10), -1.0)
+    assert e.value.code == pt2.PT2_E_INVALID
+    stray = d.copy()
+    stray[0, 0] |= np.uint64(1 << 40)
+    with pytest.raises(pt2.PT2Error) as e:
+        ctx.evaluate(stray, np.ones(10), -1.0)
+    assert e.value.code == pt2.PT2_E_INVALID
+    # the context stays usable
+    assert_matches(ctx.evaluate(c1["dets"], c1["c"], c1["e0"]), c1["ref"])
+
+
+# ---------------------------------------------------------------------------
+# The radix sort on its own
+
+@pytest.mark.parametrize("W,bits,n,pb,skew", [
+    (1, 24, 1000, 8, False), (1, 64, 70_001, 4, False), (2, 80, 123_457, 8, True),
+    (3, 152, 50_000, 8, False), (4, 200, 9_000, 4, True), (2, 72, 4096, 8, False),
+    (2, 80, 4097, 8, True), (1, 8, 300_000, 8, True)])
+def test_sort_records_matches_stable_sort(pt2, W, bits, n, pb, skew):
+    rng = np.random.default_rng(W * 1000 + n)
+    keys = rng.integers(0, 2 ** 63, size=(n, W), dtype=np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, size=(n, W), dtype=np.uint64)
+    if skew:
+        keys[rng.random(n) < 0.7] = keys[0]
+        keys[:, 0] &= np.uint64(0xFF00FF00FFFF00FF)
+    for w in range(W):
+        top = bits - 64 * w
+        if top <= 0:
+            keys[:, w] = 0
+        elif top < 64:
+            keys[:, w] &= np.uint64((1 << top) - 1)
+    pay = np.arange(n, dtype=np.float64 if pb == 8 else np.uint32)
+    sk, sp = pt2.sort_records(keys.copy(), pay.copy(), bits)
+    idx = np.lexsort(tuple(keys[:, w] for w in range(W)))
+    assert np.array_equal(sk, keys[idx])
+    assert np.array_equal(sp, pay[idx])
+
+
+# ---------------------------------------------------------------------------
+# C2 at full size: (10a,10b)/40, 10,000 references, 1.2975e9 terms
+
+@pytest.fixture(scope="module")
+def c2(pt2):
+    w, h, eri, dets, c, e0 = load("c2")
+    ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, timing=True)
+    yield dict(w=w, h=h, eri=eri, dets=dets, c=c, e0=e0, ctx=ctx)
+    ctx.close()
+
+
+def test_c2_full_size_bench_configuration(c2):
+    """The single-subset launch that the benchmark times, checked by properties
+    that hold at any size: the closed-form count, the <c|H|c> identity built
+    from the in-reference numerators, and the split-invariance of the total."""
+    import torch
+    d = torch.from_numpy(c2["dets"].view(np.int64)).cuda()
+    cc = torch.from_numpy(c2["c"]).cuda()
+    got = c2["ctx"].evaluate(d, cc, c2["e0"])
+    print({k: got[k] for k in ("e_pt2", "n_contrib", "n_unique", "n_external", "n_in_ref_hit",
+                               "ms_gen", "ms_sort", "ms_reduce", "ms_hist", "n_sort_passes")}, flush=True)
+    assert got["n_contrib"] == 1_297_500_000 and got["n_partitions"] == 1
+    O = oracle.Oracle(c2["h"], c2["eri"], 40, 10, 10)
+    hii = O.diag(c2["dets"])
+    assert got["ref_cross"] + float(np.sum(c2["c"] ** 2 * hii)) == pytest.approx(c2["e0"], abs=1e-9)
+    assert got["n_unique"] == got["n_external"] + got["n_in_ref_hit"]
+    c2["total"] = got
+
+
+def test_c2_sampled_subsets_match_oracle(c2):
+    parts = [0, 77, 511, 1023]
+    got, ep = c2["ctx"].evaluate_parts(c2["dets"], c2["c"], c2["e0"], 10, parts)
+    O = oracle.Oracle(c2["h"], c2["eri"], 40, 10, 10)
+    ref, rp = O.pt2(c2["dets"], c2["c"], c2["e0"], log2p=10, parts=parts)
+    print("subset energies", ep, rp, flush=True)
+    np.testing.assert_allclose(ep, rp, rtol=0, atol=1e-9)
+    assert_matches(got, ref)
+
+
+def test_c2_split_total_equals_single_subset(c2):
+    if "total" not in c2:
+        pytest.skip("full-size run did not complete")
+    import paper_1808_02049_amd as pt2
+    ctx = pt2.Context(c2["h"], c2["eri"], 40, 10, 10, log2_partitions=3)
+    got = ctx.evaluate(c2["dets"], c2["c"], c2["e0"])
+    ctx.close()
+    tot = c2["total"]
+    assert got["e_pt2"] == pytest.approx(tot["e_pt2"], abs=1e-9)
+    for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
+        assert got[k] == tot[k]
