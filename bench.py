@@ -1,0 +1,187 @@
+"""Benchmark: PT2 contributions/s of the MI355X engine on a synthetic workload.
+
+One step = one complete evaluation (reference sort, generation, every radix
+pass, single pass, final sum) of workload C2: (10a,10b) electrons in 40
+orbitals, 10,000 reference determinants, 1,297,500,000 single+double
+contributions, FP64, one subset.  Inputs are resident in HBM before the timed
+region starts.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+
+The roofline entry is for the dominant kernel, the onesweep digit pass:
+algorithmic bytes per launch (each record read once and written once,
+2 * (8W + 8) bytes per record) over the average pass duration measured with
+HIP events on the stream the passes run on, inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def load_workload(name):
+    import synth
+    w = synth.WORKLOADS[name]
+    h, eri, rng = synth.make_integrals(w.norb, w.n_chol, w.seed)
+    f = np.load(os.path.join(ROOT, "tests", "golden", f"inputs_{name}.npz"))
+    dets, e0 = f["dets"], float(f["e0"])
+    c = f["c"] if "c" in f else synth.decaying_coefficients(w.n_ref, w.decay,
+                                                            synth.draw_signs(rng, w.n_ref))
+    return w, h, eri, dets, c, e0
+
+
+def cpu_baseline(w, h, eri, dets, c, e0, nref_sample, gpu_ctx):
+    """The FP64 oracle on the first nref_sample references (all their
+    contributions), timed on the host cores; the same sample on the GPU gives
+    a parity check."""
+    import oracle
+    threads = oracle.default_threads()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    d, cc = dets[:nref_sample], c[:nref_sample]
+    t0 = time.perf_counter()
+    ref, _ = O.pt2(d, cc, e0, nthreads=threads)
+    dt = time.perf_counter() - t0
+    got = gpu_ctx.evaluate(d, cc, e0)
+    return {"value": ref["n_contrib"] / dt, "unit": "contributions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {nref_sample} of {len(dets)} references (rank order), all "
+                      f"{ref['n_contrib']} of their contributions, {dt:.1f} s",
+            "parity_abs_dE": abs(got["e_pt2"] - ref["e_pt2"]),
+            "parity_counts_equal": all(got[k] == ref[k] for k in
+                                       ("n_contrib", "n_unique", "n_external", "n_in_ref_hit",
+                                        "key_xor", "key_sum"))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cpu-sample", type=int, default=200,
+                    help="reference determinants in the oracle's timed sample (0: skip)")
+    ap.add_argument("--fp32-form", action="store_true",
+                    help="also time the FP32-payload form (outside the timed region)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
+              "(subsets of the hash split are independent, see DESIGN.md for sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_02049_amd as pt2
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w, h, eri, dets, c, e0 = load_workload(args.workload)
+    stream = torch.cuda.current_stream()
+    ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision=args.precision,
+                      stream=stream, allocator="torch", timing=True)
+    d_dets = torch.from_numpy(np.ascontiguousarray(dets).view(np.int64)).cuda()
+    d_c = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+    torch.cuda.synchronize()
+    print(f"bench: workload {args.workload} warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.evaluate(d_dets, d_c, e0)
+
+    torch.cuda.synchronize()
+    lat, results = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        r = ctx.evaluate(d_dets, d_c, e0)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        results.append(r)
+        print(f"bench: step {i} {lat[-1]:.1f} ms E={r['e_pt2']:.12f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    n_contrib = results[0]["n_contrib"]
+    value = n_contrib * args.steps / elapsed
+    es = {r["e_pt2"] for r in results}
+    W = pt2.key_words(w.norb)
+    pb = 8 if args.precision == "fp64" else 4
+    rec = 8 * W + pb
+    passes = sum(r["n_sort_passes"] for r in results)
+    ms_sort = sum(r["ms_sort"] for r in results)
+    n_per_pass = results[0]["n_after_cutoff"]
+    pass_ms = ms_sort / passes
+    bytes_per_pass = 2.0 * rec * n_per_pass
+    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
+    phases = {k: round(sum(r[k] for r in results) / args.steps, 3)
+              for k in ("ms_gen", "ms_hist", "ms_sort", "ms_reduce")}
+
+    # copy kernel of known size, for scaling the HBM traffic counters
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+    extra = {}
+    if args.fp32_form and args.precision == "fp64":
+        ctx32 = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision="fp32",
+                            stream=stream, allocator="torch", timing=True)
+        ctx32.evaluate(d_dets, d_c, e0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r32 = [ctx32.evaluate(d_dets, d_c, e0) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        extra["fp32_form"] = {"value": n_contrib * args.steps / el32, "unit": "contributions/s",
+                              "ms_per_step": el32 / args.steps * 1e3,
+                              "abs_dE_vs_fp64_path": abs(r32[0]["e_pt2"] - results[0]["e_pt2"])}
+        ctx32.close()
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(w, h, eri, dets, c, e0, args.cpu_sample, ctx)
+
+    line = {
+        "metric": "PT2 contributions/s at |dE_PT2| <= 1e-6 Eh vs FP64 oracle; p50/p99 latency",
+        "value": value,
+        "unit": "contributions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-payload/f64-accumulate",
+        "data": "synthetic (seeded integrals and reference, stand-in for molecular inputs)",
+        "config": {"workload": f"{args.workload}: ({w.nalpha}a,{w.nbeta}b) electrons in {w.norb} "
+                               f"orbitals, {len(dets)} reference determinants, {n_contrib} "
+                               f"contributions, one subset",
+                   "precision": args.precision, "key_words": W, "record_bytes": rec},
+        "e_pt2": results[0]["e_pt2"],
+        "deterministic": len(es) == 1,
+        "phases_ms": phases,
+        "sort_passes_per_step": passes // args.steps,
+        "roofline": {"kernel": "onesweep digit pass", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_per_pass,
+                     "avg_launch_ms": pass_ms},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -23,12 +23,13 @@ def hipcc() -> str:
     return p if os.path.exists(p) else "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 4, defines=(), output: str | None = None) -> str:
+    objdir = os.path.join(HERE, "_build" + ("_" + "_".join(d.replace("=", "") for d in defines) if defines else ""))
     os.makedirs(objdir, exist_ok=True)
     common = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-I" + os.path.join(HERE, "..", "include")]
+    common += ["-D" + d for d in defines]
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
@@ -49,13 +50,14 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             print(text)
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = LIB + ".tmp"
+    lib = output or LIB
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -381,7 +381,8 @@ int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *
     }
     Small *ds = ws.dsmall();
     HIPCHK(launch_zero_u32(&ds->flags.err, 2, st));
-    Planes ra = planes_of(ws.refA, W, ws.ref_cap, 8), rb = planes_of(ws.refB, W, ws.ref_cap, 8);
+    // plane stride = n: the generation kernel indexes reference planes by nref
+    Planes ra = planes_of(ws.refA, W, n, 8), rb = planes_of(ws.refB, W, n, 8);
     HIPCHK(launch_refs_split(W, c->norb, c->na, c->nb, dets, coeffs, n, ra, &ds->flags, st));
     Timing none;
     if ((rc = radix_sort(ws, W, 8, ra, rb, n, 2 * c->norb, st, none, nullptr, nullptr)))
@@ -1048,15 +1049,17 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->budget = o.device_budget_bytes ? o.device_budget_bytes : (uint64_t)(0.8 * (double)freeb);
 
     // resident Hamiltonian
-    const size_t n2 = n * n, n4 = n2 * n2, nso = 2 * n;
-    std::vector<double> T(nso * nso, 0.0);
-    for (size_t b1 = 0; b1 < nso; b1++) {
+    const size_t n2 = n * n, n4 = n2 * n2, nso = 2 * n, ntri = nso * (nso + 1) / 2;
+    // packed upper triangle over spin-orbitals b1 <= b2 (row b1 starts at
+    // b1*nso - b1*(b1-1)/2, entry b2 - b1 within it)
+    std::vector<double> T(ntri, 0.0);
+    for (size_t b1 = 0, o = 0; b1 < nso; b1++) {
         const size_t p = b1 < n ? b1 : b1 - n;
-        T[b1 * nso + b1] = h[p * n + p];
+        T[o++] = h[p * n + p];
         for (size_t b2 = b1 + 1; b2 < nso; b2++) {
             const size_t q = b2 < n ? b2 : b2 - n;
             const bool same = (b1 < n) == (b2 < n);
-            T[b1 * nso + b2] = E(p, p, q, q) - (same ? E(p, q, q, p) : 0.0);
+            T[o++] = E(p, p, q, q) - (same ? E(p, q, q, p) : 0.0);
         }
     }
     std::vector<uint64_t> R(nso);
@@ -1065,11 +1068,11 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         R[b] = splitmix_next(st);
     int rc;
     if ((rc = buf_alloc(c->A, c->h, n2 * 8)) || (rc = buf_alloc(c->A, c->V, n4 * 8)) ||
-        (rc = buf_alloc(c->A, c->T, nso * nso * 8)) || (rc = buf_alloc(c->A, c->R, nso * 8)))
+        (rc = buf_alloc(c->A, c->T, ntri * 8)) || (rc = buf_alloc(c->A, c->R, nso * 8)))
         return rc;
     HIPCHK(hipMemcpy(c->h.p, h, n2 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->V.p, eri, n4 * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->T.p, T.data(), nso * nso * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->T.p, T.data(), ntri * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->R.p, R.data(), nso * 8, hipMemcpyHostToDevice));
     if (o.precision == PT2_FP32_PAYLOAD) {
         std::vector<float> h32(n2), V32(n4);

@@ -40,6 +40,9 @@ struct GenLds {
     int8_t *ph[2];      // [spin][occ_idx * v + vir_idx]
     uint16_t *op[2];    // occupied pairs (i | j << 8), i < j, indices into occ
     uint16_t *vp[2];    // virtual pairs, indices into vir
+    // select by a runtime spin without indexing the pointer arrays (which
+    // would force this struct out of registers)
+    __device__ const int8_t *phs(int sp) const { return sp == 0 ? ph[0] : ph[1]; }
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -241,6 +244,13 @@ __device__ inline void flip(uint64_t (&k)[W], int bit)
 
 // Bits flipped by an excitation (spin-orbital indices) -> key and Zobrist hash.
 template <int W>
+__device__ inline void flip_hash(const GenHead *H, uint64_t (&key)[W], uint64_t &z, int bit)
+{
+    flip<W>(key, bit);
+    z ^= H->R[bit];
+}
+
+template <int W>
 __device__ inline void exc_key(const GenLds &g, int norb, const Exc &e, uint64_t (&key)[W], uint64_t &z)
 {
     const GenHead *H = g.head;
@@ -248,29 +258,21 @@ __device__ inline void exc_key(const GenLds &g, int norb, const Exc &e, uint64_t
     for (int w = 0; w < W; w++)
         key[w] = H->key[w];
     z = H->z;
-    int bits[4], nb;
     if (e.kind == 0 || e.kind == 1) {
-        int off = e.kind == 0 ? norb : 0, sp = e.kind;
-        bits[0] = off + H->occ[sp][e.oi];
-        bits[1] = off + H->vir[sp][e.vi];
-        nb = 2;
+        const int off = e.kind == 0 ? norb : 0, sp = e.kind;
+        flip_hash<W>(H, key, z, off + H->occ[sp][e.oi]);
+        flip_hash<W>(H, key, z, off + H->vir[sp][e.vi]);
     } else if (e.kind == 2 || e.kind == 3) {
-        int sp = e.kind - 2, off = sp == 0 ? norb : 0;
-        bits[0] = off + H->occ[sp][e.oi];
-        bits[1] = off + H->occ[sp][e.oj];
-        bits[2] = off + H->vir[sp][e.vi];
-        bits[3] = off + H->vir[sp][e.vj];
-        nb = 4;
+        const int sp = e.kind - 2, off = sp == 0 ? norb : 0;
+        flip_hash<W>(H, key, z, off + H->occ[sp][e.oi]);
+        flip_hash<W>(H, key, z, off + H->occ[sp][e.oj]);
+        flip_hash<W>(H, key, z, off + H->vir[sp][e.vi]);
+        flip_hash<W>(H, key, z, off + H->vir[sp][e.vj]);
     } else {
-        bits[0] = norb + H->occ[0][e.oi];
-        bits[1] = norb + H->vir[0][e.vi];
-        bits[2] = H->occ[1][e.oj];
-        bits[3] = H->vir[1][e.vj];
-        nb = 4;
-    }
-    for (int t = 0; t < nb; t++) {
-        flip<W>(key, bits[t]);
-        z ^= H->R[bits[t]];
+        flip_hash<W>(H, key, z, norb + H->occ[0][e.oi]);
+        flip_hash<W>(H, key, z, norb + H->vir[0][e.vi]);
+        flip_hash<W>(H, key, z, H->occ[1][e.oj]);
+        flip_hash<W>(H, key, z, H->vir[1][e.vj]);
     }
 }
 
@@ -301,15 +303,16 @@ __device__ inline F exc_value(const GenLds &g, const DevSys &s, const ExcLayout 
                     f -= V[eidx(n, r, j, j, a)];
             }
         }
-        return (F)g.ph[sp][e.oi * vcount + e.vi] * f;
+        return (F)g.phs(sp)[e.oi * vcount + e.vi] * f;
     }
     if (e.kind <= 3) {
         int sp = e.kind - 2;
         int vcount = sp == 0 ? L.va : L.vb;
         int r = H->occ[sp][e.oi], q = H->occ[sp][e.oj];
         int a = H->vir[sp][e.vi], b = H->vir[sp][e.vj];
-        int ph1 = g.ph[sp][e.oi * vcount + e.vi];
-        int ph2 = g.ph[sp][e.oj * vcount + e.vj];
+        const int8_t *pt = g.phs(sp);
+        int ph1 = pt[e.oi * vcount + e.vi];
+        int ph2 = pt[e.oj * vcount + e.vj];
         int lo = q < b ? q : b, hi = q < b ? b : q;
         if (r > lo && r < hi)
             ph2 = -ph2;

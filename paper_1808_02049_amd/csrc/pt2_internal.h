@@ -10,13 +10,17 @@ namespace pt2 {
 constexpr int MAXW = 4;        // 2*norb <= 256 bits
 constexpr int MAXORB = 128;
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 16;
+#ifndef PT2_SORT_ITEMS
+#define PT2_SORT_ITEMS 16
+#endif
+constexpr int SORT_ITEMS = PT2_SORT_ITEMS;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // records per onesweep tile
 constexpr int RED_THREADS = 256;
-constexpr int RED_ITEMS = 8;
+constexpr int RED_ITEMS = 4;
 constexpr int RED_TILE = RED_THREADS * RED_ITEMS;     // records per reduce tile
 constexpr int RED_GRID = 4096;                        // fixed -> bit-reproducible sums
-constexpr int RED_LDS_REFS = 256;                     // reference keys staged per tile
+constexpr int RED_LDS_REFS = 64;                      // reference keys staged per tile
+constexpr size_t RED_LDS_TABLE_MAX = 36 * 1024;       // packed diagonal table kept in LDS up to this size
 constexpr int GEN_THREADS = 256;
 
 // Device-side error flags (bitmask in Flags::err).
@@ -41,8 +45,9 @@ struct DevSys {
     const double *V;    // norb^4, (pq|rs) row-major
     const float *h32;   // FP32 copies (precision form), else null
     const float *V32;
-    const double *T;    // (2 norb)^2 spin-orbital pair table for the diagonal:
-                        // T[b][b] = h_pp; T[b1][b2] (b1<b2) = (pp|qq) - [same spin](pq|qp)
+    const double *T;    // packed upper-triangular spin-orbital pair table for the
+                        // diagonal, row b1 at b1*nso - b1*(b1-1)/2 - b1, column b2 >= b1:
+                        // T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin](pq|qp)
     const uint64_t *R;  // Zobrist words, one per bit (2 norb)
 };
 

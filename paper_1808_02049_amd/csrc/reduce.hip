@@ -9,12 +9,15 @@
 // against only the few reference bitstrings that fall inside the tile's key
 // range, staged in LDS: the sorted records and the sorted reference list are
 // merged tile by tile.  H_aa is evaluated from scratch from a spin-orbital pair
-// table, sum over occupied pairs b1 <= b2 of T[b1][b2].
+// table (packed upper triangle, in LDS when it fits), sum over occupied pairs
+// b1 <= b2 of T[b1][b2].
 //
-// A fixed grid of RED_GRID workgroups strides over tiles; each workgroup owns
-// the segments whose first record lies in its tile, follows a segment past
-// the tile end with one wavefront, and keeps a Neumaier-compensated sum.
-// Partials are combined in workgroup order, so the energy is bit-reproducible.
+// A fixed grid of RED_GRID workgroups takes contiguous ranges of tiles; a
+// workgroup owns the segments whose first record lies in its tiles, follows a
+// segment past a tile end with one wavefront, queues the segment ends of a
+// tile in LDS and evaluates them round-robin over its threads, keeping a
+// Neumaier-compensated sum.  Partials are combined in workgroup order, so the
+// energy is bit-reproducible.
 #include "pt2_internal.h"
 
 namespace pt2 {
@@ -94,9 +97,15 @@ __device__ inline uint64_t key_mix(const uint64_t (&k)[W])
     return acc;
 }
 
+// Packed upper-triangular pair table of the spin-orbitals (b1 <= b2): the row
+// of b1 starts at tri_row(b1) and is indexed by b2.
+__host__ __device__ inline int tri_row(int b1, int nso) { return b1 * nso - (b1 * (b1 - 1)) / 2 - b1; }
+
 // H_aa = sum over occupied spin-orbital pairs b1 <= b2 of T[b1][b2]
+// (T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin] (pq|qp)); two
+// independent accumulators per row keep two table reads in flight.
 template <int W>
-__device__ inline double diag_energy(const double *T, int nso, const uint64_t (&k)[W])
+__device__ inline double diag_packed(const double *Tp, int nso, const uint64_t (&k)[W])
 {
     double e = 0.0;
 #pragma unroll
@@ -105,22 +114,34 @@ __device__ inline double diag_energy(const double *T, int nso, const uint64_t (&
         while (m1) {
             const int b1 = w1 * 64 + __builtin_ctzll(m1);
             m1 &= m1 - 1;
-            const double *row = T + (int64_t)b1 * nso;
-            double acc = row[b1];
+            const double *row = Tp + tri_row(b1, nso);
+            double a0 = row[b1], a1 = 0.0;
             uint64_t m2 = m1;
             while (m2) {
-                acc += row[w1 * 64 + __builtin_ctzll(m2)];
+                const int q0 = w1 * 64 + __builtin_ctzll(m2);
                 m2 &= m2 - 1;
+                a0 += row[q0];
+                if (m2) {
+                    const int q1 = w1 * 64 + __builtin_ctzll(m2);
+                    m2 &= m2 - 1;
+                    a1 += row[q1];
+                }
             }
 #pragma unroll
             for (int w2 = w1 + 1; w2 < W; w2++) {
                 uint64_t m3 = k[w2];
                 while (m3) {
-                    acc += row[w2 * 64 + __builtin_ctzll(m3)];
+                    const int q0 = w2 * 64 + __builtin_ctzll(m3);
                     m3 &= m3 - 1;
+                    a0 += row[q0];
+                    if (m3) {
+                        const int q1 = w2 * 64 + __builtin_ctzll(m3);
+                        m3 &= m3 - 1;
+                        a1 += row[q1];
+                    }
                 }
             }
-            e += acc;
+            e += a0 + a1;
         }
     }
     return e;
@@ -155,37 +176,34 @@ struct RefSlice {
     int staged;      // 1 if [lo, hi) is staged in LDS
 };
 
+// One distinct bitstring with its numerator: exclusion test, then the term.
 template <int W>
-__device__ inline void process_segment(const DevSys &s, const Planes &refs, const RefSlice &rs, const uint64_t *s_rk,
-                                       const double *s_rc, double e0, const uint64_t (&k)[W], double num, Acc &a)
+__device__ inline void process_segment(const DevSys &s, const double *Tp, const Planes &refs, const RefSlice &rs,
+                                       const uint64_t *s_rk, const double *s_rc, double e0, const uint64_t (&k)[W],
+                                       double num, Acc &a)
 {
     a.n_unique++;
-    int64_t hit = -1;
     if (rs.staged) {
         int lo = 0, hi = (int)(rs.hi - rs.lo);
         while (lo < hi) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             uint64_t r[W];
 #pragma unroll
             for (int w = 0; w < W; w++)
                 r[w] = s_rk[w * RED_LDS_REFS + mid];
-            int c = key_cmp<W>(r, k);
+            const int c = key_cmp<W>(r, k);
             if (c == 0) {
-                hit = mid;
-                break;
+                a.n_hit++;
+                a.ref_cross += s_rc[mid] * num;
+                return;
             }
             if (c < 0)
                 lo = mid + 1;
             else
                 hi = mid;
         }
-        if (hit >= 0) {
-            a.n_hit++;
-            a.ref_cross += s_rc[hit] * num;
-            return;
-        }
     } else {
-        int64_t i = ref_bound<W>(refs, rs.lo, rs.hi, k, false);
+        const int64_t i = ref_bound<W>(refs, rs.lo, rs.hi, k, false);
         if (i < rs.hi) {
             uint64_t r[W];
             load_key<W>(refs, i, r);
@@ -196,7 +214,7 @@ __device__ inline void process_segment(const DevSys &s, const Planes &refs, cons
             }
         }
     }
-    const double haa = diag_energy<W>(s.T, 2 * s.norb, k);
+    const double haa = diag_packed<W>(Tp, 2 * s.norb, k);
     const double den = e0 - haa;
     a.n_ext++;
     const double ad = fabs(den);
@@ -212,33 +230,97 @@ __device__ inline void process_segment(const DevSys &s, const Planes &refs, cons
     a.ks += m;
 }
 
+// Wavefront scan: first index >= from whose reference key is > k (strict) or
+// >= k (!strict).  All 64 lanes of the wavefront call it with equal arguments.
+template <int W>
+__device__ inline int64_t ref_advance(const Planes &refs, int64_t nref, int64_t from, const uint64_t (&k)[W],
+                                      bool strict)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t cur = from;
+    while (cur < nref) {
+        const int64_t i = cur + lane;
+        bool before = false;
+        if (i < nref) {
+            uint64_t r[W];
+            load_key<W>(refs, i, r);
+            const int c = key_cmp<W>(r, k);
+            before = strict ? c <= 0 : c < 0;
+        }
+        const uint64_t m = __ballot(before);  // a prefix of the lanes: references are sorted
+        if (m == ~0ull) {
+            cur += 64;
+            continue;
+        }
+        cur += __builtin_ctzll(~m);
+        break;
+    }
+    return cur < nref ? cur : nref;
+}
+
+constexpr int RED_Q = RED_TILE + 1;  // segment ends of one tile plus a continuation
+
+// Each workgroup takes a contiguous range of tiles, so the cursor into the
+// sorted reference list only moves forward.
 template <int W, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int64_t n, Planes refs, int64_t nref,
-                                                        double e0, Partial *partials, Flags *flags)
+                                                        double e0, int64_t tiles_per_block, int lds_table,
+                                                        size_t q_bytes, Partial *partials, Flags *flags)
 {
+    extern __shared__ __align__(16) char dyn[];
     __shared__ uint8_t s_f[RED_THREADS];
     __shared__ double s_v[RED_THREADS];
+    __shared__ uint32_t s_cnt[RED_THREADS / 64];
     __shared__ uint64_t s_rk[W * RED_LDS_REFS];
     __shared__ double s_rc[RED_LDS_REFS];
-    __shared__ int64_t s_lo, s_hi;
     __shared__ uint64_t s_ck[W];
     __shared__ double s_cv;
+    __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
 
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int nso = 2 * s.norb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *q_key = (uint64_t *)dyn;                       // [W][RED_Q]
+    double *q_num = (double *)(dyn + (size_t)W * RED_Q * 8); // [RED_Q]
+    const double *Tp = s.T;
+    if (lds_table) {
+        double *t = (double *)(dyn + q_bytes);
+        const int ntri = nso * (nso + 1) / 2;
+        for (int i = tid; i < ntri; i += RED_THREADS)
+            t[i] = s.T[i];
+        Tp = t;
+    }
     Acc a;
     acc_init(a);
 
-    for (int64_t tile = blockIdx.x; tile * RED_TILE < n; tile += gridDim.x) {
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
+    int64_t cursor = 0;
+    if (t_begin < t_end && tid < 64) {
+        uint64_t kf[W];
+        load_key<W>(in, t_begin * RED_TILE, kf);
+        int64_t lo = 0;
+        if (lane == 0)
+            lo = ref_bound<W>(refs, 0, nref, kf, false);
+        cursor = __shfl(lo, 0);
+    }
+
+    for (int64_t tile = t_begin; tile < t_end; tile++) {
         const int64_t base = tile * RED_TILE;
         const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
-        if (tid == 0) {
+        if (tid < 64) {
             uint64_t kf[W], kl[W];
             load_key<W>(in, base, kf);
             load_key<W>(in, tend - 1, kl);
-            s_lo = ref_bound<W>(refs, 0, nref, kf, false);
-            s_hi = ref_bound<W>(refs, s_lo, nref, kl, true);
-            s_cflag = 0;
+            const int64_t lo = ref_advance<W>(refs, nref, cursor, kf, false);
+            const int64_t hi = ref_advance<W>(refs, nref, lo, kl, true);
+            cursor = lo;
+            if (lane == 0) {
+                s_lo = lo;
+                s_hi = hi;
+                s_cflag = 0;
+            }
         }
         __syncthreads();
         RefSlice rs;
@@ -252,7 +334,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 s_rc[i] = ((const double *)refs.pay)[rs.lo + i];
             }
 
-        // my records
         const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
         uint64_t k[RED_ITEMS][W];
         double p[RED_ITEMS];
@@ -317,7 +398,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             }
             __syncthreads();
             if (tid >= o) {
-                // combine (earlier = f2,v2) with (later = current)
                 const uint8_t fc = s_f[tid];
                 const double vc = s_v[tid];
                 s_v[tid] = fc ? vc : v2 + vc;
@@ -327,30 +407,57 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         }
         const bool cf = tid > 0 ? s_f[tid - 1] != 0 : false;
         const double cv = tid > 0 ? s_v[tid - 1] : 0.0;
-        __syncthreads();
 
+        // owned segment ends of this thread go to the queue in record order
+        uint32_t mine = 0;
 #pragma unroll
         for (int j = 0; j < RED_ITEMS; j++) {
             const int64_t idx = r0 + j;
-            if (idx >= tend)
-                continue;
-            const bool owned = hh[j] || cf;
-            if (!owned)
-                continue;
-            const double val = hh[j] ? run[j] : cv + run[j];
-            if (tl[j]) {
-                process_segment<W>(s, refs, rs, s_rk, s_rc, e0, k[j], val, a);
-            } else if (idx == tend - 1) {
-                // the segment continues into the next tile
+            const bool owned = idx < tend && (hh[j] || cf);
+            if (owned && tl[j])
+                mine++;
+            if (owned && !tl[j] && idx == tend - 1) {
+                // the segment continues past the tile end
 #pragma unroll
                 for (int w = 0; w < W; w++)
                     s_ck[w] = k[j][w];
-                s_cv = val;
+                s_cv = hh[j] ? run[j] : cv + run[j];
                 s_cflag = 1;
             }
         }
+        uint32_t x = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o)
+                x += y;
+        }
+        if (lane == 63)
+            s_cnt[wave] = x;
         __syncthreads();
-        if (s_cflag && tid < 64) {
+        uint32_t pre = 0, qtot = 0;
+#pragma unroll
+        for (int w = 0; w < RED_THREADS / 64; w++) {
+            const uint32_t t = s_cnt[w];
+            pre += w < wave ? t : 0u;
+            qtot += t;
+        }
+        uint32_t slot = pre + x - mine;
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            const bool owned = idx < tend && (hh[j] || cf);
+            if (owned && tl[j]) {
+#pragma unroll
+                for (int w = 0; w < W; w++)
+                    q_key[w * RED_Q + slot] = k[j][w];
+                q_num[slot] = hh[j] ? run[j] : cv + run[j];
+                slot++;
+            }
+        }
+        const int cflag = s_cflag;
+        if (cflag && tid < 64) {
+            // wave 0 follows the continuing segment into the following records
             uint64_t ck[W];
 #pragma unroll
             for (int w = 0; w < W; w++)
@@ -369,23 +476,36 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                         v = load_pay<PB>(in, idx);
                 }
                 const uint64_t m = __ballot(eq);
-                // fixed-order tree sum over the wavefront
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1)
                     v += __shfl_down(v, o);
-                total += v;  // lane 0 holds the step sum
+                total += v;  // lane 0 holds the sum of this step
                 if (m != ~0ull)
                     break;
                 pos += 64;
             }
-            if (lane == 0)
-                process_segment<W>(s, refs, rs, s_rk, s_rc, e0, ck, s_cv + total, a);
+            if (lane == 0) {
+#pragma unroll
+                for (int w = 0; w < W; w++)
+                    q_key[w * RED_Q + qtot] = ck[w];
+                q_num[qtot] = s_cv + total;
+            }
+        }
+        __syncthreads();
+        const int qn = (int)qtot + cflag;
+        for (int e = tid; e < qn; e += RED_THREADS) {
+            uint64_t kk[W];
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                kk[w] = q_key[w * RED_Q + e];
+            process_segment<W>(s, Tp, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a);
         }
         __syncthreads();
     }
 
-    // block reduction of the accumulators (fixed tree)
-    __shared__ Partial s_p[RED_THREADS];
+    // block reduction of the accumulators (fixed tree); the queue region is
+    // free now and holds the partials
+    Partial *s_p = (Partial *)dyn;
     Partial me;
     me.e_sum = a.e_sum, me.e_comp = a.e_comp, me.ref_cross = a.ref_cross, me.min_abs_denom = a.min_abs;
     me.n_unique = a.n_unique, me.n_external = a.n_ext, me.n_hit = a.n_hit, me.n_nonneg = a.n_nonneg;
@@ -396,15 +516,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __syncthreads();
     for (int o = RED_THREADS / 2; o >= 1; o >>= 1) {
         if (tid < o) {
-            Partial x = s_p[tid], y = s_p[tid + o];
-            double sum = x.e_sum, comp = x.e_comp + y.e_comp;
+            Partial x2 = s_p[tid], y = s_p[tid + o];
+            double sum = x2.e_sum, comp = x2.e_comp + y.e_comp;
             neumaier(sum, comp, y.e_sum);
-            x.e_sum = sum, x.e_comp = comp;
-            x.ref_cross += y.ref_cross;
-            x.min_abs_denom = y.min_abs_denom < x.min_abs_denom ? y.min_abs_denom : x.min_abs_denom;
-            x.n_unique += y.n_unique, x.n_external += y.n_external, x.n_hit += y.n_hit;
-            x.n_nonneg += y.n_nonneg, x.key_xor ^= y.key_xor, x.key_sum += y.key_sum;
-            s_p[tid] = x;
+            x2.e_sum = sum, x2.e_comp = comp;
+            x2.ref_cross += y.ref_cross;
+            x2.min_abs_denom = y.min_abs_denom < x2.min_abs_denom ? y.min_abs_denom : x2.min_abs_denom;
+            x2.n_unique += y.n_unique, x2.n_external += y.n_external, x2.n_hit += y.n_hit;
+            x2.n_nonneg += y.n_nonneg, x2.key_xor ^= y.key_xor, x2.key_sum += y.key_sum;
+            s_p[tid] = x2;
         }
         __syncthreads();
     }
@@ -497,8 +617,20 @@ __global__ void k_numerators(Planes in, int64_t n, Planes refs, int64_t nref, ui
 hipError_t launch_reduce(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &refs, int64_t nref,
                          double e0, Partial *partials, Flags *flags, hipStream_t st)
 {
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
+    const int nso = 2 * s.norb;
+    const size_t tri_bytes = (size_t)nso * (nso + 1) / 2 * 8;
+    const int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
+    size_t q_bytes = (size_t)(s.W + 1) * RED_Q * 8;
+    if (q_bytes < sizeof(Partial) * RED_THREADS)
+        q_bytes = sizeof(Partial) * RED_THREADS;
+    q_bytes = (q_bytes + 15) & ~(size_t)15;
+    const size_t dyn = q_bytes + (lds_table ? tri_bytes : 0);
     dim3 g(RED_GRID), b(RED_THREADS);
-#define RD(WW, PB) hipLaunchKernelGGL((k_reduce<WW, PB>), g, b, 0, st, s, sorted, n, refs, nref, e0, partials, flags)
+#define RD(WW, PB) \
+    hipLaunchKernelGGL((k_reduce<WW, PB>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, q_bytes, \
+                       partials, flags)
     switch (s.W * 2 + (fp32 ? 0 : 1)) {
     case 2: RD(1, 4); break;
     case 3: RD(1, 8); break;

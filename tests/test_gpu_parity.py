@@ -203,6 +203,22 @@ def test_random_systems_all_widths(pt2, norb, na, nb, nref, log2p):
     ctx.close()
 
 
+def test_workspace_reuse_with_smaller_reference(pt2):
+    """A context that evaluated a larger reference evaluates a smaller one
+    (multi-word keys) correctly: buffers are reused with the right strides."""
+    norb, na, nb = 40, 4, 4
+    h, eri, _ = synth.make_integrals(norb, 6, 4040)
+    dets = synth.random_determinants(norb, na, nb, 30, 4040)
+    c = np.random.default_rng(4).normal(size=30)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    e0 = float(O.diag(dets).min()) - 2.0
+    ctx = pt2.Context(h, eri, norb, na, nb)
+    for m in (30, 7, 19, 1):
+        ref, _ = O.pt2(dets[:m], c[:m], e0)
+        assert_matches(ctx.evaluate(dets[:m], c[:m], e0), ref)
+    ctx.close()
+
+
 def test_full_fci_reference_gives_zero(pt2):
     norb, na, nb = 7, 3, 2
     h, eri, _ = synth.make_integrals(norb, 6, 5)
