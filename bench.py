@@ -27,6 +27,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS_MD = os.path.join(ROOT, "profiles", "onesweep_c2_fp64_hbm_counters.md")
+SORT_SRC = os.path.join(ROOT, "paper_1808_02049_amd", "csrc", "sort.hip")
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per digit pass from the committed rocprofv3 counter summary,
+    or None if the sort kernel source changed since those counters were taken
+    (or the summary covers another workload)."""
+    import hashlib
+    import re
+    if workload != "c2" or precision != "fp64" or not os.path.exists(COUNTERS_MD):
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\S+) .*source_sha256_16=([0-9a-f]+)", open(COUNTERS_MD).read())
+    if not m:
+        return None
+    cur = hashlib.sha256(open(SORT_SRC, "rb").read()).hexdigest()[:16]
+    return float(m.group(1)) if cur == m.group(2) else None
 
 
 def load_workload(name):
@@ -174,7 +191,8 @@ def main():
         "sort_passes_per_step": passes // args.steps,
         "roofline": {"kernel": "onesweep digit pass", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": bytes_per_pass,
+                     "traffic": measured_traffic(args.workload, args.precision),
+                     "bytes_per_launch": bytes_per_pass,
                      "avg_launch_ms": pass_ms},
         "cpu_baseline": cpu,
     }

@@ -147,6 +147,89 @@ __device__ inline double diag_packed(const double *Tp, int nso, const uint64_t (
     return e;
 }
 
+__device__ inline double tri_at(const double *Tp, int nso, int b1, int b2)
+{
+    const int lo = b1 < b2 ? b1 : b2, hi = b1 < b2 ? b2 : b1;
+    return Tp[tri_row(lo, nso) + hi];
+}
+
+// H_aa relative to an anchor determinant S0 with known energy E0 and
+// g_x = h_x + sum_{c in S0, c != x} T[x][c]: with R the spin-orbitals removed
+// from S0 and A those added,
+//   H = E0 - sum_R g_r + sum_A g_a + sum_{r<r' in R} T + sum_{a<a' in A} T
+//       - sum_{a in A, r in R} T[a][r].
+// Falls back to the from-scratch sum when the difference is large.
+template <int W>
+__device__ inline double diag_anchor(const double *Tp, int nso, int nel, const uint64_t (&k)[W],
+                                     const uint64_t *anc, const double *g, double e_anc)
+{
+    uint64_t rm[W], ad[W];
+    int m = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        const uint64_t d = k[w] ^ anc[w];
+        rm[w] = d & anc[w];
+        ad[w] = d & k[w];
+        m += __popcll(ad[w]);
+    }
+    if (2 * m * m + m >= (nel * nel) / 2)
+        return diag_packed<W>(Tp, nso, k);
+    double e = e_anc, pr = 0.0;
+#pragma unroll
+    for (int w1 = 0; w1 < W; w1++) {
+        uint64_t x = rm[w1];
+        while (x) {
+            const int r = w1 * 64 + __builtin_ctzll(x);
+            x &= x - 1;
+            e -= g[r];
+            uint64_t y = x;  // r < r' within R
+            while (y) {
+                pr += tri_at(Tp, nso, r, w1 * 64 + __builtin_ctzll(y));
+                y &= y - 1;
+            }
+#pragma unroll
+            for (int w2 = w1 + 1; w2 < W; w2++) {
+                uint64_t z = rm[w2];
+                while (z) {
+                    pr += tri_at(Tp, nso, r, w2 * 64 + __builtin_ctzll(z));
+                    z &= z - 1;
+                }
+            }
+#pragma unroll
+            for (int w2 = 0; w2 < W; w2++) {
+                uint64_t z = ad[w2];  // cross pairs with A
+                while (z) {
+                    pr -= tri_at(Tp, nso, r, w2 * 64 + __builtin_ctzll(z));
+                    z &= z - 1;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int w1 = 0; w1 < W; w1++) {
+        uint64_t x = ad[w1];
+        while (x) {
+            const int a = w1 * 64 + __builtin_ctzll(x);
+            x &= x - 1;
+            e += g[a];
+            uint64_t y = x;
+            while (y) {
+                pr += tri_at(Tp, nso, a, w1 * 64 + __builtin_ctzll(y));
+                y &= y - 1;
+            }
+#pragma unroll
+            for (int w2 = w1 + 1; w2 < W; w2++) {
+                uint64_t z = ad[w2];
+                while (z) {
+                    pr += tri_at(Tp, nso, a, w2 * 64 + __builtin_ctzll(z));
+                    z &= z - 1;
+                }
+            }
+        }
+    }
+    return e + pr;
+}
+
 __device__ inline void neumaier(double &sum, double &comp, double x)
 {
     double t = sum + x;
@@ -177,10 +260,16 @@ struct RefSlice {
 };
 
 // One distinct bitstring with its numerator: exclusion test, then the term.
+struct Anchor {
+    const uint64_t *key;  // LDS, W words
+    const double *g;      // LDS, nso entries
+    double e;
+};
+
 template <int W>
-__device__ inline void process_segment(const DevSys &s, const double *Tp, const Planes &refs, const RefSlice &rs,
-                                       const uint64_t *s_rk, const double *s_rc, double e0, const uint64_t (&k)[W],
-                                       double num, Acc &a)
+__device__ inline void process_segment(const DevSys &s, const double *Tp, const Anchor &an, const Planes &refs,
+                                       const RefSlice &rs, const uint64_t *s_rk, const double *s_rc, double e0,
+                                       const uint64_t (&k)[W], double num, Acc &a)
 {
     a.n_unique++;
     if (rs.staged) {
@@ -214,7 +303,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
             }
         }
     }
-    const double haa = diag_packed<W>(Tp, 2 * s.norb, k);
+    const double haa = diag_anchor<W>(Tp, 2 * s.norb, s.na + s.nb, k, an.key, an.g, an.e);
     const double den = e0 - haa;
     a.n_ext++;
     const double ad = fabs(den);
@@ -277,6 +366,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ double s_cv;
     __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
+    __shared__ uint64_t s_anc[W];
+    __shared__ double s_g[2 * MAXORB];
+    __shared__ double s_er[RED_THREADS / 64];
 
     const int nso = 2 * s.norb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -320,9 +412,44 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 s_lo = lo;
                 s_hi = hi;
                 s_cflag = 0;
+#pragma unroll
+                for (int w = 0; w < W; w++)
+                    s_anc[w] = kf[w];
             }
         }
         __syncthreads();
+        // anchor of this tile = its first record: g_x for every spin-orbital x
+        // and the anchor's own energy as a sum of per-row partials
+        {
+            double gx = 0.0, rowx = 0.0;
+            if (tid < nso) {
+                const int bx = tid;
+                const bool occ = (s_anc[bx >> 6] >> (bx & 63)) & 1ull;
+                const double hx = Tp[tri_row(bx, nso) + bx];
+                gx = hx;
+                rowx = occ ? hx : 0.0;
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    uint64_t m = s_anc[w];
+                    while (m) {
+                        const int c = w * 64 + __builtin_ctzll(m);
+                        m &= m - 1;
+                        if (c == bx)
+                            continue;
+                        const double t = tri_at(Tp, nso, bx, c);
+                        gx += t;
+                        if (occ && c > bx)
+                            rowx += t;
+                    }
+                }
+                s_g[bx] = gx;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+                rowx += __shfl_down(rowx, o);
+            if (lane == 0)
+                s_er[wave] = rowx;
+        }
         RefSlice rs;
         rs.lo = s_lo, rs.hi = s_hi;
         rs.staged = (rs.hi - rs.lo) <= RED_LDS_REFS;
@@ -493,12 +620,19 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         }
         __syncthreads();
         const int qn = (int)qtot + cflag;
+        Anchor an;
+        an.key = s_anc;
+        an.g = s_g;
+        an.e = 0.0;
+#pragma unroll
+        for (int w = 0; w < RED_THREADS / 64; w++)
+            an.e += s_er[w];
         for (int e = tid; e < qn; e += RED_THREADS) {
             uint64_t kk[W];
 #pragma unroll
             for (int w = 0; w < W; w++)
                 kk[w] = q_key[w * RED_Q + e];
-            process_segment<W>(s, Tp, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a);
+            process_segment<W>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a);
         }
         __syncthreads();
     }

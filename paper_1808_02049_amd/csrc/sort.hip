@@ -20,6 +20,7 @@ constexpr uint64_t ST_AGG = 1ull << 62;
 constexpr uint64_t ST_INC = 2ull << 62;
 constexpr uint64_t ST_VAL = (1ull << 46) - 1;
 constexpr uint32_t SPIN_MAX = 1u << 24;
+constexpr int LB_WIN = 16;  // predecessors examined per look-back step
 
 __device__ inline uint64_t st_pack(uint64_t flag, uint32_t epoch, uint64_t v)
 {
@@ -218,23 +219,39 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out
         s_tstart[d] = block_excl_scan256(tot, s_sc, tile_total);
         int64_t excl = 0;
         if (tile > 0) {
+            // windowed look-back: LB_WIN predecessors' status words are read at
+            // once; AGG values are summed newest to oldest until an INC is found
             int64_t p = (int64_t)tile - 1;
             uint32_t spins = 0;
-            while (true) {
+            bool done = false;
+            while (!done) {
+                uint64_t v[LB_WIN];
+#pragma unroll
+                for (int i = 0; i < LB_WIN; i++)
+                    v[i] = p - i >= 0 ? ld_agent(status + (p - i) * 256 + d) : 0ull;
+                int used = 0;
+#pragma unroll
+                for (int i = 0; i < LB_WIN; i++) {
+                    if (done || used != i)
+                        continue;
+                    const uint64_t flag = v[i] & (3ull << 62);
+                    const uint32_t ep = (uint32_t)(v[i] >> 46) & 0xFFFFu;
+                    if (flag == 0 || ep != (epoch & 0xFFFFu))
+                        continue;  // not yet published: stop consuming here
+                    excl += (int64_t)(v[i] & ST_VAL);
+                    used = i + 1;
+                    if (flag == ST_INC)
+                        done = true;
+                }
+                if (done)
+                    break;
+                p -= used;
                 if (p < 0) {
                     atomicOr(&flags->err, ERR_LOOKBACK);
                     s_fail = 1;
                     break;
                 }
-                const uint64_t v = ld_agent(status + p * 256 + d);
-                const uint64_t flag = v & (3ull << 62);
-                const uint32_t ep = (uint32_t)(v >> 46) & 0xFFFFu;
-                if (flag != 0 && ep == (epoch & 0xFFFFu)) {
-                    excl += (int64_t)(v & ST_VAL);
-                    if (flag == ST_INC)
-                        break;
-                    p--;
-                } else {
+                if (used == 0) {
                     if (++spins > SPIN_MAX) {
                         atomicOr(&flags->err, ERR_LOOKBACK);
                         s_fail = 1;
