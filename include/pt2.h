@@ -98,7 +98,7 @@ typedef struct {
     uint64_t n_external;      /* distinct bitstrings outside the reference           */
     uint64_t n_in_ref_hit;    /* distinct bitstrings found in the reference          */
     uint32_t n_partitions;    /* subsets evaluated                                   */
-    uint32_t n_sort_passes;   /* 8-bit digit passes launched, all subsets            */
+    uint32_t n_sort_passes;   /* 8-bit digit passes run, all subsets                 */
     double min_abs_denom;     /* min |E0 - H_aa| over external bitstrings            */
     uint64_t n_nonneg_denom;  /* external bitstrings with E0 - H_aa >= 0             */
     double ref_cross;         /* sum over reference hits of c_i * N_i                */
@@ -106,11 +106,15 @@ typedef struct {
     uint64_t key_sum;         /* sum (mod 2^64) of the same mix                      */
     double ms_total;          /* wall time of the call (host clock)                  */
     double ms_gen;            /* device time (timing != 0): generation kernels       */
-    double ms_sort;           /*   onesweep digit passes only                        */
+    double ms_sort;           /*   radix digit passes (count, scan, scatter)         */
+    double ms_sort_scatter;   /*   of which the rank-and-scatter kernels             */
     double ms_reduce;         /*   single pass and final sum                         */
     double ms_hist;           /*   digit histograms, count pass, reference sort      */
-    double ms_sort_pass_max;  /*   slowest single digit pass                         */
-    double bytes_gen, bytes_sort, bytes_reduce; /* algorithmic bytes per phase       */
+    double ms_sort_pass_max;  /*   slowest single scatter kernel                     */
+    double bytes_gen, bytes_sort, bytes_reduce; /* algorithmic bytes per phase (a
+                                 digit pass: every record read and written once by
+                                 the scatter, the digit's key plane read once by
+                                 the count)                                          */
 } pt2_result;
 
 /* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */

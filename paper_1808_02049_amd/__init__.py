@@ -55,7 +55,7 @@ class Result(C.Structure):
                 ("min_abs_denom", C.c_double), ("n_nonneg_denom", C.c_uint64),
                 ("ref_cross", C.c_double), ("key_xor", C.c_uint64), ("key_sum", C.c_uint64),
                 ("ms_total", C.c_double), ("ms_gen", C.c_double), ("ms_sort", C.c_double),
-                ("ms_reduce", C.c_double), ("ms_hist", C.c_double),
+                ("ms_sort_scatter", C.c_double), ("ms_reduce", C.c_double), ("ms_hist", C.c_double),
                 ("ms_sort_pass_max", C.c_double), ("bytes_gen", C.c_double),
                 ("bytes_sort", C.c_double), ("bytes_reduce", C.c_double)]
 

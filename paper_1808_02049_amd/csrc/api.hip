@@ -8,7 +8,7 @@
 //      must fit the device budget; a count pass (the work list of Section V)
 //      gives each subset's exact size when the split has more than one subset
 //      or a cutoff drops terms;
-//   3. per subset: generation -> LSD onesweep radix sort -> single pass;
+//   3. per subset: generation -> LSD radix sort -> single pass;
 //   4. sums the subsets in index order.
 // The serving form queues requests from any context into one scheduler whose
 // worker threads each own a stream and a workspace; a request starts when a
@@ -114,9 +114,12 @@ int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
 void buf_free(const Alloc &A, Buf &b)
 {
     if (b.p) {
-        if (A.ff)
+        if (A.ff) {
+            // an external allocator may hand the block out at once: let every
+            // queued kernel that might still use it finish first
+            (void)hipDeviceSynchronize();
             A.ff(b.p, b.bytes, A.user);
-        else
+        } else
             (void)hipFree(b.p);
     }
     b.p = nullptr;
@@ -156,9 +159,8 @@ struct Workspace {
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0;
-    Buf status;              // look-back status words
-    int64_t status_tiles = 0;
-    uint32_t epoch = 0;
+    Buf counts, csum, coff, offs;  // per-tile digit counts and scanned offsets
+    int64_t scan_tiles = 0;
     Buf small;
     Buf cnt, off, tot, parts_dev;
     Small *host_small = nullptr;  // pinned mirror
@@ -170,9 +172,10 @@ struct Workspace {
     void release()
     {
         buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB);
-        buf_free(A, recA), buf_free(A, recB), buf_free(A, status), buf_free(A, small);
+        buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
+        buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
-        ref_cap = rec_cap = status_tiles = 0;
+        ref_cap = rec_cap = scan_tiles = 0;
         if (host_small) {
             (void)hipHostFree(host_small);
             host_small = nullptr;
@@ -182,7 +185,7 @@ struct Workspace {
         evpool.clear();
     }
 
-    size_t record_bytes() const { return recA.bytes + recB.bytes + status.bytes; }
+    size_t record_bytes() const { return recA.bytes + recB.bytes + counts.bytes + offs.bytes; }
 
     Small *dsmall() { return (Small *)small.p; }
 
@@ -237,7 +240,7 @@ struct Timing {
     bool on = false;
     struct Ev {
         hipEvent_t a, b;
-        int kind;  // 0 gen, 1 sort pass, 2 reduce, 3 hist/other
+        int kind;  // 0 gen, 1 radix scatter, 2 reduce, 3 hist/other, 4 radix count+scan
     };
     std::vector<Ev> evs;
 };
@@ -279,31 +282,24 @@ int ensure_small(Workspace &ws)
     return PT2_OK;
 }
 
-int ensure_status(Workspace &ws, int64_t n, hipStream_t st)
+int ensure_scan(Workspace &ws, int64_t n)
 {
     int64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
     if (tiles < 1)
         tiles = 1;
-    if (ws.status_tiles < tiles) {
-        buf_free(ws.A, ws.status);
-        int rc = buf_alloc(ws.A, ws.status, (size_t)tiles * 256 * 8);
-        if (rc)
+    if (ws.scan_tiles < tiles) {
+        buf_free(ws.A, ws.counts), buf_free(ws.A, ws.csum), buf_free(ws.A, ws.coff), buf_free(ws.A, ws.offs);
+        ws.scan_tiles = 0;
+        const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        int rc;
+        if ((rc = buf_alloc(ws.A, ws.counts, (size_t)tiles * 256 * 4)) ||
+            (rc = buf_alloc(ws.A, ws.offs, (size_t)tiles * 256 * 8)) ||
+            (rc = buf_alloc(ws.A, ws.csum, (size_t)chunks * 256 * 8)) ||
+            (rc = buf_alloc(ws.A, ws.coff, (size_t)chunks * 256 * 8)))
             return rc;
-        ws.status_tiles = tiles;
-        HIPCHK(launch_zero_u64((uint64_t *)ws.status.p, tiles * 256, st));
-        ws.epoch = 0;
+        ws.scan_tiles = tiles;
     }
     return PT2_OK;
-}
-
-uint32_t next_epoch(Workspace &ws, hipStream_t st)
-{
-    ws.epoch++;
-    if (ws.epoch >= 0xFFFFu) {
-        (void)launch_zero_u64((uint64_t *)ws.status.p, ws.status_tiles * 256, st);
-        ws.epoch = 1;
-    }
-    return ws.epoch;
 }
 
 // Stable LSD sort of n records held in *src (ping-pong with *dst) on key bits
@@ -316,7 +312,7 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
     const int ndig = (nbits + 7) / 8;
     if (ndig > MAX_DIG)
         return fail(PT2_E_INVALID, "key too long");
-    int rc = ensure_status(ws, n, st);
+    int rc = ensure_scan(ws, n);
     if (rc)
         return rc;
     Small *ds = ws.dsmall();
@@ -339,18 +335,24 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
                 trivial = true;
         if (trivial)
             continue;
-        const uint32_t ep = next_epoch(ws, st);
-        if ((rc = timed_begin(ws, tm, st, a)))
+        hipEvent_t pa, mid = nullptr;
+        if ((rc = timed_begin(ws, tm, st, pa)))
             return rc;
-        HIPCHK(launch_onesweep(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint64_t *)ws.status.p,
-                               ds->tile_ctr + (d % MAX_PASS_CTR), ep, &ds->flags, st));
-        if ((rc = timed_end(ws, tm, st, a, 1)))
-            return rc;
+        if (tm.on && !(mid = ws.event()))
+            return fail(PT2_E_DEVICE, "hipEventCreate failed");
+        HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint32_t *)ws.counts.p,
+                                 (uint64_t *)ws.csum.p, (uint64_t *)ws.coff.p, (uint64_t *)ws.offs.p, &ds->flags,
+                                 st, mid));
+        if (tm.on) {
+            if ((rc = timed_end(ws, tm, st, mid, 1)))
+                return rc;
+            tm.evs.push_back({pa, mid, 4});
+        }
         std::swap(src, dst);
         if (passes_out)
             (*passes_out)++;
         if (bytes_out)
-            *bytes_out += 2.0 * (double)n * (8.0 * W + pb);
+            *bytes_out += 2.0 * (double)n * (8.0 * W + pb) + 8.0 * (double)n;
     }
     return PT2_OK;
 }
@@ -398,8 +400,8 @@ int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *
         return fail(PT2_E_INVALID, "a reference determinant has bits at or above 2*norb");
     if (err & ERR_DUPLICATE)
         return fail(PT2_E_INVALID, "duplicate reference determinants");
-    if (err & ERR_LOOKBACK)
-        return fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+    if (err & ERR_BOUNDS)
+        return fail(PT2_E_DEVICE, "radix scatter destination out of range");
     refs = ra;
     (void)tm;
     return PT2_OK;
@@ -422,7 +424,12 @@ int ensure_records(Workspace &ws, int W, int pb, int64_t cap)
 }
 
 // projected device bytes for one subset of n records
-double subset_bytes(int W, int pb, double n) { return n * (2.0 * (8.0 * W + pb) + 0.5) + 4096.0 * 16; }
+// (two record buffers, plus per-tile counts and offsets: 12 B per digit value
+// per tile of SORT_TILE records)
+double subset_bytes(int W, int pb, double n)
+{
+    return n * (2.0 * (8.0 * W + pb) + 12.0 * 256.0 / SORT_TILE) + 65536.0;
+}
 
 struct Plan {
     int log2p = 0;
@@ -698,8 +705,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     HIPCHK(hipMemcpyAsync(&ws.host_small->flags, &ds->flags, sizeof(Flags), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const uint32_t err = ws.host_small->flags.err;
-    if (err & ERR_LOOKBACK)
-        return fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+    if (err & ERR_BOUNDS)
+        return fail(PT2_E_DEVICE, "radix scatter destination out of range");
     if (err & ERR_OVERFLOW)
         return fail(PT2_E_DEVICE, "compacted generation exceeded its planned range");
     // combine subsets in index order
@@ -733,8 +740,11 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             res.ms_gen += ms;
         else if (e.kind == 1) {
             res.ms_sort += ms;
+            res.ms_sort_scatter += ms;
             res.ms_sort_pass_max = std::max(res.ms_sort_pass_max, (double)ms);
-        } else if (e.kind == 2)
+        } else if (e.kind == 4)
+            res.ms_sort += ms;
+        else if (e.kind == 2)
             res.ms_reduce += ms;
         else
             res.ms_hist += ms;
@@ -1289,8 +1299,8 @@ PT2_API int pt2_sort_records(int device, int W, int key_bits, uint64_t *keys, vo
         if (hipStreamSynchronize(st) != hipSuccess ||
             hipMemcpy(&f, &ws.dsmall()->flags, sizeof f, hipMemcpyDeviceToHost) != hipSuccess)
             rc = fail(PT2_E_DEVICE, "sort failed");
-        else if (f.err & ERR_LOOKBACK)
-            rc = fail(PT2_E_DEVICE, "radix sort look-back bound exceeded");
+        else if (f.err & ERR_BOUNDS)
+            rc = fail(PT2_E_DEVICE, "radix scatter destination out of range");
     }
     if (!rc) {
         for (int w = 0; w < W; w++)

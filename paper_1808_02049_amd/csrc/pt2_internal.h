@@ -11,10 +11,11 @@ constexpr int MAXW = 4;        // 2*norb <= 256 bits
 constexpr int MAXORB = 128;
 constexpr int SORT_THREADS = 256;
 #ifndef PT2_SORT_ITEMS
-#define PT2_SORT_ITEMS 16
+#define PT2_SORT_ITEMS 8
 #endif
 constexpr int SORT_ITEMS = PT2_SORT_ITEMS;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // records per onesweep tile
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // records per radix tile
+constexpr int SCAN_CHUNK = 256;                        // tiles per chunk of the offset scan
 constexpr int RED_THREADS = 256;
 constexpr int RED_ITEMS = 4;
 constexpr int RED_TILE = RED_THREADS * RED_ITEMS;     // records per reduce tile
@@ -28,7 +29,7 @@ enum : uint32_t {
     ERR_POPCOUNT = 1u,      // a reference has the wrong electron count
     ERR_STRAY_BITS = 2u,    // bits at or above 2*norb
     ERR_DUPLICATE = 4u,     // two equal reference determinants
-    ERR_LOOKBACK = 8u,      // a look-back wait exceeded its bound
+    ERR_BOUNDS = 8u,        // a radix scatter destination fell outside the buffer
     ERR_SINGULAR = 16u,     // E0 - H_aa == 0 for an external determinant
     ERR_OVERFLOW = 32u      // a compacted write ran past its planned range
 };
@@ -139,10 +140,13 @@ hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, con
 hipError_t launch_hist(int W, const Planes &in, int64_t n, int ndig, uint64_t *hist, hipStream_t st);
 // bucket[d*256 + v] = exclusive scan of hist[d][*].
 hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hipStream_t st);
-// One stable LSD digit pass (onesweep): scatter in -> out by digit `dig`.
-hipError_t launch_onesweep(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n,
-                           int dig, const uint64_t *bucket, uint64_t *status, uint32_t *tile_ctr,
-                           uint32_t epoch, Flags *flags, hipStream_t st);
+// One stable LSD digit pass: per-tile counts, offset scan, rank and scatter
+// (in -> out by digit `dig`).  counts: ntiles*256 u32; csum, coff:
+// nchunks*256 u64; offs: ntiles*256 u64.  `mid` (optional) is recorded between
+// the counting/scan kernels and the scatter.
+hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
+                             const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
+                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t st);
 // AoS dets + coeffs -> SoA planes, with input checks.

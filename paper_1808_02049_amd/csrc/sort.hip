@@ -3,39 +3,25 @@
 // library, Section V).  Records are structure-of-arrays: W uint64 key planes
 // and one payload plane (FP64 or FP32 bits).
 //
-// Each 8-bit digit is one "onesweep" pass (Adinets and Merrill, 2022): a tile
-// of SORT_TILE records takes its tile index from an atomic counter, ranks its
-// records by digit inside the tile with wavefront ballots, publishes its
-// per-digit counts, and resolves its global offsets by decoupled look-back
-// over the tiles before it.  Records are then staged through LDS in digit
-// order so that each plane is written in runs of consecutive addresses.
+// Each 8-bit digit is one pass of three steps (reduce-then-scan):
+//   1. k_tile_count: every tile of SORT_TILE records counts its digits (one
+//      read of the plane holding the digit, LDS histograms per wavefront);
+//   2. k_chunk_sum / k_chunk_scan / k_tile_offsets: exclusive scan of the
+//      counts over tiles, per digit value, added to the digit's bucket start;
+//   3. k_scatter: every tile ranks its records by digit with wavefront
+//      ballots (stable), stages each plane through LDS in digit order and
+//      writes it out in runs of consecutive addresses.
+// Tiles never wait for each other.  (A single-kernel "onesweep" pass with
+// decoupled look-back was measured slower on MI355X: its status words must be
+// read coherently across the eight XCDs' L2 caches, and the look-back took
+// about 40% of the pass.)
 // Digit histograms of all positions are computed up front in one read of the
-// key planes; a digit whose histogram has a single nonzero bin is skipped.
+// key planes; they give the bucket starts, and a digit whose histogram has a
+// single nonzero bin is skipped.
 #include "pt2_internal.h"
 
 namespace pt2 {
 namespace {
-
-constexpr uint64_t ST_AGG = 1ull << 62;
-constexpr uint64_t ST_INC = 2ull << 62;
-constexpr uint64_t ST_VAL = (1ull << 46) - 1;
-constexpr uint32_t SPIN_MAX = 1u << 24;
-constexpr int LB_WIN = 16;  // predecessors examined per look-back step
-
-__device__ inline uint64_t st_pack(uint64_t flag, uint32_t epoch, uint64_t v)
-{
-    return flag | ((uint64_t)(epoch & 0xFFFFu) << 46) | (v & ST_VAL);
-}
-
-__device__ inline uint64_t ld_agent(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline void st_agent(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 template <int W>
 __device__ inline const uint64_t *plane_c(const Planes &p, int w)
@@ -143,34 +129,119 @@ __global__ __launch_bounds__(256) void k_hist_scan(const unsigned long long *his
 }
 
 // ---------------------------------------------------------------------------
-// One onesweep digit pass.
-template <int W, int PB>
-__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out, int64_t n, int dig,
-                                                           const uint64_t *bucket, uint64_t *status,
-                                                           uint32_t *tile_ctr, uint32_t epoch, Flags *flags)
+// Step 1: digit counts of every tile (counts[tile * 256 + digit]).  Each
+// thread reads SORT_ITEMS consecutive records, merges runs of equal digits,
+// and adds them to its wavefront's LDS histogram.
+template <int W>
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t n, int dig, uint32_t *counts)
 {
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t h[SORT_THREADS / 64][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < (SORT_THREADS / 64) * 256; i += SORT_THREADS)
+        (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int word = dig >> 3, shift = (dig & 7) * 8;
+    const uint64_t *src = plane_c<W>(in, word);
+    const int64_t r0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)tid * SORT_ITEMS;
+    uint64_t v[SORT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; j++)
+        v[j] = r0 + j < n ? src[r0 + j] : 0ull;
+    uint32_t last = 0xFFFFFFFFu, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; j++) {
+        if (r0 + j < n) {
+            const uint32_t d = (uint32_t)(v[j] >> shift) & 255u;
+            if (d == last) {
+                cnt++;
+            } else {
+                if (cnt)
+                    atomicAdd(&h[wave][last], cnt);
+                last = d;
+                cnt = 1;
+            }
+        }
+    }
+    if (cnt)
+        atomicAdd(&h[wave][last], cnt);
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < SORT_THREADS / 64; w++)
+        t += h[w][tid];
+    counts[(int64_t)blockIdx.x * 256 + tid] = t;
+}
+
+// Step 2a: per chunk of SCAN_CHUNK tiles, the sum of each digit's counts.
+__global__ __launch_bounds__(256) void k_chunk_sum(const uint32_t *counts, int64_t ntiles, uint64_t *csum)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
+    uint64_t acc = 0;
+    for (int64_t t = t0; t < t1; t++)
+        acc += counts[t * 256 + threadIdx.x];
+    csum[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// Step 2b: exclusive scan of the chunk sums per digit, starting at the
+// digit's bucket start.
+__global__ __launch_bounds__(256) void k_chunk_scan(const uint64_t *csum, int64_t nchunks, const uint64_t *bucket,
+                                                    uint64_t *coff)
+{
+    uint64_t run = bucket[threadIdx.x];
+    int64_t c = 0;
+    for (; c + 8 <= nchunks; c += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            x[i] = csum[(c + i) * 256 + threadIdx.x];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            coff[(c + i) * 256 + threadIdx.x] = run;
+            run += x[i];
+        }
+    }
+    for (; c < nchunks; c++) {
+        const uint64_t x = csum[c * 256 + threadIdx.x];
+        coff[c * 256 + threadIdx.x] = run;
+        run += x;
+    }
+}
+
+// Step 2c: output offset of each tile's first record of each digit.
+__global__ __launch_bounds__(256) void k_tile_offsets(const uint32_t *counts, int64_t ntiles, const uint64_t *coff,
+                                                      uint64_t *offs)
+{
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
+    const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
+    uint64_t run = coff[(int64_t)blockIdx.x * 256 + threadIdx.x];
+    for (int64_t t = t0; t < t1; t++) {
+        offs[t * 256 + threadIdx.x] = run;
+        run += counts[t * 256 + threadIdx.x];
+    }
+}
+
+// Step 3: rank and scatter one tile.
+template <int W, int PB>
+__global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out, int64_t n, int dig,
+                                                          const uint64_t *offs, Flags *flags)
+{
     __shared__ uint32_t s_wc[4][256];
     __shared__ uint32_t s_tstart[256];
     __shared__ int64_t s_gbase[256];
     __shared__ uint32_t s_sc[4];
     __shared__ uint64_t s_stage[SORT_TILE];
     __shared__ uint8_t s_dig[SORT_TILE];
-    __shared__ int s_fail;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (tid == 0) {
-        s_tile = atomicAdd(tile_ctr, 1u);
-        s_fail = 0;
-    }
     for (int i = tid; i < 4 * 256; i += SORT_THREADS)
         (&s_wc[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * SORT_TILE;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * SORT_TILE;
     const int word = dig >> 3, shift = (dig & 7) * 8;
     const uint64_t *src = plane_c<W>(in, word);
+    const uint64_t my_off = offs[tile * 256 + tid];
 
     uint64_t kw[SORT_ITEMS];
     uint32_t rank[SORT_ITEMS];
@@ -179,7 +250,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out
         const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
         kw[j] = idx < n ? src[idx] : 0ull;
     }
-    // rank within the wave: peers = lanes with the same digit
+    __syncthreads();
+    // rank within the wave: peers = lanes with the same digit (stable)
 #pragma unroll
     for (int j = 0; j < SORT_ITEMS; j++) {
         const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
@@ -202,67 +274,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out
         }
     }
     __syncthreads();
-
-    // thread = digit: wave offsets, tile totals, look-back
     {
         const int d = tid;
         uint32_t tot = 0;
 #pragma unroll
         for (int w = 0; w < 4; w++) {
-            uint32_t c = s_wc[w][d];
+            const uint32_t c = s_wc[w][d];
             s_wc[w][d] = tot;
             tot += c;
         }
-        uint64_t *my = status + (int64_t)tile * 256 + d;
-        st_agent(my, st_pack(tile == 0 ? ST_INC : ST_AGG, epoch, tot));
         uint32_t tile_total;
         s_tstart[d] = block_excl_scan256(tot, s_sc, tile_total);
-        int64_t excl = 0;
-        if (tile > 0) {
-            // windowed look-back: LB_WIN predecessors' status words are read at
-            // once; AGG values are summed newest to oldest until an INC is found
-            int64_t p = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            bool done = false;
-            while (!done) {
-                uint64_t v[LB_WIN];
-#pragma unroll
-                for (int i = 0; i < LB_WIN; i++)
-                    v[i] = p - i >= 0 ? ld_agent(status + (p - i) * 256 + d) : 0ull;
-                int used = 0;
-#pragma unroll
-                for (int i = 0; i < LB_WIN; i++) {
-                    if (done || used != i)
-                        continue;
-                    const uint64_t flag = v[i] & (3ull << 62);
-                    const uint32_t ep = (uint32_t)(v[i] >> 46) & 0xFFFFu;
-                    if (flag == 0 || ep != (epoch & 0xFFFFu))
-                        continue;  // not yet published: stop consuming here
-                    excl += (int64_t)(v[i] & ST_VAL);
-                    used = i + 1;
-                    if (flag == ST_INC)
-                        done = true;
-                }
-                if (done)
-                    break;
-                p -= used;
-                if (p < 0) {
-                    atomicOr(&flags->err, ERR_LOOKBACK);
-                    s_fail = 1;
-                    break;
-                }
-                if (used == 0) {
-                    if (++spins > SPIN_MAX) {
-                        atomicOr(&flags->err, ERR_LOOKBACK);
-                        s_fail = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            st_agent(my, st_pack(ST_INC, epoch, (uint64_t)excl + tot));
-        }
-        s_gbase[d] = (int64_t)bucket[d] + excl - (int64_t)s_tstart[d];
+        s_gbase[d] = (int64_t)my_off - (int64_t)s_tstart[d];
     }
     __syncthreads();
 
@@ -274,10 +297,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out
     }
     const int64_t rem = n - base;
     const int tile_n = rem < SORT_TILE ? (int)rem : SORT_TILE;
-    if (s_fail)
-        return;  // offsets are unknown: write nothing (the host reports the error)
 
-    // scatter every plane through LDS
 #pragma unroll
     for (int w = 0; w < W + 1; w++) {
 #pragma unroll
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(Planes in, Planes out
         for (int q = tid; q < tile_n; q += SORT_THREADS) {
             const int64_t dst = s_gbase[s_dig[q]] + q;
             if ((uint64_t)dst >= (uint64_t)n) {
-                atomicOr(&flags->err, ERR_LOOKBACK);
+                atomicOr(&flags->err, ERR_BOUNDS);
                 continue;
             }
             const uint64_t v = s_stage[q];
@@ -418,31 +438,42 @@ hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hi
     return hipGetLastError();
 }
 
-hipError_t launch_onesweep(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
-                           const uint64_t *bucket, uint64_t *status, uint32_t *tile_ctr, uint32_t epoch,
-                           Flags *flags, hipStream_t st)
+hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
+                             const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
+                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid)
 {
     if (n <= 0)
         return hipSuccess;
-    const int64_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
-    if (tiles > 0xFFFFFFFFll)
+    const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    const int64_t nchunks = (ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    if (ntiles > 0x7FFFFFFFll)
         return hipErrorInvalidValue;
-    dim3 g((unsigned)tiles), b(SORT_THREADS);
-#define OS(WW, PB) hipLaunchKernelGGL((k_onesweep<WW, PB>), g, b, 0, st, in, out, n, dig, bucket, status, tile_ctr, \
-                                      epoch, flags)
-    const int key = W * 2 + (pay_bytes == 8 ? 1 : 0);
-    switch (key) {
-    case 2: OS(1, 4); break;
-    case 3: OS(1, 8); break;
-    case 4: OS(2, 4); break;
-    case 5: OS(2, 8); break;
-    case 6: OS(3, 4); break;
-    case 7: OS(3, 8); break;
-    case 8: OS(4, 4); break;
-    case 9: OS(4, 8); break;
+    dim3 g((unsigned)ntiles), b(SORT_THREADS);
+    switch (W) {
+    case 1: hipLaunchKernelGGL((k_tile_count<1>), g, b, 0, st, in, n, dig, counts); break;
+    case 2: hipLaunchKernelGGL((k_tile_count<2>), g, b, 0, st, in, n, dig, counts); break;
+    case 3: hipLaunchKernelGGL((k_tile_count<3>), g, b, 0, st, in, n, dig, counts); break;
+    case 4: hipLaunchKernelGGL((k_tile_count<4>), g, b, 0, st, in, n, dig, counts); break;
     default: return hipErrorInvalidValue;
     }
-#undef OS
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, csum);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, csum, nchunks, bucket, coff);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, coff, offs);
+    if (mid)
+        (void)hipEventRecord(mid, st);
+#define SC(WW, PB) hipLaunchKernelGGL((k_scatter<WW, PB>), g, b, 0, st, in, out, n, dig, offs, flags)
+    switch (W * 2 + (pay_bytes == 8 ? 1 : 0)) {
+    case 2: SC(1, 4); break;
+    case 3: SC(1, 8); break;
+    case 4: SC(2, 4); break;
+    case 5: SC(2, 8); break;
+    case 6: SC(3, 4); break;
+    case 7: SC(3, 8); break;
+    case 8: SC(4, 4); break;
+    case 9: SC(4, 8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SC
     return hipGetLastError();
 }
 
