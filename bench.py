@@ -10,7 +10,8 @@ region starts.  Prints one JSON line.
 
 The roofline entry is for the dominant kernel, the radix rank-and-scatter
 kernel of each digit pass: algorithmic bytes per launch (each record read once
-and written once, 2 * (8W + 8) bytes per record) over its average duration
+and written once: 2 x record_bytes per record, where a record is the key
+planes, the last one only as wide as the key's top bits, plus the payload) over its average duration
 measured with HIP events on the stream the passes run on, inside the timed
 region.  The whole digit pass (count, offset scan, scatter) is reported
 beside it.
@@ -133,15 +134,14 @@ def main():
     value = n_contrib * args.steps / elapsed
     es = {r["e_pt2"] for r in results}
     W = pt2.key_words(w.norb)
-    pb = 8 if args.precision == "fp64" else 4
-    rec = 8 * W + pb
+    rec = results[0]["record_bytes"]
     passes = sum(r["n_sort_passes"] for r in results)
     n_per_pass = results[0]["n_after_cutoff"]
     scatter_ms = sum(r["ms_sort_scatter"] for r in results) / passes
     pass_ms = sum(r["ms_sort"] for r in results) / passes
     bytes_per_pass = 2.0 * rec * n_per_pass           # rank-and-scatter: read + write every record
     achieved = bytes_per_pass / (scatter_ms * 1e-3) / 1e9
-    pass_gbs = (bytes_per_pass + 8.0 * n_per_pass) / (pass_ms * 1e-3) / 1e9
+    pass_gbs = results[0]["bytes_sort"] / results[0]["n_sort_passes"] / (pass_ms * 1e-3) / 1e9
     phases = {k: round(sum(r[k] for r in results) / args.steps, 3)
               for k in ("ms_gen", "ms_hist", "ms_sort", "ms_sort_scatter", "ms_reduce")}
 

@@ -99,6 +99,7 @@ typedef struct {
     uint64_t n_in_ref_hit;    /* distinct bitstrings found in the reference          */
     uint32_t n_partitions;    /* subsets evaluated                                   */
     uint32_t n_sort_passes;   /* 8-bit digit passes run, all subsets                 */
+    uint32_t record_bytes;    /* bytes of one stored term: key planes + payload     */
     double min_abs_denom;     /* min |E0 - H_aa| over external bitstrings            */
     uint64_t n_nonneg_denom;  /* external bitstrings with E0 - H_aa >= 0             */
     double ref_cross;         /* sum over reference hits of c_i * N_i                */

@@ -52,6 +52,7 @@ class Result(C.Structure):
                 ("n_after_cutoff", C.c_uint64), ("n_unique", C.c_uint64),
                 ("n_external", C.c_uint64), ("n_in_ref_hit", C.c_uint64),
                 ("n_partitions", C.c_uint32), ("n_sort_passes", C.c_uint32),
+                ("record_bytes", C.c_uint32),
                 ("min_abs_denom", C.c_double), ("n_nonneg_denom", C.c_uint64),
                 ("ref_cross", C.c_double), ("key_xor", C.c_uint64), ("key_sum", C.c_uint64),
                 ("ms_total", C.c_double), ("ms_gen", C.c_double), ("ms_sort", C.c_double),

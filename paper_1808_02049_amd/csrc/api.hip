@@ -158,7 +158,7 @@ struct Workspace {
     int64_t ref_cap = 0;
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
-    int rec_W = 0, rec_pb = 0;
+    int rec_W = 0, rec_pb = 0, rec_topb = 0;
     Buf counts, csum, coff, offs;  // per-tile digit counts and scanned offsets
     int64_t scan_tiles = 0;
     Buf small;
@@ -201,18 +201,35 @@ struct Workspace {
     }
 };
 
-Planes planes_of(const Buf &b, int W, int64_t cap, int pb)
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// W-1 uint64 planes, then the last key plane of topb-byte elements, then the
+// payload plane; every plane starts on a 256-byte boundary.
+Planes planes_of(const Buf &b, int W, int64_t cap, int pb, int topb)
 {
     Planes p;
     char *base = (char *)b.p;
-    for (int w = 0; w < MAXW; w++)
-        p.key[w] = w < W ? (uint64_t *)(base + (size_t)w * cap * 8) : nullptr;
-    p.pay = base + (size_t)W * cap * 8;
+    size_t o = 0;
+    for (int w = 0; w < MAXW; w++) {
+        p.key[w] = nullptr;
+        if (w < W) {
+            p.key[w] = (uint64_t *)(base + o);
+            o += align256((size_t)cap * (w == W - 1 ? topb : 8));
+        }
+    }
+    p.pay = base + o;
+    p.topb = topb;
     (void)pb;
     return p;
 }
 
-size_t planes_bytes(int W, int64_t cap, int pb) { return (size_t)cap * (8 * (size_t)W + pb); }
+size_t planes_bytes(int W, int64_t cap, int pb, int topb)
+{
+    return align256((size_t)cap * 8) * (W - 1) + align256((size_t)cap * topb) + align256((size_t)cap * pb);
+}
+
+// bytes of one record: W-1 full key words, the narrow top word, the payload
+double record_bytes(int W, int pb, int topb) { return 8.0 * (W - 1) + topb + pb; }
 
 }  // namespace
 
@@ -222,6 +239,7 @@ size_t planes_bytes(int W, int64_t cap, int pb) { return (size_t)cap * (8 * (siz
 struct pt2_ctx {
     pt2_options opt;
     int norb, na, nb, W;
+    int topb;  // bytes of the last key plane of a record
     Alloc A;
     Buf h, V, h32, V32, T, R;
     DevSys sys;
@@ -352,7 +370,8 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
         if (passes_out)
             (*passes_out)++;
         if (bytes_out)
-            *bytes_out += 2.0 * (double)n * (8.0 * W + pb) + 8.0 * (double)n;
+            *bytes_out += 2.0 * (double)n * record_bytes(W, pb, src.topb) +
+                          (double)n * ((d >> 3) == W - 1 ? src.topb : 8);
     }
     return PT2_OK;
 }
@@ -376,15 +395,15 @@ int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *
     }
     if (ws.ref_cap < n) {
         buf_free(ws.A, ws.refA), buf_free(ws.A, ws.refB);
-        if ((rc = buf_alloc(ws.A, ws.refA, planes_bytes(W, n, 8))) ||
-            (rc = buf_alloc(ws.A, ws.refB, planes_bytes(W, n, 8))))
+        if ((rc = buf_alloc(ws.A, ws.refA, planes_bytes(W, n, 8, 8))) ||
+            (rc = buf_alloc(ws.A, ws.refB, planes_bytes(W, n, 8, 8))))
             return rc;
         ws.ref_cap = n;
     }
     Small *ds = ws.dsmall();
     HIPCHK(launch_zero_u32(&ds->flags.err, 2, st));
     // plane stride = n: the generation kernel indexes reference planes by nref
-    Planes ra = planes_of(ws.refA, W, n, 8), rb = planes_of(ws.refB, W, n, 8);
+    Planes ra = planes_of(ws.refA, W, n, 8, 8), rb = planes_of(ws.refB, W, n, 8, 8);
     HIPCHK(launch_refs_split(W, c->norb, c->na, c->nb, dets, coeffs, n, ra, &ds->flags, st));
     Timing none;
     if ((rc = radix_sort(ws, W, 8, ra, rb, n, 2 * c->norb, st, none, nullptr, nullptr)))
@@ -407,28 +426,28 @@ int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *
     return PT2_OK;
 }
 
-int ensure_records(Workspace &ws, int W, int pb, int64_t cap)
+int ensure_records(Workspace &ws, int W, int pb, int topb, int64_t cap)
 {
-    if (ws.rec_cap >= cap && ws.rec_W == W && ws.rec_pb == pb)
+    if (ws.rec_cap >= cap && ws.rec_W == W && ws.rec_pb == pb && ws.rec_topb == topb)
         return PT2_OK;
     buf_free(ws.A, ws.recA), buf_free(ws.A, ws.recB);
     ws.rec_cap = 0;
     int rc;
-    if ((rc = buf_alloc(ws.A, ws.recA, planes_bytes(W, cap, pb))) ||
-        (rc = buf_alloc(ws.A, ws.recB, planes_bytes(W, cap, pb)))) {
+    if ((rc = buf_alloc(ws.A, ws.recA, planes_bytes(W, cap, pb, topb))) ||
+        (rc = buf_alloc(ws.A, ws.recB, planes_bytes(W, cap, pb, topb)))) {
         buf_free(ws.A, ws.recA), buf_free(ws.A, ws.recB);
         return rc;
     }
-    ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb;
+    ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb, ws.rec_topb = topb;
     return PT2_OK;
 }
 
 // projected device bytes for one subset of n records
 // (two record buffers, plus per-tile counts and offsets: 12 B per digit value
 // per tile of SORT_TILE records)
-double subset_bytes(int W, int pb, double n)
+double subset_bytes(int W, int pb, int topb, double n)
 {
-    return n * (2.0 * (8.0 * W + pb) + 12.0 * 256.0 / SORT_TILE) + 65536.0;
+    return n * (2.0 * record_bytes(W, pb, topb) + 12.0 * 256.0 / SORT_TILE) + 65536.0;
 }
 
 struct Plan {
@@ -472,7 +491,7 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_count(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, nref, P.chunk, P.log2p, cutoff,
+    HIPCHK(launch_count(c->sys, c->L, fp32, refs, nref, P.chunk, P.log2p, cutoff,
                         (uint32_t *)ws.cnt.p, P.nchunks, st));
     HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
                              (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
@@ -498,7 +517,7 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
         k = c->opt.log2_partitions;
     else {
         k = 0;
-        while (k < MAX_LOG2P && subset_bytes(W, pb, total / (double)(1 << k) * 1.02 + 4096.0) > cap_bytes)
+        while (k < MAX_LOG2P && subset_bytes(W, pb, c->topb, total / (double)(1 << k) * 1.02 + 4096.0) > cap_bytes)
             k++;
     }
     for (int attempt = 0; attempt < 4; attempt++) {
@@ -542,7 +561,7 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
         uint64_t mx = 0;
         for (auto t : tot)
             mx = std::max(mx, t);
-        if (subset_bytes(W, pb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
+        if (subset_bytes(W, pb, c->topb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
             return PT2_OK;
         k++;
     }
@@ -598,28 +617,30 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     uint64_t mx = 0;
     for (auto s : P.sizes)
         mx = std::max(mx, s);
-    if ((rc = ensure_records(ws, W, pb, (int64_t)std::max<uint64_t>(mx, 1))))
+    if ((rc = ensure_records(ws, W, pb, c->topb, (int64_t)std::max<uint64_t>(mx, 1))))
         return rc;
+    const double rbytes = record_bytes(W, pb, c->topb);
+    res.record_bytes = (uint32_t)rbytes;
     Small *ds = ws.dsmall();
     std::vector<Partial> part_res(P.parts.size());
     for (size_t q = 0; q < P.parts.size(); q++) {
         const int64_t n = (int64_t)P.sizes[q];
         res.n_contrib += P.structural[q];
         res.n_after_cutoff += (uint64_t)n;
-        Planes A = planes_of(ws.recA, W, ws.rec_cap, pb), B = planes_of(ws.recB, W, ws.rec_cap, pb);
+        Planes A = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb), B = planes_of(ws.recB, W, ws.rec_cap, pb, c->topb);
         hipEvent_t a;
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
         if (!P.compact)
-            HIPCHK(launch_gen_direct(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, J.n, P.chunk, A, st));
+            HIPCHK(launch_gen_direct(c->sys, c->L, fp32, refs, J.n, P.chunk, A, st));
         else
-            HIPCHK(launch_gen_compact(c->sys, c->L, fp32, refs.key[0], (const double *)refs.pay, J.n, P.chunk,
+            HIPCHK(launch_gen_compact(c->sys, c->L, fp32, refs, J.n, P.chunk,
                                       P.log2p, P.parts[q], c->opt.cutoff,
                                       (const uint64_t *)ws.off.p + (size_t)q * P.nchunks, P.nchunks,
                                       (uint64_t)ws.rec_cap, A, &ds->flags, st));
         if ((rc = timed_end(ws, tm, st, a, 0)))
             return rc;
-        res.bytes_gen += (double)n * (8.0 * W + pb);
+        res.bytes_gen += (double)n * rbytes;
         if (J.dump == 1)
             break;  // generation order: the records are in recA
         if ((rc = radix_sort(ws, W, pb, A, B, n, 2 * c->norb, st, tm, &res.n_sort_passes, &res.bytes_sort)))
@@ -636,7 +657,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;
-        res.bytes_reduce += (double)n * (8.0 * W + pb);
+        res.bytes_reduce += (double)n * rbytes;
         HIPCHK(hipMemcpyAsync(&part_res[q], &ds->result, sizeof(Partial), hipMemcpyDeviceToHost, st));
     }
     if (J.dump) {
@@ -650,7 +671,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             if ((rc = buf_alloc(ws.A, kb, (size_t)std::max<int64_t>(m, 1) * W * 8)) ||
                 (rc = buf_alloc(ws.A, vb, (size_t)std::max<int64_t>(m, 1) * 8)))
                 return rc;
-            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb);
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb);
             HIPCHK(launch_planes_to_aos(W, pb, S, m, (uint64_t *)kb.p, (double *)vb.p, st));
             if (m > 0) {
                 HIPCHK(hipMemcpyAsync(J.keys_out, kb.p, (size_t)m * W * 8, hipMemcpyDeviceToHost, st));
@@ -664,7 +685,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             if ((rc = buf_alloc(ws.A, kb, (size_t)m * W * 8)) || (rc = buf_alloc(ws.A, vb, (size_t)m * 8)) ||
                 (rc = buf_alloc(ws.A, ib, (size_t)m)))
                 return rc;
-            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb);
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb);
             HIPCHK(launch_zero_u64((uint64_t *)&ds->n_out, 1, st));
             HIPCHK(launch_numerators(W, fp32, S, n, refs, J.n, (uint64_t *)kb.p, (double *)vb.p, (uint8_t *)ib.p,
                                      &ds->n_out, J.cap, st));
@@ -801,11 +822,11 @@ class Scheduler {
         const double total = (double)n * (double)c->L.nper;
         double cap = (double)(c->opt.max_partition_bytes ? std::min<uint64_t>(c->opt.max_partition_bytes, c->budget)
                                                          : c->budget);
-        double per = subset_bytes(c->W, pb, total * 1.02 + 4096.0);
+        double per = subset_bytes(c->W, pb, c->topb, total * 1.02 + 4096.0);
         int k = 0;
         while (k < MAX_LOG2P && per > cap) {
             k++;
-            per = subset_bytes(c->W, pb, total / (double)(1 << k) * 1.02 + 4096.0);
+            per = subset_bytes(c->W, pb, c->topb, total / (double)(1 << k) * 1.02 + 4096.0);
         }
         r->projected = per;
         std::unique_lock<std::mutex> lk(mu_);
@@ -1043,6 +1064,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     auto c = std::make_unique<pt2_ctx>();
     c->opt = o;
     c->norb = norb, c->na = nalpha, c->nb = nbeta, c->W = pt2_key_words(norb);
+    c->topb = top_bytes(norb);
     c->A.fa = o.alloc, c->A.ff = o.free, c->A.user = o.alloc_user, c->A.device = o.device;
     c->ws.A = c->A;
     c->L = make_layout(norb, nalpha, nbeta);
@@ -1277,7 +1299,7 @@ PT2_API int pt2_sort_records(int device, int W, int key_bits, uint64_t *keys, vo
     HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     Workspace ws;
     int rc;
-    const size_t pbytes = planes_bytes(W, n, payload_bytes);
+    const size_t pbytes = planes_bytes(W, n, payload_bytes, 8);
     if ((rc = ensure_small(ws)) || (rc = buf_alloc(ws.A, ws.recA, pbytes)) || (rc = buf_alloc(ws.A, ws.recB, pbytes))) {
         (void)hipStreamDestroy(st);
         return rc;
@@ -1286,10 +1308,14 @@ PT2_API int pt2_sort_records(int device, int W, int key_bits, uint64_t *keys, vo
     for (int64_t i = 0; i < n; i++)
         for (int w = 0; w < W; w++)
             planes[(size_t)w * n + i] = keys[i * W + w];
-    Planes A = planes_of(ws.recA, W, n, payload_bytes), B = planes_of(ws.recB, W, n, payload_bytes);
+    Planes A = planes_of(ws.recA, W, n, payload_bytes, 8), B = planes_of(ws.recB, W, n, payload_bytes, 8);
     Timing none;
     rc = PT2_OK;
-    if (hipMemcpy(ws.recA.p, planes.data(), (size_t)n * W * 8, hipMemcpyHostToDevice) != hipSuccess ||
+    bool up_ok = true;
+    for (int w = 0; w < W; w++)
+        up_ok = up_ok && hipMemcpy(A.key[w], planes.data() + (size_t)w * n, (size_t)n * 8, hipMemcpyHostToDevice) ==
+                             hipSuccess;
+    if (!up_ok ||
         hipMemcpy(A.pay, payload, (size_t)n * payload_bytes, hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(PT2_E_DEVICE, "upload failed");
     if (!rc)

@@ -115,15 +115,14 @@ __device__ inline void pair_decode(int k, int n, int &i, int &j)
 }
 
 template <int W>
-__device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, const uint64_t *refkeys,
-                          const double *refc, int64_t nref, int64_t det)
+__device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t det)
 {
     GenHead *H = g.head;
     const int tid = threadIdx.x;
     if (tid < W)
-        H->key[tid] = refkeys[(int64_t)tid * nref + det];
+        H->key[tid] = pl_get<W>(refs, tid, det);
     if (tid == 0)
-        H->c = refc[det];
+        H->c = ((const double *)refs.pay)[det];
     for (int b = tid; b < 2 * s.norb; b += blockDim.x)
         H->R[b] = s.R[b];
     __syncthreads();
@@ -343,20 +342,19 @@ __device__ inline void store_keys(const Planes &out, int64_t pos, const uint64_t
 {
 #pragma unroll
     for (int w = 0; w < W; w++)
-        out.key[w][pos] = key[w];
+        pl_put<W>(out, w, pos, key[w]);
 }
 
 // ---------------------------------------------------------------------------
 template <int W, bool F32>
-__global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout L, const uint64_t *refkeys,
-                                                            const double *refc, int64_t nref, int64_t chunk,
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                             int cpd, Planes out)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
     const int64_t det = blockIdx.x / cpd;
     const int64_t ch = blockIdx.x - det * cpd;
-    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    det_setup<W>(g, s, L, refs, det);
     const DivConsts D = div_consts(L);
     const int64_t lo = ch * chunk;
     const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
@@ -395,8 +393,7 @@ __device__ inline bool keep_term(const GenLds &g, const DevSys &s, const ExcLayo
 __device__ inline uint32_t part_of(uint64_t z, int log2p) { return log2p == 0 ? 0u : (uint32_t)(z >> (64 - log2p)); }
 
 template <int W, bool F32>
-__global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, const uint64_t *refkeys,
-                                                       const double *refc, int64_t nref, int64_t chunk,
+__global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                        int cpd, int log2p, double cutoff, uint32_t *cnt,
                                                        int64_t nchunks)
 {
@@ -409,7 +406,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
         hist[p] = 0;
     const int64_t det = blockIdx.x / cpd;
     const int64_t ch = blockIdx.x - det * cpd;
-    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    det_setup<W>(g, s, L, refs, det);
     const DivConsts D = div_consts(L);
     const int64_t lo = ch * chunk;
     const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
@@ -426,8 +423,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
 }
 
 template <int W, bool F32>
-__global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout L, const uint64_t *refkeys,
-                                                             const double *refc, int64_t nref, int64_t chunk,
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                              int cpd, int log2p, uint32_t part, double cutoff,
                                                              const uint64_t *off, uint64_t cap, Planes out,
                                                              Flags *flags)
@@ -438,7 +434,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
     uint32_t *wtot = (uint32_t *)(lds + lds_layout(L, &a, &b, &c2, &d, &e2, &f));
     const int64_t det = blockIdx.x / cpd;
     const int64_t ch = blockIdx.x - det * cpd;
-    det_setup<W>(g, s, L, refkeys, refc, nref, det);
+    det_setup<W>(g, s, L, refs, det);
     const DivConsts D = div_consts(L);
     const int64_t lo = ch * chunk;
     const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
@@ -514,16 +510,14 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
 }
 
 template <int W, bool F32>
-hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc,
-                        int64_t nref, int64_t chunk, Planes out, hipStream_t st)
+hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
 {
     int cpd = (int)((L.nper + chunk - 1) / chunk);
     int64_t blocks = nref * cpd;
     if (blocks == 0 || L.nper == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L);
-    hipLaunchKernelGGL((k_gen_direct<W, F32>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refkeys,
-                       refc, nref, chunk, cpd, out);
+    hipLaunchKernelGGL((k_gen_direct<W, F32>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, out);
     return hipGetLastError();
 }
 
@@ -548,17 +542,16 @@ size_t gen_lds_bytes(const ExcLayout &L)
     default: return hipErrorInvalidValue;                                                              \
     }
 
-hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
-                             const double *refc, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
 {
-#define CALL(W, F) gen_direct_t<W, F>(s, L, refkeys, refc, nref, chunk, out, st)
+#define CALL(W, F) gen_direct_t<W, F>(s, L, refs, nref, chunk, out, st)
     PT2_DISPATCH(s.W, fp32, CALL)
 #undef CALL
 }
 
 namespace {
 template <int W, bool F32>
-hipError_t count_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc, int64_t nref,
+hipError_t count_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref,
                    int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st)
 {
     int cpd = (int)((L.nper + chunk - 1) / chunk);
@@ -567,14 +560,13 @@ hipError_t count_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys,
     if (nchunks == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * ((size_t)1 << log2p);
-    hipLaunchKernelGGL((k_count<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refkeys, refc,
+    hipLaunchKernelGGL((k_count<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs,
                        nref, chunk, cpd, log2p, cutoff, cnt, nchunks);
     return hipGetLastError();
 }
 
 template <int W, bool F32>
-hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const uint64_t *refkeys, const double *refc,
-                         int64_t nref, int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
+hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
                          int64_t nchunks, uint64_t cap, Planes out, Flags *flags, hipStream_t st)
 {
     int cpd = (int)((L.nper + chunk - 1) / chunk);
@@ -583,28 +575,25 @@ hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const uint64_t *re
     if (nchunks == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * (GEN_THREADS / 64);
-    hipLaunchKernelGGL((k_gen_compact<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refkeys,
-                       refc, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
+    hipLaunchKernelGGL((k_gen_compact<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys, const double *refc,
-                        int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
                         hipStream_t st)
 {
-#define CALL(W, F) count_t<W, F>(s, L, refkeys, refc, nref, chunk, log2p, cutoff, cnt, nchunks, st)
+#define CALL(W, F) count_t<W, F>(s, L, refs, nref, chunk, log2p, cutoff, cnt, nchunks, st)
     PT2_DISPATCH(s.W, fp32, CALL)
 #undef CALL
 }
 
-hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
-                              const double *refc, int64_t nref, int64_t chunk, int log2p, uint32_t part,
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, int log2p, uint32_t part,
                               double cutoff, const uint64_t *off, int64_t nchunks, uint64_t cap, Planes out,
                               Flags *flags, hipStream_t st)
 {
 #define CALL(W, F) \
-    gen_compact_t<W, F>(s, L, refkeys, refc, nref, chunk, log2p, part, cutoff, off, nchunks, cap, out, flags, st)
+    gen_compact_t<W, F>(s, L, refs, nref, chunk, log2p, part, cutoff, off, nchunks, cap, out, flags, st)
     PT2_DISPATCH(s.W, fp32, CALL)
 #undef CALL
 }

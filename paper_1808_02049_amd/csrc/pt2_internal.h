@@ -53,10 +53,60 @@ struct DevSys {
 };
 
 // Structure-of-arrays record buffer: W key planes then one payload plane.
+// Planes 0..W-2 hold uint64 words; the last key plane holds `topb`-byte
+// elements (2, 4 or 8), wide enough for the key's top bits.
 struct Planes {
     uint64_t *key[MAXW];
     void *pay;
+    int topb;
 };
+
+// bytes of the last key plane for a 2*norb-bit key
+inline int top_bytes(int norb)
+{
+    const int W = (2 * norb + 63) / 64;
+    const int top_bits = 2 * norb - 64 * (W - 1);
+    return top_bits <= 16 ? 2 : (top_bits <= 32 ? 4 : 8);
+}
+
+template <int W>
+__device__ inline const void *plane_ptr(const Planes &p, int w)
+{
+    const void *r = p.key[0];
+    if (W > 1 && w == 1)
+        r = p.key[1];
+    if (W > 2 && w == 2)
+        r = p.key[2];
+    if (W > 3 && w == 3)
+        r = p.key[3];
+    return r;
+}
+
+// word w of record i (the last plane widened from its element size)
+template <int W>
+__device__ inline uint64_t pl_get(const Planes &p, int w, int64_t i)
+{
+    const void *b = plane_ptr<W>(p, w);
+    const int eb = w == W - 1 ? p.topb : 8;
+    if (eb == 8)
+        return ((const uint64_t *)b)[i];
+    if (eb == 4)
+        return ((const uint32_t *)b)[i];
+    return ((const uint16_t *)b)[i];
+}
+
+template <int W>
+__device__ inline void pl_put(const Planes &p, int w, int64_t i, uint64_t v)
+{
+    void *b = (void *)plane_ptr<W>(p, w);
+    const int eb = w == W - 1 ? p.topb : 8;
+    if (eb == 8)
+        ((uint64_t *)b)[i] = v;
+    else if (eb == 4)
+        ((uint32_t *)b)[i] = (uint32_t)v;
+    else
+        ((uint16_t *)b)[i] = (uint16_t)v;
+}
 
 // Per-block partial of the single pass; summed in block order.
 struct Partial {
@@ -120,20 +170,18 @@ inline int64_t gen_nchunks(const ExcLayout &L, int64_t nref, int64_t chunk)
 size_t gen_lds_bytes(const ExcLayout &L);
 // Direct generation: every term of every reference, record index
 // det*nper + k.  Requires no cutoff and a single subset.
-hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
-                             const double *refc, int64_t nref, int64_t chunk, Planes out, hipStream_t st);
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+                             int64_t chunk, Planes out, hipStream_t st);
 // Count pass: cnt[p * nchunks + chunk] = kept terms of chunk in subset p.
-hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
-                        const double *refc, int64_t nref, int64_t chunk, int log2p, double cutoff,
-                        uint32_t *cnt, int64_t nchunks, hipStream_t st);
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+                        int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st);
 // Exclusive scan of cnt[p][*] into off[p][*] for each listed subset; tot[k] = N of parts[k].
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
                              uint64_t *off, uint64_t *tot, hipStream_t st);
 // Compacting generation of subset `part` (offsets from launch_chunk_scan).
-hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const uint64_t *refkeys,
-                              const double *refc, int64_t nref, int64_t chunk, int log2p,
-                              uint32_t part, double cutoff, const uint64_t *off, int64_t nchunks,
-                              uint64_t cap, Planes out, Flags *flags, hipStream_t st);
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+                              int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
+                              int64_t nchunks, uint64_t cap, Planes out, Flags *flags, hipStream_t st);
 
 // sort.hip
 // hist[d*256 + v] += count of digit value v at digit position d (d < ndig).

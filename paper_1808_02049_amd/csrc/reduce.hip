@@ -51,7 +51,7 @@ __device__ inline void load_key(const Planes &p, int64_t i, uint64_t (&k)[W])
 {
 #pragma unroll
     for (int w = 0; w < W; w++)
-        k[w] = p.key[w][i];
+        k[w] = pl_get<W>(p, w, i);
 }
 
 template <int PB>
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             for (int i = tid; i < (int)(rs.hi - rs.lo); i += RED_THREADS) {
 #pragma unroll
                 for (int w = 0; w < W; w++)
-                    s_rk[w * RED_LDS_REFS + i] = refs.key[w][rs.lo + i];
+                    s_rk[w * RED_LDS_REFS + i] = pl_get<W>(refs, w, rs.lo + i);
                 s_rc[i] = ((const double *)refs.pay)[rs.lo + i];
             }
 

@@ -23,19 +23,6 @@
 namespace pt2 {
 namespace {
 
-template <int W>
-__device__ inline const uint64_t *plane_c(const Planes &p, int w)
-{
-    const uint64_t *r = p.key[0];
-    if (W > 1 && w == 1)
-        r = p.key[1];
-    if (W > 2 && w == 2)
-        r = p.key[2];
-    if (W > 3 && w == 3)
-        r = p.key[3];
-    return r;
-}
-
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t *sh4, uint32_t &total)
 {
@@ -77,10 +64,9 @@ __global__ __launch_bounds__(256) void k_hist(Planes in, int64_t n, int ndig, un
 #pragma unroll
         for (int w = 0; w < W; w++) {
             uint64_t v[RI];
-            const uint64_t *src = plane_c<W>(in, w);
 #pragma unroll
             for (int j = 0; j < RI; j++)
-                v[j] = r0 + j < n ? src[r0 + j] : 0;
+                v[j] = r0 + j < n ? pl_get<W>(in, w, r0 + j) : 0;
 #pragma unroll
             for (int dd = 0; dd < 8; dd++) {
                 const int d = w * 8 + dd;
@@ -141,12 +127,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t 
         (&h[0][0])[i] = 0;
     __syncthreads();
     const int word = dig >> 3, shift = (dig & 7) * 8;
-    const uint64_t *src = plane_c<W>(in, word);
     const int64_t r0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)tid * SORT_ITEMS;
     uint64_t v[SORT_ITEMS];
 #pragma unroll
     for (int j = 0; j < SORT_ITEMS; j++)
-        v[j] = r0 + j < n ? src[r0 + j] : 0ull;
+        v[j] = r0 + j < n ? pl_get<W>(in, word, r0 + j) : 0ull;
     uint32_t last = 0xFFFFFFFFu, cnt = 0;
 #pragma unroll
     for (int j = 0; j < SORT_ITEMS; j++) {
@@ -240,7 +225,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * SORT_TILE;
     const int word = dig >> 3, shift = (dig & 7) * 8;
-    const uint64_t *src = plane_c<W>(in, word);
     const uint64_t my_off = offs[tile * 256 + tid];
 
     uint64_t kw[SORT_ITEMS];
@@ -248,7 +232,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
 #pragma unroll
     for (int j = 0; j < SORT_ITEMS; j++) {
         const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
-        kw[j] = idx < n ? src[idx] : 0ull;
+        kw[j] = idx < n ? pl_get<W>(in, word, idx) : 0ull;
     }
     __syncthreads();
     // rank within the wave: peers = lanes with the same digit (stable)
@@ -308,7 +292,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
                 if (w == word)
                     v = kw[j];
                 else if (w < W)
-                    v = plane_c<W>(in, w)[idx];
+                    v = pl_get<W>(in, w, idx);
                 else
                     v = PB == 8 ? ((const uint64_t *)in.pay)[idx] : (uint64_t)((const uint32_t *)in.pay)[idx];
                 s_stage[lpos[j]] = v;
@@ -325,7 +309,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
             }
             const uint64_t v = s_stage[q];
             if (w < W)
-                out.key[w][dst] = v;
+                pl_put<W>(out, w, dst, v);
             else if (PB == 8)
                 ((uint64_t *)out.pay)[dst] = v;
             else
@@ -357,7 +341,7 @@ __global__ void k_refs_split(int norb, int na, int nb, const uint64_t *dets, con
 #pragma unroll
         for (int w = 0; w < W; w++) {
             const uint64_t v = dets[i * W + w];
-            out.key[w][i] = v;
+            pl_put<W>(out, w, i, v);
             for (int b = 0; b < 64; b++) {
                 const int bit = w * 64 + b;
                 if (!((v >> b) & 1ull))
@@ -386,7 +370,7 @@ __global__ void k_dup_check(Planes sorted, int64_t n, Flags *flags)
         bool eq = true;
 #pragma unroll
         for (int w = 0; w < W; w++)
-            eq = eq && sorted.key[w][i] == sorted.key[w][i - 1];
+            eq = eq && pl_get<W>(sorted, w, i) == pl_get<W>(sorted, w, i - 1);
         if (eq)
             atomicOr(&flags->err, ERR_DUPLICATE);
     }
@@ -398,7 +382,7 @@ __global__ void k_planes_to_aos(Planes in, int pay_bytes, int64_t n, uint64_t *k
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
         for (int w = 0; w < W; w++)
-            keys[i * W + w] = in.key[w][i];
+            keys[i * W + w] = pl_get<W>(in, w, i);
         if (pay)
             pay[i] = pay_bytes == 8 ? ((const double *)in.pay)[i] : (double)((const float *)in.pay)[i];
     }
