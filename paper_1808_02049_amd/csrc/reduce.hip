@@ -357,8 +357,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                                                         size_t q_bytes, Partial *partials, Flags *flags)
 {
     extern __shared__ __align__(16) char dyn[];
-    __shared__ uint8_t s_f[RED_THREADS];
-    __shared__ double s_v[RED_THREADS];
+    __shared__ uint8_t s_f[RED_THREADS / 64];
+    __shared__ double s_v[RED_THREADS / 64];
     __shared__ uint32_t s_cnt[RED_THREADS / 64];
     __shared__ uint64_t s_rk[W * RED_LDS_REFS];
     __shared__ double s_rc[RED_LDS_REFS];
@@ -367,16 +367,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
     __shared__ uint64_t s_anc[W];
-    __shared__ double s_g[2 * MAXORB];
     __shared__ double s_er[RED_THREADS / 64];
 
     const int nso = 2 * s.norb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *q_key = (uint64_t *)dyn;                       // [W][RED_Q]
     double *q_num = (double *)(dyn + (size_t)W * RED_Q * 8); // [RED_Q]
+    // g vector of the tile's anchor (nso entries) after the queue region
+    double *s_g = (double *)(dyn + q_bytes);
     const double *Tp = s.T;
     if (lds_table) {
-        double *t = (double *)(dyn + q_bytes);
+        double *t = (double *)(dyn + q_bytes + (size_t)nso * 8);
         const int ntri = nso * (nso + 1) / 2;
         for (int i = tid; i < ntri; i += RED_THREADS)
             t[i] = s.T[i];
@@ -512,28 +513,42 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             run[j] = sacc;
             hh[j] = any;
         }
-        // block exclusive segmented scan of (any, sacc) over threads
-        s_f[tid] = any ? 1 : 0;
-        s_v[tid] = sacc;
-        __syncthreads();
-        for (int o = 1; o < RED_THREADS; o <<= 1) {
-            uint8_t f2 = 0;
-            double v2 = 0.0;
-            if (tid >= o) {
-                f2 = s_f[tid - o];
-                v2 = s_v[tid - o];
+        // block exclusive segmented scan of (any, sacc) over threads: inclusive
+        // scan within each wavefront by shuffles, then the earlier wavefronts'
+        // totals; the operator is (f1,v1).(f2,v2) = (f1|f2, f2 ? v2 : v1+v2)
+        bool fi = any;
+        double vi = sacc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int fo = __shfl_up((int)fi, o);
+            const double vo = __shfl_up(vi, o);
+            if (lane >= o) {
+                vi = fi ? vi : vo + vi;
+                fi = fi || fo;
             }
-            __syncthreads();
-            if (tid >= o) {
-                const uint8_t fc = s_f[tid];
-                const double vc = s_v[tid];
-                s_v[tid] = fc ? vc : v2 + vc;
-                s_f[tid] = fc | f2;
-            }
-            __syncthreads();
         }
-        const bool cf = tid > 0 ? s_f[tid - 1] != 0 : false;
-        const double cv = tid > 0 ? s_v[tid - 1] : 0.0;
+        if (lane == 63) {
+            s_f[wave] = fi ? 1 : 0;
+            s_v[wave] = vi;
+        }
+        // exclusive value within the wavefront
+        int fx = __shfl_up((int)fi, 1);
+        double vx = __shfl_up(vi, 1);
+        if (lane == 0) {
+            fx = 0;
+            vx = 0.0;
+        }
+        __syncthreads();
+        // prefix of the earlier wavefronts, combined in order
+        bool fw = false;
+        double vw = 0.0;
+        for (int w = 0; w < wave; w++) {
+            const bool f2 = s_f[w] != 0;
+            vw = f2 ? s_v[w] : vw + s_v[w];
+            fw = fw || f2;
+        }
+        const bool cf = fx ? true : fw;
+        const double cv = fx ? vx : vw + vx;
 
         // owned segment ends of this thread go to the queue in record order
         uint32_t mine = 0;
@@ -760,7 +775,7 @@ hipError_t launch_reduce(const DevSys &s, int fp32, const Planes &sorted, int64_
     if (q_bytes < sizeof(Partial) * RED_THREADS)
         q_bytes = sizeof(Partial) * RED_THREADS;
     q_bytes = (q_bytes + 15) & ~(size_t)15;
-    const size_t dyn = q_bytes + (lds_table ? tri_bytes : 0);
+    const size_t dyn = q_bytes + (size_t)nso * 8 + (lds_table ? tri_bytes : 0);
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RD(WW, PB) \
     hipLaunchKernelGGL((k_reduce<WW, PB>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, q_bytes, \
