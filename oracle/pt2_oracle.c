@@ -775,6 +775,13 @@ static void *exp_worker(void *arg)
     for (int64_t i = J->lo; i < J->hi; i++) {
         double row = 0.0, rc = 0.0;
         for (int64_t j = 0; j < J->n; j++) {
+            /* H_ij vanishes beyond double excitations (more than four differing
+             * spin-orbitals); orc_hij returns 0 there too, this only skips the call */
+            int ndiff = 0;
+            for (int w = 0; w < W; w++)
+                ndiff += __builtin_popcountll(J->dets[i * W + w] ^ J->dets[j * W + w]);
+            if (ndiff > 4)
+                continue;
             double hij = orc_hij(J->s, J->dets + i * W, J->dets + j * W);
             if (hij != 0.0)
                 neumaier_add(&row, &rc, hij * J->c[j]);

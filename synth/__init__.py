@@ -34,6 +34,7 @@ __all__ = [
     "Workload", "WORKLOADS", "key_words", "pack_keys", "unpack_keys",
     "hf_key", "make_integrals", "excitation_pool", "decaying_coefficients",
     "draw_signs", "select_lowest", "random_determinants", "n_excitations_per_det",
+    "ladder_references", "Request", "serving_requests", "request_inputs",
 ]
 
 
@@ -223,3 +224,97 @@ def random_determinants(norb: int, na: int, nb: int, n: int, seed: int) -> np.nd
         seen.add(t)
         rows.append(k)
     return np.array(rows, dtype=np.uint64).reshape(n, key_words(norb))
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: 200 requests of different active spaces.
+
+def _displacement_strings(norb: int, n: int, max_e: int):
+    """Occupations of one spin whose orbital-index displacement from the
+    lowest n orbitals, sum_i (o_i - i), is at most max_e; returns
+    (list of occupied-index tuples, list of displacements)."""
+    v = norb - n
+    out, es = [], []
+
+    def rec(i, lo, total, acc):
+        if i == n:
+            out.append(tuple(k + d for k, d in enumerate(acc)))
+            es.append(total)
+            return
+        # displacements are non-decreasing and bounded by v
+        for d in range(lo, v + 1):
+            # the remaining n - i displacements are all >= d
+            if total + d * (n - i) > max_e:
+                break
+            acc.append(d)
+            rec(i + 1, d, total + d, acc)
+            acc.pop()
+
+    if n == 0:
+        return [()], [0]
+    rec(0, 0, 0, [])
+    return out, es
+
+
+def ladder_references(norb: int, na: int, nb: int, n_ref: int) -> np.ndarray:
+    """The n_ref determinants lowest in orbital-ladder excitation energy: the
+    total displacement of occupied orbital indices from the aufbau
+    determinant (alpha plus beta), ties broken by the bitstring.  With the
+    linear h_pp = -2 + 0.25 p of this recipe this is the one-body energy
+    ordering; it uses orbital indices only, no integrals."""
+    max_e = 0
+    while True:
+        sa, ea = _displacement_strings(norb, na, max_e)
+        sb, eb = _displacement_strings(norb, nb, max_e)
+        ea_arr, eb_arr = np.array(ea), np.array(eb)
+        cnt = sum(int(np.sum(eb_arr <= max_e - e)) for e in ea)
+        if cnt >= n_ref or max_e > 4 * norb:
+            break
+        max_e += 1
+    ia, ib = np.nonzero(ea_arr[:, None] + eb_arr[None, :] <= max_e)
+    SA = np.zeros((len(sa), norb), bool)
+    SB = np.zeros((len(sb), norb), bool)
+    for r, occ in enumerate(sa):
+        SA[r, list(occ)] = True
+    for r, occ in enumerate(sb):
+        SB[r, list(occ)] = True
+    keys = pack_keys(SA[ia], SB[ib], norb)
+    energy = ea_arr[ia] + eb_arr[ib]
+    W = keys.shape[1]
+    order = np.lexsort(tuple(keys[:, w] for w in range(W)) + (energy,))
+    return np.ascontiguousarray(keys[order[:n_ref]])
+
+
+@dataclass(frozen=True)
+class Request:
+    index: int
+    nalpha: int
+    norb: int
+    n_ref: int
+    seed: int
+    arrival_s: float
+
+
+def serving_requests(count: int = 200, rate_per_s: float = 1.0) -> list[Request]:
+    """Request parameters: electrons uniform on {10, 12, ..., 24} (equal alpha
+    and beta), orbitals round(U[2.0, 2.5] * electrons), references
+    round(exp U[ln 1e3, ln 5e4]), integral seed 4000 + j; Poisson arrivals of
+    the given rate (exponential gaps from seed 4999; parameters from 4998)."""
+    prm = np.random.default_rng(4998)
+    arr = np.random.default_rng(4999)
+    t, out = 0.0, []
+    for j in range(count):
+        ne = int(prm.integers(5, 13)) * 2
+        norb = int(round(prm.uniform(2.0, 2.5) * ne))
+        nref = int(round(math.exp(prm.uniform(math.log(1e3), math.log(5e4)))))
+        t += float(arr.exponential(1.0 / rate_per_s))
+        out.append(Request(j, ne // 2, norb, nref, 4000 + j, t))
+    return out
+
+
+def request_inputs(req: Request, n_chol: int = 64, decay: float = 0.002):
+    """(h, eri, dets, c) of one serving request; E0 is stored separately."""
+    h, eri, rng = make_integrals(req.norb, n_chol, req.seed)
+    dets = ladder_references(req.norb, req.nalpha, req.nalpha, req.n_ref)
+    c = decaying_coefficients(req.n_ref, decay, draw_signs(rng, req.n_ref))
+    return h, eri, dets, c

@@ -80,3 +80,59 @@ def test_stored_inputs_regenerate():
     assert np.all(a.sum(1) == 10) and np.all(b.sum(1) == 10)
     assert np.array_equal(f["dets"][0], synth.hf_key(40, 10, 10))
     assert len({tuple(r) for r in f["dets"]}) == w.n_ref
+
+
+def _brute_ladder(norb, na, nb):
+    """Every determinant with its total orbital-index displacement (itertools)."""
+    import itertools
+    rows = []
+    for oa in itertools.combinations(range(norb), na):
+        for ob in itertools.combinations(range(norb), nb):
+            e = sum(o - i for i, o in enumerate(oa)) + sum(o - i for i, o in enumerate(ob))
+            A = np.zeros((1, norb), bool)
+            B = np.zeros((1, norb), bool)
+            A[0, list(oa)] = True
+            B[0, list(ob)] = True
+            rows.append((e, tuple(int(x) for x in synth.pack_keys(A, B, norb)[0][::-1])))
+    rows.sort()
+    return rows
+
+
+@pytest.mark.parametrize("norb,na,nb,n_ref", [(8, 3, 3, 50), (9, 4, 2, 200), (7, 2, 2, 441), (10, 5, 5, 1)])
+def test_ladder_references_match_brute_force(norb, na, nb, n_ref):
+    got = synth.ladder_references(norb, na, nb, n_ref)
+    want = _brute_ladder(norb, na, nb)[:n_ref]
+    assert got.shape == (n_ref, synth.key_words(norb))
+    assert [tuple(int(x) for x in r[::-1]) for r in got] == [k for _, k in want]
+    assert np.array_equal(got[0], synth.hf_key(norb, na, nb))
+
+
+def test_serving_requests_recipe():
+    reqs = synth.serving_requests()
+    assert len(reqs) == 200
+    assert all(5 <= r.nalpha <= 12 for r in reqs)
+    assert all(round(2.0 * 2 * r.nalpha) <= r.norb <= round(2.5 * 2 * r.nalpha) for r in reqs)
+    assert all(1000 <= r.n_ref <= 50000 for r in reqs)
+    t = [r.arrival_s for r in reqs]
+    assert all(b > a for a, b in zip(t, t[1:]))
+    assert 150 < t[-1] < 250      # 200 exponential gaps of mean 1 s
+    assert synth.serving_requests(rate_per_s=2.0)[-1].arrival_s == pytest.approx(t[-1] / 2)
+
+
+def test_stored_serving_e0_regenerates():
+    """The stored E0 of the three smallest requests equals the oracle's
+    <c|H|c> on the regenerated inputs (catches drift in the request recipe)."""
+    import json
+    import os
+    import oracle
+    stored = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                         "serving_requests.json")))
+    reqs = synth.serving_requests()
+    assert [(r.index, r.nalpha, r.norb, r.n_ref, r.seed) for r in reqs] == \
+        [(s["index"], s["nalpha"], s["norb"], s["n_ref"], s["seed"]) for s in stored]
+    for r in sorted(reqs, key=lambda r: r.n_ref)[:3]:
+        h, eri, dets, c = synth.request_inputs(r)
+        e0 = oracle.Oracle(h, eri, r.norb, r.nalpha, r.nalpha).expectation(dets, c)
+        s = stored[r.index]
+        assert abs(e0 - s["e0"]) <= 1e-12 * abs(s["e0"])
+        assert float.fromhex(s["e0_hex"]) == s["e0"]
