@@ -80,6 +80,8 @@ struct Alloc {
     void (*ff)(void *, size_t, void *) = nullptr;
     void *user = nullptr;
     int device = 0;
+    hipStream_t stream = nullptr;  // non-null: stream-ordered allocation on this stream
+    bool same_source(const Alloc &o) const { return fa == o.fa && ff == o.ff && user == o.user; }
 };
 
 struct Buf {
@@ -100,10 +102,10 @@ int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
         if (!p)
             return fail(PT2_E_NOMEM, "allocator hook failed for %zu bytes", bytes);
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
+        hipError_t e = A.stream ? hipMallocAsync(&p, bytes, A.stream) : hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            return fail(PT2_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+            return fail(PT2_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
         }
     }
     b.p = p;
@@ -119,8 +121,11 @@ void buf_free(const Alloc &A, Buf &b)
             // queued kernel that might still use it finish first
             (void)hipDeviceSynchronize();
             A.ff(b.p, b.bytes, A.user);
-        } else
+        } else if (A.stream) {
+            (void)hipFreeAsync(b.p, A.stream);
+        } else {
             (void)hipFree(b.p);
+        }
     }
     b.p = nullptr;
     b.bytes = 0;
@@ -891,16 +896,13 @@ class Scheduler {
     std::unordered_map<int64_t, std::unique_ptr<Request>> all_;
     std::vector<std::unique_ptr<Worker>> workers_;
     int64_t next_id_ = 1;
-    double in_use_ = 0.0;
-    double budget_ = 0.0;
-    int running_ = 0;
+    std::unordered_map<int, double> in_use_;  // projected bytes of running requests, per device
+    std::unordered_map<int, int> running_;    // running requests, per device
     bool stopping_ = false;
     bool atexit_ = false;
 
     void start_workers_locked(pt2_ctx *c)
     {
-        if (budget_ == 0.0 || (double)c->budget > budget_)
-            budget_ = (double)c->budget;
         const int want = std::max(1, c->opt.n_streams);
         if (!atexit_) {
             atexit_ = true;
@@ -917,12 +919,15 @@ class Scheduler {
         }
     }
 
-    // first queued request that fits; a request bypassed too often blocks the rest
+    // first queued request whose projected bytes, added to what runs on its
+    // device, fit its own context's budget (or that would run alone there);
+    // a request bypassed too often blocks the rest
     Request *pick_locked()
     {
         for (size_t i = 0; i < queue_.size(); i++) {
             Request *r = queue_[i];
-            if (running_ == 0 || in_use_ + r->projected <= budget_) {
+            const int dev = r->ctx->opt.device;
+            if (running_[dev] == 0 || in_use_[dev] + r->projected <= (double)r->ctx->budget) {
                 queue_.erase(queue_.begin() + (long)i);
                 return r;
             }
@@ -948,11 +953,16 @@ class Scheduler {
                 bypass_++;
             else
                 bypass_ = 0;
-            in_use_ += r->projected;
-            running_++;
-            lk.unlock();
             pt2_ctx *c = r->ctx;
-            w->ws->A = c->A;
+            in_use_[c->opt.device] += r->projected;
+            running_[c->opt.device]++;
+            lk.unlock();
+            (void)hipSetDevice(c->opt.device);
+            Alloc A = c->A;
+            A.stream = A.fa ? nullptr : w->stream;  // stream-ordered unless a hook allocates
+            if (!w->ws->A.same_source(A) || w->ws->A.stream != A.stream)
+                w->ws->release();  // buffers go back to the allocator that made them
+            w->ws->A = A;
             Job J{};
             J.dets = r->dets.data();
             J.coeffs = r->c.data();
@@ -965,16 +975,22 @@ class Scheduler {
             res.struct_size = sizeof res;
             int rc = w->stream ? run_job(c, *w->ws, w->stream, J, &res)
                                : fail(PT2_E_DEVICE, "worker stream creation failed");
-            // release record buffers so the budget accounting stays truthful
+            // give the record buffers back (stream-ordered, no device-wide wait)
+            // so that admission by projected bytes stays truthful
             buf_free(w->ws->A, w->ws->recA), buf_free(w->ws->A, w->ws->recB);
+            buf_free(w->ws->A, w->ws->counts), buf_free(w->ws->A, w->ws->offs);
+            buf_free(w->ws->A, w->ws->csum), buf_free(w->ws->A, w->ws->coff);
             w->ws->rec_cap = 0;
+            w->ws->scan_tiles = 0;
+            if (w->stream)
+                (void)hipStreamSynchronize(w->stream);
             lk.lock();
             r->rc = rc;
             r->err = rc != PT2_OK ? g_err : std::string();
             r->res = res;
             r->done = true;
-            in_use_ -= r->projected;
-            running_--;
+            in_use_[c->opt.device] -= r->projected;
+            running_[c->opt.device]--;
             done_cv_.notify_all();
             cv_.notify_all();
         }
