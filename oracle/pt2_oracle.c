@@ -46,6 +46,7 @@
 
 #define ORC_MAXW 4
 #define ORC_MAXORB 128
+#define ORC_MAXTHREADS 256
 
 typedef struct {
     int norb, nalpha, nbeta;
@@ -269,33 +270,32 @@ typedef struct {
     const uint64_t *R; /* Zobrist table */
     int W, log2p;
     double cutoff;
-    /* which subsets to keep: keep[part] != 0 */
-    const unsigned char *keep;
-    uint64_t n_candidates; /* candidates whose subset is kept */
+    /* slot[part]: where records of that subset go (index into outs), or -1
+     * for a subset not evaluated; with log2p == 0 everything goes to slot 0 */
+    const int32_t *slot;
+    uint64_t *n_candidates; /* per slot: candidates whose subset is kept */
+    orc_vec *outs;          /* per slot: emitted records */
 } orc_emit_ctx;
 
-/* Emit one candidate if its subset is kept and it passes the cutoff.  z is
- * the Zobrist hash of the candidate: the parent's hash XOR the words of the
- * flipped bits (XOR hashing is incremental by construction). */
-static int emit(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, uint64_t z, double hval, double ci,
-                uint64_t seq)
+/* Slot of a candidate with Zobrist hash z (-1: its subset is not evaluated).
+ * Tested before the matrix element is evaluated.  z is the parent's hash XOR
+ * the words of the flipped bits (XOR hashing is incremental by construction). */
+static int kept(const orc_emit_ctx *E, uint64_t z) { return E->log2p == 0 ? 0 : E->slot[part_of(z, E->log2p)]; }
+
+/* Emit one candidate of a kept subset if it passes the cutoff. */
+static int emit(orc_emit_ctx *E, int slot, const uint64_t *key, double hval, double ci, uint64_t seq)
 {
-    if (E->log2p > 0 && !E->keep[part_of(z, E->log2p)])
-        return 0;
-    E->n_candidates++;
+    E->n_candidates[slot]++;
     double v = hval * ci;
     if (E->cutoff > 0.0 && fabs(v) < E->cutoff)
         return 0;
-    return vec_push(out, key, E->W, v, seq);
+    return vec_push(&E->outs[slot], key, E->W, v, seq);
 }
-
-/* Subset test done before the matrix element is evaluated. */
-static int kept(const orc_emit_ctx *E, uint64_t z) { return E->log2p == 0 || E->keep[part_of(z, E->log2p)]; }
 
 /* All singles and doubles of one reference determinant, in a fixed order:
  * alpha singles, beta singles, alpha-alpha doubles, beta-beta doubles,
  * alpha-beta doubles. */
-static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double ci, uint64_t seq0)
+static int expand_det(orc_emit_ctx *E, const uint64_t *key, double ci, uint64_t seq0)
 {
     const orc_system *s = E->s;
     int n = s->norb, W = E->W;
@@ -315,12 +315,13 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                 flip_bit(k1, spin_bit(s, spin, r));
                 flip_bit(k1, spin_bit(s, spin, a));
                 uint64_t z = zp ^ R[spin_bit(s, spin, r)] ^ R[spin_bit(s, spin, a)];
-                if (!kept(E, z)) {
+                const int sl = kept(E, z);
+                if (sl < 0) {
                     seq++;
                     continue;
                 }
                 double hv = phase_move(s, key, spin, r, a) * single_value(s, key, spin, r, a);
-                if (emit(E, out, k1, z, hv, ci, seq++))
+                if (emit(E, sl, k1, hv, ci, seq++))
                     return -1;
             }
         }
@@ -345,12 +346,13 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                         flip_bit(k2, spin_bit(s, spin, b));
                         uint64_t z = zp ^ R[spin_bit(s, spin, r)] ^ R[spin_bit(s, spin, t)] ^
                                      R[spin_bit(s, spin, a)] ^ R[spin_bit(s, spin, b)];
-                        if (!kept(E, z)) {
+                        const int sl = kept(E, z);
+                        if (sl < 0) {
                             seq++;
                             continue;
                         }
                         double hv = double_same(s, key, spin, r, t, a, b);
-                        if (emit(E, out, k2, z, hv, ci, seq++))
+                        if (emit(E, sl, k2, hv, ci, seq++))
                             return -1;
                     }
                 }
@@ -371,7 +373,8 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                         continue;
                     uint64_t z = zp ^ R[spin_bit(s, 0, r)] ^ R[spin_bit(s, 0, a)] ^ R[spin_bit(s, 1, t)] ^
                                  R[spin_bit(s, 1, b)];
-                    if (!kept(E, z)) {
+                    const int sl = kept(E, z);
+                    if (sl < 0) {
                         seq++;
                         continue;
                     }
@@ -381,7 +384,7 @@ static int expand_det(orc_emit_ctx *E, orc_vec *out, const uint64_t *key, double
                     flip_bit(k2, spin_bit(s, 1, t));
                     flip_bit(k2, spin_bit(s, 1, b));
                     double hv = double_opp(s, key, r, a, t, b);
-                    if (emit(E, out, k2, z, hv, ci, seq++))
+                    if (emit(E, sl, k2, hv, ci, seq++))
                         return -1;
                 }
             }
@@ -485,63 +488,154 @@ static double single_pass(const orc_system *s, const orc_refset *R, double e0, o
 /* ------------------------------------------------------------------------ */
 /* Driver                                                                    */
 
-typedef struct {
-    const orc_system *s;
-    const uint64_t *dets;
-    const double *c;
-    int64_t n;
-    double e0, cutoff;
-    int log2p, W;
-    const uint64_t *R;
-    const orc_refset *refs;
-    const uint32_t *parts; /* subsets this worker evaluates */
-    int nparts;
-    int stride, first;   /* worker handles parts[first], parts[first+stride], ... */
-    double *e_part;      /* output per entry of parts */
-    orc_result *res_part;
-    int err;
-} orc_job;
-
 static void result_init(orc_result *r)
 {
     memset(r, 0, sizeof(*r));
     r->min_abs_denom = INFINITY;
 }
 
-static void *worker(void *arg)
+/* Expansion of a contiguous slice of the reference determinants into the
+ * slots of the subsets being evaluated (one job per thread). */
+typedef struct {
+    const uint64_t *dets;
+    const double *c;
+    int64_t lo, hi;
+    orc_emit_ctx E;
+    int err;
+} gen_job;
+
+static void *gen_worker(void *arg)
 {
-    orc_job *J = (orc_job *)arg;
-    size_t np = (size_t)1 << J->log2p;
-    unsigned char *keep = (unsigned char *)calloc(np, 1);
-    if (!keep) {
-        J->err = -1;
-        return NULL;
-    }
-    for (int k = J->first; k < J->nparts; k += J->stride) {
-        uint32_t part = J->parts[k];
-        memset(keep, 0, np);
-        keep[part] = 1;
-        orc_emit_ctx E = {J->s, J->R, J->W, J->log2p, J->cutoff, keep, 0};
-        orc_vec v = {NULL, 0, 0};
-        orc_result *res = &J->res_part[k];
-        result_init(res);
-        for (int64_t i = 0; i < J->n; i++) {
-            if (expand_det(&E, &v, J->dets + i * J->W, J->c[i], (uint64_t)i << 32)) {
-                J->err = -1;
-                free(v.r);
-                free(keep);
-                return NULL;
-            }
+    gen_job *J = (gen_job *)arg;
+    for (int64_t i = J->lo; i < J->hi; i++)
+        if (expand_det(&J->E, J->dets + i * J->E.W, J->c[i], (uint64_t)i << 32)) {
+            J->err = -1;
+            return NULL;
         }
-        res->n_contrib = E.n_candidates;
-        res->n_kept = v.n;
-        qsort(v.r, v.n, sizeof(orc_rec), cmp_rec);
-        J->e_part[k] = single_pass(J->s, J->refs, J->e0, v.r, v.n, res);
-        res->e_pt2 = J->e_part[k];
-        free(v.r);
-    }
-    free(keep);
     return NULL;
+}
+
+/* Grouping and single pass of the slots first, first+stride, ... */
+typedef struct {
+    const orc_system *s;
+    const orc_refset *refs;
+    double e0;
+    gen_job *gen;
+    int ngen, nslot, stride, first;
+    double *e_slot;
+    orc_result *res_slot;
+    int err;
+} pass_job;
+
+static void *pass_worker(void *arg)
+{
+    pass_job *J = (pass_job *)arg;
+    for (int k = J->first; k < J->nslot; k += J->stride) {
+        orc_result *res = &J->res_slot[k];
+        result_init(res);
+        size_t tot = 0;
+        for (int t = 0; t < J->ngen; t++) {
+            tot += J->gen[t].E.outs[k].n;
+            res->n_contrib += J->gen[t].E.n_candidates[k];
+        }
+        orc_rec *all = (orc_rec *)malloc(sizeof(orc_rec) * (tot ? tot : 1));
+        if (!all) {
+            J->err = -1;
+            return NULL;
+        }
+        size_t o = 0;
+        for (int t = 0; t < J->ngen; t++) {
+            orc_vec *v = &J->gen[t].E.outs[k];
+            if (v->n)
+                memcpy(all + o, v->r, sizeof(orc_rec) * v->n);
+            o += v->n;
+            free(v->r);
+            v->r = NULL, v->n = v->cap = 0;
+        }
+        res->n_kept = tot;
+        /* the sequence number makes the order total: emission order within a key */
+        qsort(all, tot, sizeof(orc_rec), cmp_rec);
+        J->e_slot[k] = single_pass(J->s, J->refs, J->e0, all, tot, res);
+        res->e_pt2 = J->e_slot[k];
+        free(all);
+    }
+    return NULL;
+}
+
+static void run_threads(void *(*fn)(void *), void *jobs, size_t size, int nt)
+{
+    pthread_t th[ORC_MAXTHREADS];
+    if (nt == 1) {
+        fn(jobs);
+        return;
+    }
+    for (int t = 0; t < nt; t++)
+        pthread_create(&th[t], NULL, fn, (char *)jobs + (size_t)t * size);
+    for (int t = 0; t < nt; t++)
+        pthread_join(th[t], NULL);
+}
+
+/* Expand every reference determinant once for the subsets parts[0..nslot)
+ * (threads over slices of the reference), then group and pass each subset
+ * (threads over subsets).  The records of a subset are the same set, and
+ * after sorting by (bitstring, emission order) in the same order, whatever
+ * the thread count. */
+static int run_batch(const orc_system *s, const uint64_t *dets, const double *c, int64_t n, double e0,
+                     double cutoff, int log2p, const uint64_t *R, const orc_refset *refs, int32_t *slot,
+                     const uint32_t *parts, int nslot, int nthreads, double *e_slot, orc_result *res_slot)
+{
+    const int W = orc_key_words(s->norb);
+    int ng = nthreads;
+    if (ng > n)
+        ng = n > 0 ? (int)n : 1;
+    if (log2p > 0)
+        for (int k = 0; k < nslot; k++)
+            slot[parts[k]] = k;
+    gen_job *gen = (gen_job *)calloc((size_t)ng, sizeof(gen_job));
+    int err = gen ? 0 : -1;
+    for (int t = 0; t < ng && !err; t++) {
+        gen_job *g = &gen[t];
+        g->dets = dets, g->c = c;
+        g->lo = n * t / ng, g->hi = n * (t + 1) / ng;
+        g->E.s = s, g->E.R = R, g->E.W = W, g->E.log2p = log2p, g->E.cutoff = cutoff, g->E.slot = slot;
+        g->E.n_candidates = (uint64_t *)calloc((size_t)nslot, sizeof(uint64_t));
+        g->E.outs = (orc_vec *)calloc((size_t)nslot, sizeof(orc_vec));
+        if (!g->E.n_candidates || !g->E.outs)
+            err = -1;
+    }
+    if (!err) {
+        run_threads(gen_worker, gen, sizeof(gen_job), ng);
+        for (int t = 0; t < ng; t++)
+            if (gen[t].err)
+                err = -1;
+    }
+    if (!err) {
+        int np = nthreads < nslot ? nthreads : nslot;
+        pass_job *pj = (pass_job *)calloc((size_t)np, sizeof(pass_job));
+        if (!pj)
+            err = -1;
+        for (int t = 0; t < np && !err; t++) {
+            pass_job j = {s, refs, e0, gen, ng, nslot, np, t, e_slot, res_slot, 0};
+            pj[t] = j;
+        }
+        if (!err) {
+            run_threads(pass_worker, pj, sizeof(pass_job), np);
+            for (int t = 0; t < np; t++)
+                if (pj[t].err)
+                    err = -1;
+        }
+        free(pj);
+    }
+    if (log2p > 0)
+        for (int k = 0; k < nslot; k++)
+            slot[parts[k]] = -1;
+    for (int t = 0; gen && t < ng; t++) {
+        for (int k = 0; gen[t].E.outs && k < nslot; k++)
+            free(gen[t].E.outs[k].r);
+        free(gen[t].E.outs), free(gen[t].E.n_candidates);
+    }
+    free(gen);
+    return err;
 }
 
 static int cmp_idx_W;
@@ -555,8 +649,8 @@ static int cmp_idx(const void *pa, const void *pb)
 /*
  * Evaluate the PT2 energy restricted to the listed subsets of a 2^log2p
  * split of the external space (parts == NULL: all subsets).  Subsets are
- * processed by nthreads workers; per-subset results are combined in list
- * order, so the result does not depend on the thread count.
+ * taken nthreads at a time; per-subset results are combined in list order,
+ * so the result does not depend on the thread count.
  *
  * Returns 0 on success, -1 on allocation failure, -2 on invalid input
  * (duplicate reference determinants).
@@ -569,6 +663,8 @@ int orc_pt2(const orc_system *s, const uint64_t *dets, const double *c, int64_t 
     orc_zobrist_table(s->norb, R);
     if (nthreads < 1)
         nthreads = 1;
+    if (nthreads > ORC_MAXTHREADS)
+        nthreads = ORC_MAXTHREADS;
 
     /* sorted reference set (input order kept for emission) */
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
@@ -601,26 +697,17 @@ int orc_pt2(const orc_system *s, const uint64_t *dets, const double *c, int64_t 
             all[p] = (uint32_t)p;
         parts = all;
     }
-    orc_result *rp = (orc_result *)calloc((size_t)nparts, sizeof(orc_result));
-    double *ep = (double *)calloc((size_t)nparts, sizeof(double));
-    int nt = nthreads < nparts ? nthreads : nparts;
-    orc_job *jobs = (orc_job *)calloc((size_t)(nt > 0 ? nt : 1), sizeof(orc_job));
-    pthread_t *th = (pthread_t *)calloc((size_t)(nt > 0 ? nt : 1), sizeof(pthread_t));
-    int err = 0;
-    for (int t = 0; t < nt; t++) {
-        orc_job j = {s, dets, c, n, e0, cutoff, log2p, W, R, &refs, parts, nparts, nt, t, ep, rp, 0};
-        jobs[t] = j;
-        if (nt == 1)
-            worker(&jobs[t]);
-        else
-            pthread_create(&th[t], NULL, worker, &jobs[t]);
+    orc_result *rp = (orc_result *)calloc((size_t)(nparts > 0 ? nparts : 1), sizeof(orc_result));
+    double *ep = (double *)calloc((size_t)(nparts > 0 ? nparts : 1), sizeof(double));
+    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * ((size_t)1 << log2p));
+    int err = (rp && ep && slot) ? 0 : -1;
+    for (size_t p = 0; slot && p < ((size_t)1 << log2p); p++)
+        slot[p] = -1;
+    for (int k0 = 0; k0 < nparts && !err; k0 += nthreads) {
+        int nb = nparts - k0 < nthreads ? nparts - k0 : nthreads;
+        err = run_batch(s, dets, c, n, e0, cutoff, log2p, R, &refs, slot, parts + k0, nb, nthreads, ep + k0,
+                        rp + k0);
     }
-    if (nt > 1)
-        for (int t = 0; t < nt; t++)
-            pthread_join(th[t], NULL);
-    for (int t = 0; t < nt; t++)
-        if (jobs[t].err)
-            err = -1;
 
     result_init(total);
     double sum = 0.0, comp = 0.0;
@@ -641,7 +728,28 @@ int orc_pt2(const orc_system *s, const uint64_t *dets, const double *c, int64_t 
         total->key_sum += rp[k].key_sum;
     }
     total->e_pt2 = sum + comp;
-    free(all), free(rp), free(ep), free(jobs), free(th), free(idx), free(rk), free(rc);
+    free(all), free(rp), free(ep), free(slot), free(idx), free(rk), free(rc);
+    return err;
+}
+
+/* Records of one subset in emission order (single thread). */
+static int emit_one(const orc_system *s, const uint64_t *dets, const double *c, int64_t n, double cutoff,
+                    int log2p, uint32_t part, orc_vec *v, uint64_t *ncand)
+{
+    int W = orc_key_words(s->norb);
+    uint64_t R[2 * ORC_MAXORB];
+    orc_zobrist_table(s->norb, R);
+    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * ((size_t)1 << log2p));
+    if (!slot)
+        return -1;
+    for (size_t p = 0; p < ((size_t)1 << log2p); p++)
+        slot[p] = -1;
+    slot[part] = 0;
+    orc_emit_ctx E = {s, R, W, log2p, cutoff, slot, ncand, v};
+    int err = 0;
+    for (int64_t i = 0; i < n && !err; i++)
+        err = expand_det(&E, dets + i * W, c[i], (uint64_t)i << 32);
+    free(slot);
     return err;
 }
 
@@ -654,48 +762,36 @@ int64_t orc_emit(const orc_system *s, const uint64_t *dets, const double *c, int
                  uint32_t part, uint64_t *keys_out, double *vals_out, int64_t cap)
 {
     int W = orc_key_words(s->norb);
-    uint64_t R[2 * ORC_MAXORB];
-    orc_zobrist_table(s->norb, R);
-    size_t np = (size_t)1 << log2p;
-    unsigned char *keep = (unsigned char *)calloc(np, 1);
-    keep[part] = 1;
-    orc_emit_ctx E = {s, R, W, log2p, cutoff, keep, 0};
     orc_vec v = {NULL, 0, 0};
-    for (int64_t i = 0; i < n; i++)
-        if (expand_det(&E, &v, dets + i * W, c[i], (uint64_t)i << 32)) {
-            free(v.r), free(keep);
-            return -1;
-        }
+    uint64_t ncand = 0;
+    if (emit_one(s, dets, c, n, cutoff, log2p, part, &v, &ncand)) {
+        free(v.r);
+        return -1;
+    }
     for (size_t i = 0; i < v.n && (int64_t)i < cap; i++) {
         memcpy(keys_out + i * W, v.r[i].key, sizeof(uint64_t) * W);
         vals_out[i] = v.r[i].v;
     }
     int64_t cnt = (int64_t)v.n;
-    free(v.r), free(keep);
+    free(v.r);
     return cnt;
 }
 
 /*
  * The distinct bitstrings of one subset with their numerators N_a, sorted
- * ascending, and a flag telling whether each is in the reference.  Returns the
- * count (only the first cap are written) or -1 on allocation failure.
+ * ascending.  Returns the count (only the first cap are written) or -1 on
+ * allocation failure.
  */
 int64_t orc_numerators(const orc_system *s, const uint64_t *dets, const double *c, int64_t n, int log2p,
                        uint32_t part, uint64_t *keys_out, double *num_out, int64_t cap)
 {
     int W = orc_key_words(s->norb);
-    uint64_t R[2 * ORC_MAXORB];
-    orc_zobrist_table(s->norb, R);
-    size_t np = (size_t)1 << log2p;
-    unsigned char *keep = (unsigned char *)calloc(np, 1);
-    keep[part] = 1;
-    orc_emit_ctx E = {s, R, W, log2p, 0.0, keep, 0};
     orc_vec v = {NULL, 0, 0};
-    for (int64_t i = 0; i < n; i++)
-        if (expand_det(&E, &v, dets + i * W, c[i], (uint64_t)i << 32)) {
-            free(v.r), free(keep);
-            return -1;
-        }
+    uint64_t ncand = 0;
+    if (emit_one(s, dets, c, n, 0.0, log2p, part, &v, &ncand)) {
+        free(v.r);
+        return -1;
+    }
     qsort(v.r, v.n, sizeof(orc_rec), cmp_rec);
     int64_t cnt = 0;
     size_t i = 0;
@@ -711,7 +807,7 @@ int64_t orc_numerators(const orc_system *s, const uint64_t *dets, const double *
         cnt++;
         i = j;
     }
-    free(v.r), free(keep);
+    free(v.r);
     return cnt;
 }
 

@@ -160,7 +160,6 @@ struct Workspace {
     Alloc A;
     Buf dets, coef;          // device copies of host inputs
     Buf refA, refB;          // reference planes (W keys + FP64 coefficient)
-    int64_t ref_cap = 0;
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -180,7 +179,7 @@ struct Workspace {
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
-        ref_cap = rec_cap = scan_tiles = 0;
+        rec_cap = scan_tiles = 0;
         if (host_small) {
             (void)hipHostFree(host_small);
             host_small = nullptr;
@@ -398,13 +397,10 @@ int prepare_refs(pt2_ctx *c, Workspace &ws, const uint64_t *dets, const double *
         dets = (const uint64_t *)ws.dets.p;
         coeffs = (const double *)ws.coef.p;
     }
-    if (ws.ref_cap < n) {
-        buf_free(ws.A, ws.refA), buf_free(ws.A, ws.refB);
-        if ((rc = buf_alloc(ws.A, ws.refA, planes_bytes(W, n, 8, 8))) ||
-            (rc = buf_alloc(ws.A, ws.refB, planes_bytes(W, n, 8, 8))))
-            return rc;
-        ws.ref_cap = n;
-    }
+    // sized in bytes: a workspace serves contexts of different key widths
+    if ((rc = buf_ensure(ws.A, ws.refA, planes_bytes(W, n, 8, 8))) ||
+        (rc = buf_ensure(ws.A, ws.refB, planes_bytes(W, n, 8, 8))))
+        return rc;
     Small *ds = ws.dsmall();
     HIPCHK(launch_zero_u32(&ds->flags.err, 2, st));
     // plane stride = n: the generation kernel indexes reference planes by nref

@@ -127,3 +127,26 @@ def test_invalid_request_reports_error_at_poll(pt2, reqs):
         ctx.wait(rid)
     assert e.value.code == pt2.PT2_E_INVALID
     ctx.close()
+
+
+def test_workers_reused_across_key_widths(pt2):
+    """Requests of one-word and two-word keys alternate on the scheduler's
+    workers; reference buffers sized for one width must not be reused for a
+    wider one (regression: planes were sized by determinant count)."""
+    systems = []
+    for norb, na, nref, seed in ((20, 5, 3000, 71), (36, 5, 2500, 72)):
+        req = synth.Request(0, na, norb, nref, seed, 0.0)
+        h, eri, dets, c = synth.request_inputs(req)
+        e0 = oracle.Oracle(h, eri, norb, na, na).expectation(dets, c)
+        ctx = pt2.Context(h, eri, norb, na, na, precision="fp32")
+        systems.append((ctx, dets, c, e0, ctx.evaluate(dets, c, e0)))
+    ids = []
+    for j in range(16):
+        ctx, dets, c, e0, _ = systems[j % 2]
+        ids.append((j % 2, ctx.submit(dets, c, e0)))
+    for s, rid in ids:
+        got = systems[s][0].wait(rid)
+        for k in KEYS:
+            assert got[k] == systems[s][4][k], (s, k)
+    for ctx, *_ in systems:
+        ctx.close()
