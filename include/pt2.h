@@ -64,17 +64,30 @@ enum {
 
 enum {
     PT2_FP64 = 0,          /* FP64 integrals and numerator terms                 */
-    PT2_FP32_PAYLOAD = 1   /* FP32 integrals and H_ai c_i terms; N_a, H_aa,
-                              denominators and sums stay FP64                    */
+    PT2_FP32_PAYLOAD = 1,  /* H_ai c_i computed in FP64 and stored rounded to
+                              FP32 (4 bytes less per record and sort pass);
+                              N_a, H_aa, denominators and sums stay FP64         */
+    PT2_FP32_ARITH = 2     /* as PT2_FP32_PAYLOAD, but the integrals are rounded
+                              to FP32 and H_ai c_i is computed in FP32; the
+                              rounding of the integrals is shared by every term,
+                              so the error in E_PT2 grows with the system (about
+                              1e-8 relative at 1e11 terms)                       */
 };
 
 typedef struct {
     uint32_t struct_size;          /* sizeof(pt2_options)                            */
-    int precision;                 /* PT2_FP64 or PT2_FP32_PAYLOAD                   */
+    int precision;                 /* PT2_FP64, PT2_FP32_PAYLOAD or PT2_FP32_ARITH   */
     double cutoff;                 /* drop a term when |H_ai c_i| < cutoff (strict;
                                       Section IV uses 1e-8); 0 keeps every term      */
     uint64_t device_budget_bytes;  /* device memory the engine may hold for
-                                      record buffers; 0 = 80% of free memory         */
+                                      record buffers; 0 = 80% of free memory: for
+                                      pt2_evaluate* free memory at the call plus
+                                      the buffers the context already holds, for
+                                      pt2_submit free memory at pt2_create.  The
+                                      budget sets the hash split, and the split
+                                      sets the summation grouping: for results
+                                      that are bit-identical across calls, fix
+                                      this or log2_partitions                      */
     uint64_t max_partition_bytes;  /* cap on the record buffers of one subset;
                                       0 = the budget                                 */
     int log2_partitions;           /* -1: the planner picks the split; 0 <= k <= 12

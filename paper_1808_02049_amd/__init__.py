@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 PT2_OK, PT2_NOT_READY = 0, 1
 PT2_E_INVALID, PT2_E_NOMEM, PT2_E_DEVICE = -1, -2, -3
 PT2_E_BUSY, PT2_E_SINGULAR, PT2_E_UNKNOWN_REQ = -4, -5, -6
-PT2_FP64, PT2_FP32_PAYLOAD = 0, 1
+PT2_FP64, PT2_FP32_PAYLOAD, PT2_FP32_ARITH = 0, 1, 2
 
 _ERRNAMES = {PT2_E_INVALID: "PT2_E_INVALID", PT2_E_NOMEM: "PT2_E_NOMEM",
              PT2_E_DEVICE: "PT2_E_DEVICE", PT2_E_BUSY: "PT2_E_BUSY",
@@ -170,7 +170,8 @@ class Context:
         self.norb, self.nalpha, self.nbeta = int(norb), int(nalpha), int(nbeta)
         self.W = key_words(self.norb)
         o = default_options()
-        o.precision = {"fp64": PT2_FP64, "fp32": PT2_FP32_PAYLOAD}[precision]
+        o.precision = {"fp64": PT2_FP64, "fp32": PT2_FP32_PAYLOAD,
+                       "fp32-arith": PT2_FP32_ARITH}[precision]
         o.cutoff = float(cutoff)
         o.log2_partitions = int(log2_partitions)
         o.device = int(device)

@@ -467,6 +467,7 @@ struct Job {
     bool host;
     double e0;
     int forced_log2p;              // -1 planner
+    bool live_budget = false;      // plan against free memory now, not at creation
     const uint32_t *parts = nullptr;
     int nparts = 0;
     double *e_parts = nullptr;
@@ -484,7 +485,7 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
 {
     int rc;
     const int Pn = 1 << P.log2p;
-    const int fp32 = c->opt.precision == PT2_FP32_PAYLOAD;
+    const int pm = c->opt.precision;
     if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * Pn * 4)))
         return rc;
     if ((rc = buf_ensure(ws.A, ws.off, (size_t)P.nchunks * P.parts.size() * 8)) ||
@@ -492,7 +493,7 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_count(c->sys, c->L, fp32, refs, nref, P.chunk, P.log2p, cutoff,
+    HIPCHK(launch_count(c->sys, c->L, pm, refs, nref, P.chunk, P.log2p, cutoff,
                         (uint32_t *)ws.cnt.p, P.nchunks, st));
     HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
                              (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
@@ -505,11 +506,19 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
 int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
 {
     const int W = c->W;
-    const int pb = c->opt.precision == PT2_FP32_PAYLOAD ? 4 : 8;
+    const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
     const double total = (double)nref * (double)c->L.nper;
+    // without an explicit budget: 80% of what is free now plus the record
+    // buffers this workspace already holds (they are reused)
+    uint64_t budget = c->budget;
+    if (!c->opt.device_budget_bytes && J.live_budget) {
+        size_t freeb = 0, totalb = 0;
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess)
+            budget = (uint64_t)(0.8 * ((double)freeb + (double)ws.record_bytes()));
+    }
     const double cap_bytes =
-        (double)(c->opt.max_partition_bytes && c->opt.max_partition_bytes < c->budget ? c->opt.max_partition_bytes
-                                                                                      : c->budget);
+        (double)(c->opt.max_partition_bytes && c->opt.max_partition_bytes < budget ? c->opt.max_partition_bytes
+                                                                                  : budget);
     const double cutoff = c->opt.cutoff;
     int k;
     if (J.forced_log2p >= 0)
@@ -586,7 +595,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
 {
     const double t0 = now_ms();
     const int W = c->W;
-    const int fp32 = c->opt.precision == PT2_FP32_PAYLOAD;
+    const int pm = c->opt.precision;
+    const int fp32 = pm != PT2_FP64;  // 4-byte payload plane
     const int pb = fp32 ? 4 : 8;
     int rc;
     Timing tm;
@@ -633,9 +643,9 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
         if (!P.compact)
-            HIPCHK(launch_gen_direct(c->sys, c->L, fp32, refs, J.n, P.chunk, A, st));
+            HIPCHK(launch_gen_direct(c->sys, c->L, pm, refs, J.n, P.chunk, A, st));
         else
-            HIPCHK(launch_gen_compact(c->sys, c->L, fp32, refs, J.n, P.chunk,
+            HIPCHK(launch_gen_compact(c->sys, c->L, pm, refs, J.n, P.chunk,
                                       P.log2p, P.parts[q], c->opt.cutoff,
                                       (const uint64_t *)ws.off.p + (size_t)q * P.nchunks, P.nchunks,
                                       (uint64_t)ws.rec_cap, A, &ds->flags, st));
@@ -819,7 +829,7 @@ class Scheduler {
         r->c.assign(coeffs, coeffs + n);
         r->n = n;
         r->e0 = e0;
-        const int pb = c->opt.precision == PT2_FP32_PAYLOAD ? 4 : 8;
+        const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
         const double total = (double)n * (double)c->L.nper;
         double cap = (double)(c->opt.max_partition_bytes ? std::min<uint64_t>(c->opt.max_partition_bytes, c->budget)
                                                          : c->budget);
@@ -1035,7 +1045,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
             return fail(PT2_E_INVALID, "pt2_options.struct_size mismatch");
         o = *opt;
     }
-    if (o.precision != PT2_FP64 && o.precision != PT2_FP32_PAYLOAD)
+    if (o.precision != PT2_FP64 && o.precision != PT2_FP32_PAYLOAD && o.precision != PT2_FP32_ARITH)
         return fail(PT2_E_INVALID, "unknown precision %d", o.precision);
     if (!(o.cutoff >= 0.0))
         return fail(PT2_E_INVALID, "cutoff must be >= 0");
@@ -1118,7 +1128,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     HIPCHK(hipMemcpy(c->V.p, eri, n4 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->T.p, T.data(), ntri * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->R.p, R.data(), nso * 8, hipMemcpyHostToDevice));
-    if (o.precision == PT2_FP32_PAYLOAD) {
+    if (o.precision == PT2_FP32_ARITH) {
         std::vector<float> h32(n2), V32(n4);
         for (size_t i = 0; i < n2; i++)
             h32[i] = (float)h[i];
@@ -1174,6 +1184,7 @@ PT2_API int pt2_evaluate(pt2_ctx *c, const uint64_t *dets, const double *coeffs,
         return rc;
     Job J{};
     J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = e0, J.forced_log2p = -1;
+    J.live_budget = true;
     return eval_common(c, J, out);
 }
 
@@ -1185,6 +1196,7 @@ PT2_API int pt2_evaluate_device(pt2_ctx *c, const uint64_t *d_dets, const double
         return rc;
     Job J{};
     J.dets = d_dets, J.coeffs = d_coeffs, J.n = n, J.host = false, J.e0 = e0, J.forced_log2p = -1;
+    J.live_budget = true;
     return eval_common(c, J, out);
 }
 

@@ -345,8 +345,22 @@ __device__ inline void store_keys(const Planes &out, int64_t pos, const uint64_t
         pl_put<W>(out, w, pos, key[w]);
 }
 
+// The payload H_ai * c_i: FP64; FP64 arithmetic rounded once to FP32; or
+// FP32 integrals and arithmetic.
+template <int PM>
+__device__ inline void store_pay(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e, double c,
+                                 const Planes &out, int64_t i)
+{
+    if (PM == PM_FP64)
+        ((double *)out.pay)[i] = exc_value<double>(g, s, L, e, s.V, s.h) * c;
+    else if (PM == PM_FP32_PAYLOAD)
+        ((float *)out.pay)[i] = (float)(exc_value<double>(g, s, L, e, s.V, s.h) * c);
+    else
+        ((float *)out.pay)[i] = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c;
+}
+
 // ---------------------------------------------------------------------------
-template <int W, bool F32>
+template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                             int cpd, Planes out)
 {
@@ -360,29 +374,24 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
     const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
     const int64_t base = det * L.nper;
     const double c = g.head->c;
-    const float c32 = (float)c;
     for (int64_t k = lo + threadIdx.x; k < hi; k += GEN_THREADS) {
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
         store_keys<W>(out, base + k, key);
-        if (F32) {
-            float v = exc_value<float>(g, s, L, e, s.V32, s.h32) * c32;
-            ((float *)out.pay)[base + k] = v;
-        } else {
-            double v = exc_value<double>(g, s, L, e, s.V, s.h) * c;
-            ((double *)out.pay)[base + k] = v;
-        }
+        store_pay<PM>(g, s, L, e, c, out, base + k);
     }
 }
 
-template <int W, bool F32>
+// The cutoff test in the precision the term is computed in (FP32 only when
+// the integrals and the arithmetic are FP32).
+template <int W, int PM>
 __device__ inline bool keep_term(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
                                  double cutoff)
 {
     if (cutoff <= 0.0)
         return true;
-    if (F32) {
+    if (PM == PM_FP32_ARITH) {
         float v = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)g.head->c;
         return fabsf(v) >= (float)cutoff;
     }
@@ -392,7 +401,7 @@ __device__ inline bool keep_term(const GenLds &g, const DevSys &s, const ExcLayo
 
 __device__ inline uint32_t part_of(uint64_t z, int log2p) { return log2p == 0 ? 0u : (uint32_t)(z >> (64 - log2p)); }
 
-template <int W, bool F32>
+template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                        int cpd, int log2p, double cutoff, uint32_t *cnt,
                                                        int64_t nchunks)
@@ -414,7 +423,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        if (keep_term<W, F32>(g, s, L, e, cutoff))
+        if (keep_term<W, PM>(g, s, L, e, cutoff))
             atomicAdd(&hist[part_of(z, log2p)], 1u);
     }
     __syncthreads();
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
         cnt[(int64_t)p * nchunks + blockIdx.x] = hist[p];
 }
 
-template <int W, bool F32>
+template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
                                                              int cpd, int log2p, uint32_t part, double cutoff,
                                                              const uint64_t *off, uint64_t cap, Planes out,
@@ -442,7 +451,6 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     uint64_t pos = off[blockIdx.x];
     const double c = g.head->c;
-    const float c32 = (float)c;
     for (int64_t k0 = lo; k0 < hi; k0 += GEN_THREADS) {
         const int64_t k = k0 + threadIdx.x;
         bool keep = false;
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
         if (k < hi) {
             e = decode(g, L, D, k);
             exc_key<W>(g, s.norb, e, key, z);
-            keep = part_of(z, log2p) == part && keep_term<W, F32>(g, s, L, e, cutoff);
+            keep = part_of(z, log2p) == part && keep_term<W, PM>(g, s, L, e, cutoff);
         }
         uint64_t m = __ballot(keep);
         if (lane == 0)
@@ -467,10 +475,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
             uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
             if (p < cap) {
                 store_keys<W>(out, (int64_t)p, key);
-                if (F32)
-                    ((float *)out.pay)[p] = exc_value<float>(g, s, L, e, s.V32, s.h32) * c32;
-                else
-                    ((double *)out.pay)[p] = exc_value<double>(g, s, L, e, s.V, s.h) * c;
+                store_pay<PM>(g, s, L, e, c, out, (int64_t)p);
             } else {
                 atomicOr(&flags->err, ERR_OVERFLOW);
             }
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
         tot[blockIdx.x] = carry;
 }
 
-template <int W, bool F32>
+template <int W, int PM>
 hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
 {
     int cpd = (int)((L.nper + chunk - 1) / chunk);
@@ -517,7 +522,7 @@ hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs,
     if (blocks == 0 || L.nper == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L);
-    hipLaunchKernelGGL((k_gen_direct<W, F32>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, out);
+    hipLaunchKernelGGL((k_gen_direct<W, PM>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, out);
     return hipGetLastError();
 }
 
@@ -529,28 +534,32 @@ size_t gen_lds_bytes(const ExcLayout &L)
     return lds_layout(L, &a, &b, &c, &d, &e, &f);
 }
 
-#define PT2_DISPATCH(W_, F32_, CALL)                                                                   \
-    switch ((W_) * 2 + ((F32_) ? 1 : 0)) {                                                             \
-    case 2: return CALL(1, false);                                                                     \
-    case 3: return CALL(1, true);                                                                      \
-    case 4: return CALL(2, false);                                                                     \
-    case 5: return CALL(2, true);                                                                      \
-    case 6: return CALL(3, false);                                                                     \
-    case 7: return CALL(3, true);                                                                      \
-    case 8: return CALL(4, false);                                                                     \
-    case 9: return CALL(4, true);                                                                      \
+#define PT2_DISPATCH(W_, PM_, CALL)                                                                    \
+    switch ((W_) * 3 + (PM_)) {                                                                        \
+    case 3: return CALL(1, 0);                                                                         \
+    case 4: return CALL(1, 1);                                                                         \
+    case 5: return CALL(1, 2);                                                                         \
+    case 6: return CALL(2, 0);                                                                         \
+    case 7: return CALL(2, 1);                                                                         \
+    case 8: return CALL(2, 2);                                                                         \
+    case 9: return CALL(3, 0);                                                                         \
+    case 10: return CALL(3, 1);                                                                        \
+    case 11: return CALL(3, 2);                                                                        \
+    case 12: return CALL(4, 0);                                                                        \
+    case 13: return CALL(4, 1);                                                                        \
+    case 14: return CALL(4, 2);                                                                        \
     default: return hipErrorInvalidValue;                                                              \
     }
 
-hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
 {
 #define CALL(W, F) gen_direct_t<W, F>(s, L, refs, nref, chunk, out, st)
-    PT2_DISPATCH(s.W, fp32, CALL)
+    PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }
 
 namespace {
-template <int W, bool F32>
+template <int W, int PM>
 hipError_t count_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref,
                    int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st)
 {
@@ -560,12 +569,12 @@ hipError_t count_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int6
     if (nchunks == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * ((size_t)1 << log2p);
-    hipLaunchKernelGGL((k_count<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs,
+    hipLaunchKernelGGL((k_count<W, PM>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs,
                        nref, chunk, cpd, log2p, cutoff, cnt, nchunks);
     return hipGetLastError();
 }
 
-template <int W, bool F32>
+template <int W, int PM>
 hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
                          int64_t nchunks, uint64_t cap, Planes out, Flags *flags, hipStream_t st)
 {
@@ -575,26 +584,26 @@ hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs
     if (nchunks == 0)
         return hipSuccess;
     size_t lds = gen_lds_bytes(L) + sizeof(uint32_t) * (GEN_THREADS / 64);
-    hipLaunchKernelGGL((k_gen_compact<W, F32>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
+    hipLaunchKernelGGL((k_gen_compact<W, PM>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
                         hipStream_t st)
 {
 #define CALL(W, F) count_t<W, F>(s, L, refs, nref, chunk, log2p, cutoff, cnt, nchunks, st)
-    PT2_DISPATCH(s.W, fp32, CALL)
+    PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }
 
-hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref, int64_t chunk, int log2p, uint32_t part,
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk, int log2p, uint32_t part,
                               double cutoff, const uint64_t *off, int64_t nchunks, uint64_t cap, Planes out,
                               Flags *flags, hipStream_t st)
 {
 #define CALL(W, F) \
     gen_compact_t<W, F>(s, L, refs, nref, chunk, log2p, part, cutoff, off, nchunks, cap, out, flags, st)
-    PT2_DISPATCH(s.W, fp32, CALL)
+    PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }
 

@@ -8,6 +8,10 @@
 namespace pt2 {
 
 constexpr int MAXW = 4;        // 2*norb <= 256 bits
+// Payload modes (the values of pt2_options.precision)
+constexpr int PM_FP64 = 0;          // FP64 integrals, arithmetic and payload
+constexpr int PM_FP32_PAYLOAD = 1;  // FP64 arithmetic, payload rounded once to FP32
+constexpr int PM_FP32_ARITH = 2;    // FP32 integrals, arithmetic and payload
 constexpr int MAXORB = 128;
 constexpr int SORT_THREADS = 256;
 #ifndef PT2_SORT_ITEMS
@@ -170,16 +174,16 @@ inline int64_t gen_nchunks(const ExcLayout &L, int64_t nref, int64_t chunk)
 size_t gen_lds_bytes(const ExcLayout &L);
 // Direct generation: every term of every reference, record index
 // det*nper + k.  Requires no cutoff and a single subset.
-hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                              int64_t chunk, Planes out, hipStream_t st);
 // Count pass: cnt[p * nchunks + chunk] = kept terms of chunk in subset p.
-hipError_t launch_count(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                         int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st);
 // Exclusive scan of cnt[p][*] into off[p][*] for each listed subset; tot[k] = N of parts[k].
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
                              uint64_t *off, uint64_t *tot, hipStream_t st);
 // Compacting generation of subset `part` (offsets from launch_chunk_scan).
-hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int fp32, const Planes &refs, int64_t nref,
+hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                               int64_t chunk, int log2p, uint32_t part, double cutoff, const uint64_t *off,
                               int64_t nchunks, uint64_t cap, Planes out, Flags *flags, hipStream_t st);
 

@@ -56,6 +56,7 @@ def test_c3_full_fp64_and_fp32_forms(c3):
     d = torch.from_numpy(c3["dets"].view(np.int64)).cuda()
     cc = torch.from_numpy(c3["c"]).cuda()
     got = c3["ctx"].evaluate(d, cc, c3["e0"])
+    c3["ctx"].close()          # free its record buffers before the FP32 context plans
     print({k: got[k] for k in ("e_pt2", "n_contrib", "n_unique", "n_external", "n_in_ref_hit",
                                "n_partitions", "ms_total", "ms_gen", "ms_sort", "ms_reduce")},
           flush=True)
@@ -68,7 +69,8 @@ def test_c3_full_fp64_and_fp32_forms(c3):
     ctx32 = c3["pt2"].Context(c3["h"], c3["eri"], w.norb, w.nalpha, w.nbeta, precision="fp32")
     got32 = ctx32.evaluate(d, cc, c3["e0"])
     ctx32.close()
-    print("fp32 form", got32["e_pt2"], got32["e_pt2"] - got["e_pt2"], got32["ms_total"], flush=True)
+    print("fp32 payload form", got32["e_pt2"], got32["e_pt2"] - got["e_pt2"], got32["ms_total"],
+          got32["n_partitions"], flush=True)
     assert abs(got32["e_pt2"] - got["e_pt2"]) <= 1e-6
     for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
         assert got32[k] == got[k]

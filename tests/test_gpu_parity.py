@@ -166,6 +166,36 @@ def test_c1_fp32_payload_form(pt2, c1):
     ctx.close()
 
 
+def test_c1_fp32_payload_records_are_rounded_fp64_terms(pt2, c1):
+    """The FP32-payload form computes H_ai c_i in FP64 and rounds it once:
+    every stored term is the oracle's term rounded to FP32 (within one FP32
+    ulp, as the FP64 sums may differ in their last bits)."""
+    order = sort_by_key(c1["dets"])
+    dets, c = c1["dets"][order], c1["c"][order]
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, precision="fp32")
+    gk, gv = ctx.dump_records(dets, c)
+    ctx.close()
+    ok, ov = c1["O"].emit(dets, c)
+    assert np.array_equal(gk, ok)
+    o32 = ov.astype(np.float32)
+    assert np.all(gv.astype(np.float32) == gv)               # stored as FP32
+    ulp = np.spacing(np.abs(o32)).astype(np.float64)
+    assert np.all(np.abs(gv - o32.astype(np.float64)) <= ulp)
+    assert np.mean(gv == o32.astype(np.float64)) > 0.99
+
+
+def test_c1_fp32_arith_form(pt2, c1):
+    """FP32 integrals and arithmetic: error bounded relative to E_PT2."""
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, precision="fp32-arith")
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    ctx.close()
+    ref = c1["ref"]
+    print("fp32-arith dE", got["e_pt2"] - ref["e_pt2"], flush=True)
+    assert abs(got["e_pt2"] - ref["e_pt2"]) <= 1e-6 * abs(ref["e_pt2"])
+    for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
+        assert got[k] == ref[k]
+
+
 def test_c1_cutoff(pt2, c1):
     k, v = c1["O"].emit(c1["dets"], c1["c"])
     cut = float(np.quantile(np.abs(v), 0.4))
