@@ -109,6 +109,7 @@ def serving_bench(args):
           f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     keep = []          # contexts stay resident until the end (no device-wide free mid-run)
     lock = threading.Lock()
+    progress = {"done": 0, "t0": time.perf_counter()}
 
     def one(j):
         r = reqs[j]
@@ -119,6 +120,10 @@ def serving_bench(args):
         done = time.perf_counter()
         with lock:
             keep.append(ctx)
+            progress["done"] += 1
+            if progress["done"] % 10 == 0:
+                print(f"bench: {progress['done']} requests done, {done - progress['t0']:.1f} s",
+                      file=sys.stderr, flush=True)
         return res, done
 
     pool = cf.ThreadPoolExecutor(max_workers=64)

@@ -454,6 +454,7 @@ double subset_bytes(int W, int pb, int topb, double n)
 struct Plan {
     int log2p = 0;
     bool compact = false;
+    bool target = false;  // targeted count/generation, one determinant per chunk
     int64_t chunk = 0, nchunks = 0;
     std::vector<uint32_t> parts;
     std::vector<uint64_t> sizes;  // records per listed subset
@@ -493,8 +494,11 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_count(c->sys, c->L, pm, refs, nref, P.chunk, P.log2p, cutoff,
-                        (uint32_t *)ws.cnt.p, P.nchunks, st));
+    if (P.target && cutoff <= 0.0)
+        HIPCHK(launch_count_target(c->sys, c->L, refs, nref, P.log2p, (uint32_t *)ws.cnt.p, st));
+    else
+        HIPCHK(launch_count(c->sys, c->L, pm, refs, nref, P.chunk, P.log2p, cutoff,
+                            (uint32_t *)ws.cnt.p, P.nchunks, st));
     HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
                              (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
     tot_out.assign(P.parts.size(), 0);
@@ -553,9 +557,16 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
             P.structural = P.sizes;
             return PT2_OK;
         }
-        const int64_t max_chunks = std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 23, ((int64_t)1 << 27) >> k));
-        P.chunk = gen_chunk(c->L, nref, max_chunks);
-        P.nchunks = gen_nchunks(c->L, nref, P.chunk);
+        P.target = target_ok(c->L, nref, k);
+        if (P.target) {
+            P.chunk = std::max<int64_t>(c->L.nper, 1);
+            P.nchunks = nref;
+        } else {
+            const int64_t max_chunks =
+                std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 23, ((int64_t)1 << 27) >> k));
+            P.chunk = gen_chunk(c->L, nref, max_chunks);
+            P.nchunks = gen_nchunks(c->L, nref, P.chunk);
+        }
         int rc;
         std::vector<uint64_t> tot;
         if (cutoff > 0.0) {
@@ -644,6 +655,10 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         if (!P.compact)
             HIPCHK(launch_gen_direct(c->sys, c->L, pm, refs, J.n, P.chunk, A, st));
+        else if (P.target)
+            HIPCHK(launch_gen_target(c->sys, c->L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
+                                     (const uint64_t *)ws.off.p + (size_t)q * P.nchunks,
+                                     (const uint64_t *)ws.tot.p + q, A, &ds->flags, st));
         else
             HIPCHK(launch_gen_compact(c->sys, c->L, pm, refs, J.n, P.chunk,
                                       P.log2p, P.parts[q], c->opt.cutoff,
@@ -740,7 +755,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     if (err & ERR_BOUNDS)
         return fail(PT2_E_DEVICE, "radix scatter destination out of range");
     if (err & ERR_OVERFLOW)
-        return fail(PT2_E_DEVICE, "compacted generation exceeded its planned range");
+        return fail(PT2_E_DEVICE, "generation did not match the count pass");
     // combine subsets in index order
     double sum = 0.0, comp = 0.0;
     for (size_t q = 0; q < P.parts.size(); q++) {
@@ -869,6 +884,14 @@ class Scheduler {
         c->inflight--;
         all_.erase(it);
         return rc;
+    }
+
+    // projected bytes of the requests running on a device
+    double held(int dev)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = in_use_.find(dev);
+        return it == in_use_.end() ? 0.0 : it->second;
     }
 
     int inflight(pt2_ctx *c)
@@ -1100,7 +1123,10 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     }
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    c->budget = o.device_budget_bytes ? o.device_budget_bytes : (uint64_t)(0.8 * (double)freeb);
+    // memory the scheduler's running requests hold now is theirs only until
+    // they finish: count it as available, admission keeps the sum in bounds
+    c->budget = o.device_budget_bytes ? o.device_budget_bytes
+                                      : (uint64_t)(0.8 * ((double)freeb + Scheduler::get().held(o.device)));
 
     // resident Hamiltonian
     const size_t n2 = n * n, n4 = n2 * n2, nso = 2 * n, ntri = nso * (nso + 1) / 2;

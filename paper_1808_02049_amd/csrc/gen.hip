@@ -66,6 +66,12 @@ __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, 
     return o;
 }
 
+__host__ __device__ inline size_t gen_lds_bytes_dev(const ExcLayout &L)
+{
+    size_t a, b, c, d, e, f;
+    return lds_layout(L, &a, &b, &c, &d, &e, &f);
+}
+
 __device__ inline GenLds carve(char *base, const ExcLayout &L)
 {
     size_t a, b, c, d, e, f;
@@ -514,6 +520,347 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
         tot[blockIdx.x] = carry;
 }
 
+// ---------------------------------------------------------------------------
+// Targeted counting and generation for a 2^k hash split (one workgroup per
+// reference determinant).
+//
+// The subset of a candidate is top_k(z), z = z(D) ^ (table words of the
+// flipped spin-orbitals), and top_k is XOR-linear.  Doubles split into an
+// outer and an inner part whose words combine by XOR:
+//   same-spin doubles:  outer = occupied pair (r, s), inner = virtual pair (a, b)
+//   alpha-beta doubles: outer = alpha single r -> a, inner = beta single s -> b
+// so the inner parts completing outer part o into subset p are exactly those
+// with top_k(h_inner) == p ^ top_k(z(D) ^ h_outer(o)).  The inner parts are
+// bucketed by top_k(h_inner) in LDS, each bucket in ascending index order,
+// and only the matching bucket of every outer part is walked: the work per
+// subset is the subset's own terms instead of every candidate.  Singles are
+// few and are filtered.
+
+struct Tgt {
+    uint32_t *bstart;  // [B + 1] bucket counts, then starts
+    uint32_t *bfill;   // [B] fill cursors
+    uint16_t *blist;   // [max inner] inner indices grouped by bucket
+    uint16_t *tgt;     // [max outer] matching bucket of each outer part
+    uint32_t *pre;     // [max outer + 1] prefix of matching inner counts
+    uint32_t *wsum;    // [GEN_THREADS / 64]
+};
+
+__host__ __device__ inline void tgt_sizes(const ExcLayout &L, int *max_in, int *max_out)
+{
+    int a = L.nvpa > L.nvpb ? L.nvpa : L.nvpb;
+    *max_in = a > (int)L.nSb ? a : (int)L.nSb;
+    int b = L.nopa > L.nopb ? L.nopa : L.nopb;
+    *max_out = b > (int)L.nSa ? b : (int)L.nSa;
+}
+
+__host__ __device__ inline size_t tgt_lds_layout(const ExcLayout &L, int log2p, size_t *o)
+{
+    int mi, mo;
+    tgt_sizes(L, &mi, &mo);
+    const size_t B = (size_t)1 << log2p;
+    size_t x = 0;
+    o[0] = x, x = align16(x + 4 * (B + 1));
+    o[1] = x, x = align16(x + 4 * B);
+    o[2] = x, x = align16(x + 2 * (size_t)(mi > 0 ? mi : 1));
+    o[3] = x, x = align16(x + 2 * (size_t)(mo > 0 ? mo : 1));
+    o[4] = x, x = align16(x + 4 * ((size_t)mo + 1));
+    o[5] = x, x = align16(x + 4 * (GEN_THREADS / 64));
+    return x;
+}
+
+__device__ inline Tgt carve_tgt(char *base, const ExcLayout &L, int log2p)
+{
+    size_t o[6];
+    tgt_lds_layout(L, log2p, o);
+    Tgt t;
+    t.bstart = (uint32_t *)(base + o[0]);
+    t.bfill = (uint32_t *)(base + o[1]);
+    t.blist = (uint16_t *)(base + o[2]);
+    t.tgt = (uint16_t *)(base + o[3]);
+    t.pre = (uint32_t *)(base + o[4]);
+    t.wsum = (uint32_t *)(base + o[5]);
+    return t;
+}
+
+__device__ inline uint32_t top_bits(uint64_t z, int log2p) { return (uint32_t)(z >> (64 - log2p)); }
+
+// In-place exclusive scan of a[0..n) (block-wide); returns the total.
+__device__ uint32_t block_scan_excl(uint32_t *a, int n, uint32_t *wsum)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + GEN_THREADS - 1) / GEN_THREADS;
+    const int lo = tid * per, hi = lo + per < n ? lo + per : n;
+    uint32_t loc = 0;
+    for (int i = lo; i < hi; i++)
+        loc += a[i];
+    uint32_t x = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        wsum[wave] = x;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+    for (int w = 0; w < GEN_THREADS / 64; w++) {
+        const uint32_t t = wsum[w];
+        wpre += w < wave ? t : 0u;
+        tot += t;
+    }
+    uint32_t run = wpre + x - loc;
+    for (int i = lo; i < hi; i++) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Hash words of the inner / outer parts (kind 2, 3: spin sp; kind 4: alpha-beta).
+__device__ inline uint64_t inner_hash(const GenLds &g, const ExcLayout &L, int norb, int kind, int q)
+{
+    const GenHead *H = g.head;
+    if (kind == 4) {
+        const int oj = q / L.vb, vj = q - oj * L.vb;
+        return H->R[H->occ[1][oj]] ^ H->R[H->vir[1][vj]];
+    }
+    const int sp = kind - 2, off = sp == 0 ? norb : 0;
+    const uint16_t vp = sp == 0 ? g.vp[0][q] : g.vp[1][q];
+    return H->R[off + H->vir[sp][vp & 255]] ^ H->R[off + H->vir[sp][vp >> 8]];
+}
+
+__device__ inline uint64_t outer_hash(const GenLds &g, const ExcLayout &L, int norb, int kind, int o)
+{
+    const GenHead *H = g.head;
+    if (kind == 4) {
+        const int oi = o / L.va, vi = o - oi * L.va;
+        return H->R[norb + H->occ[0][oi]] ^ H->R[norb + H->vir[0][vi]];
+    }
+    const int sp = kind - 2, off = sp == 0 ? norb : 0;
+    const uint16_t op = sp == 0 ? g.op[0][o] : g.op[1][o];
+    return H->R[off + H->occ[sp][op & 255]] ^ H->R[off + H->occ[sp][op >> 8]];
+}
+
+__device__ inline int n_inner(const ExcLayout &L, int kind) { return kind == 2 ? L.nvpa : kind == 3 ? L.nvpb : (int)L.nSb; }
+__device__ inline int n_outer(const ExcLayout &L, int kind) { return kind == 2 ? L.nopa : kind == 3 ? L.nopb : (int)L.nSa; }
+
+// Bucket counts (and, if fill, the bucket lists in ascending index order) of
+// the inner parts of one kind.
+__device__ void build_buckets(const GenLds &g, const Tgt &t, const ExcLayout &L, int norb, int kind, int log2p,
+                              bool fill)
+{
+    const int tid = threadIdx.x, B = 1 << log2p, ni = n_inner(L, kind);
+    for (int b = tid; b <= B; b += GEN_THREADS)
+        t.bstart[b] = 0;
+    __syncthreads();
+    for (int q = tid; q < ni; q += GEN_THREADS)
+        atomicAdd(&t.bstart[top_bits(inner_hash(g, L, norb, kind, q), log2p)], 1u);
+    __syncthreads();
+    if (!fill)
+        return;
+    block_scan_excl(t.bstart, B + 1, t.wsum);
+    for (int b = tid; b < B; b += GEN_THREADS)
+        t.bfill[b] = t.bstart[b];
+    __syncthreads();
+    for (int q = tid; q < ni; q += GEN_THREADS) {
+        const uint32_t slot = atomicAdd(&t.bfill[top_bits(inner_hash(g, L, norb, kind, q), log2p)], 1u);
+        t.blist[slot] = (uint16_t)q;
+    }
+    __syncthreads();
+    // the fill order above is arbitrary: sort every bucket (they are small)
+    for (int b = tid; b < B; b += GEN_THREADS) {
+        const uint32_t lo = t.bstart[b], hi = t.bstart[b + 1];
+        for (uint32_t i = lo + 1; i < hi; i++) {
+            const uint16_t v = t.blist[i];
+            uint32_t j = i;
+            while (j > lo && t.blist[j - 1] > v) {
+                t.blist[j] = t.blist[j - 1];
+                j--;
+            }
+            t.blist[j] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, int kind, int o, int q)
+{
+    Exc e;
+    e.kind = kind;
+    if (kind == 4) {
+        e.oi = o / L.va, e.vi = o - e.oi * L.va;
+        e.oj = q / L.vb, e.vj = q - e.oj * L.vb;
+    } else {
+        const int sp = kind - 2;
+        const uint16_t op = sp == 0 ? g.op[0][o] : g.op[1][o];
+        const uint16_t vp = sp == 0 ? g.vp[0][q] : g.vp[1][q];
+        e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
+    }
+    return e;
+}
+
+// One block-wide step of compacted emission: threads with have == true hold
+// a candidate; kept ones are written at consecutive positions from pos.
+template <int W, int PM>
+__device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayout &L, bool have, const Exc &e,
+                                 bool filter, int log2p, uint32_t part, double cutoff, uint64_t &pos,
+                                 uint64_t end, const Planes &out, Flags *flags, uint32_t *wtot, bool &bad)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t key[W], z = 0;
+    bool keep = false;
+    if (have) {
+        exc_key<W>(g, s.norb, e, key, z);
+        const bool in = part_of(z, log2p) == part;
+        if (!in && !filter)
+            bad = true;  // a walked candidate outside the subset: bucketing is inconsistent
+        keep = in && keep_term<W, PM>(g, s, L, e, cutoff);
+    }
+    const uint64_t m = __ballot(keep);
+    if (lane == 0)
+        wtot[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+    for (int w = 0; w < GEN_THREADS / 64; w++) {
+        const uint32_t t = wtot[w];
+        woff += w < wave ? t : 0u;
+        btot += t;
+    }
+    if (keep) {
+        const uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
+        if (p < end) {
+            store_keys<W>(out, (int64_t)p, key);
+            store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
+        } else {
+            atomicOr(&flags->err, ERR_OVERFLOW);
+        }
+    }
+    pos += btot;
+    __syncthreads();
+}
+
+template <int W, int PM>
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
+                                                            int log2p, uint32_t part, double cutoff,
+                                                            const uint64_t *off, const uint64_t *tot, Planes out,
+                                                            Flags *flags)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    const int64_t det = blockIdx.x;
+    const int tid = threadIdx.x;
+    det_setup<W>(g, s, L, refs, det);
+    const DivConsts D = div_consts(L);
+    uint64_t pos = off[det];
+    const uint64_t end = det + 1 < nref ? off[det + 1] : *tot;
+    const uint64_t zp = g.head->z;
+    bool bad = false;
+    // singles: filtered
+    for (int64_t k0 = 0; k0 < L.o2; k0 += GEN_THREADS) {
+        const int64_t k = k0 + tid;
+        Exc e;
+        const bool have = k < L.o2;
+        if (have)
+            e = decode(g, L, D, k);
+        emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad);
+    }
+    // doubles: alpha-alpha, beta-beta, alpha-beta
+    for (int kind = 2; kind <= 4; kind++) {
+        const int no = n_outer(L, kind);
+        if (no == 0 || n_inner(L, kind) == 0)
+            continue;
+        build_buckets(g, t, L, s.norb, kind, log2p, true);
+        for (int o = tid; o < no; o += GEN_THREADS) {
+            const uint32_t b = part ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p);
+            t.tgt[o] = (uint16_t)b;
+            t.pre[o] = t.bstart[b + 1] - t.bstart[b];
+        }
+        if (tid == 0)
+            t.pre[no] = 0;
+        __syncthreads();
+        const uint32_t T = block_scan_excl(t.pre, no + 1, t.wsum);
+        for (uint32_t f0 = 0; f0 < T; f0 += GEN_THREADS) {
+            const uint32_t f = f0 + tid;
+            const bool have = f < T;
+            Exc e;
+            if (have) {
+                // outer part: the last o with pre[o] <= f
+                int lo = 0, hi = no;  // pre[lo] <= f < pre[hi] (pre[no] = T)
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (t.pre[mid] <= f)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                const int q = t.blist[t.bstart[t.tgt[lo]] + (f - t.pre[lo])];
+                e = make_exc(g, L, kind, lo, q);
+            }
+            emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad);
+        }
+        __syncthreads();
+    }
+    if (bad || (tid == 0 && pos != end))
+        atomicOr(&flags->err, ERR_OVERFLOW);
+}
+
+// Subset counts of every reference determinant (cutoff 0): cnt[p * nref + det].
+template <int W>
+__global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
+                                                              int log2p, uint32_t *cnt)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    const int64_t det = blockIdx.x;
+    const int tid = threadIdx.x, B = 1 << log2p;
+    uint32_t *hist = t.bfill;  // [B]
+    det_setup<W>(g, s, L, refs, det);
+    const DivConsts D = div_consts(L);
+    const uint64_t zp = g.head->z;
+    for (int b = tid; b < B; b += GEN_THREADS)
+        hist[b] = 0;
+    __syncthreads();
+    for (int64_t k = tid; k < L.o2; k += GEN_THREADS) {
+        const Exc e = decode(g, L, D, k);
+        uint64_t key[W], z;
+        exc_key<W>(g, s.norb, e, key, z);
+        atomicAdd(&hist[top_bits(z, log2p)], 1u);
+    }
+    for (int kind = 2; kind <= 4; kind++) {
+        const int no = n_outer(L, kind), ni = n_inner(L, kind);
+        if (no == 0 || ni == 0)
+            continue;
+        if (B <= ni) {
+            // bucket counts, then every (outer part, bucket) pair
+            build_buckets(g, t, L, s.norb, kind, log2p, false);
+            const int64_t np = (int64_t)no * B;
+            for (int64_t x = tid; x < np; x += GEN_THREADS) {
+                const int o = (int)(x >> log2p), b = (int)(x & (B - 1));
+                const uint32_t c = t.bstart[b];
+                if (c)
+                    atomicAdd(&hist[b ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p)], c);
+            }
+        } else {
+            // fewer inner parts than subsets: every pair
+            const int64_t np = (int64_t)no * ni;
+            for (int64_t x = tid; x < np; x += GEN_THREADS) {
+                const int o = (int)(x / ni), q = (int)(x - (int64_t)o * ni);
+                const uint64_t z = zp ^ outer_hash(g, L, s.norb, kind, o) ^ inner_hash(g, L, s.norb, kind, q);
+                atomicAdd(&hist[top_bits(z, log2p)], 1u);
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int b = tid; b < B; b += GEN_THREADS)
+        cnt[(int64_t)b * nref + det] = hist[b];
+}
+
 template <int W, int PM>
 hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk, Planes out, hipStream_t st)
 {
@@ -532,6 +879,18 @@ size_t gen_lds_bytes(const ExcLayout &L)
 {
     size_t a, b, c, d, e, f;
     return lds_layout(L, &a, &b, &c, &d, &e, &f);
+}
+
+size_t target_lds_bytes(const ExcLayout &L, int log2p)
+{
+    size_t o[6];
+    return gen_lds_bytes(L) + tgt_lds_layout(L, log2p, o);
+}
+
+bool target_ok(const ExcLayout &L, int64_t nref, int log2p)
+{
+    return log2p >= 1 && log2p <= 12 && target_lds_bytes(L, log2p) <= 65536 &&
+           ((int64_t)1 << log2p) * nref <= ((int64_t)1 << 30);
 }
 
 #define PT2_DISPATCH(W_, PM_, CALL)                                                                    \
@@ -587,6 +946,30 @@ hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs
     hipLaunchKernelGGL((k_gen_compact<W, PM>), dim3((unsigned)nchunks), dim3(GEN_THREADS), lds, st, s, L, refs, nref, chunk, cpd, log2p, part, cutoff, off, cap, out, flags);
     return hipGetLastError();
 }
+template <int W>
+hipError_t count_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                          uint32_t *cnt, hipStream_t st)
+{
+    if (nref == 0)
+        return hipSuccess;
+    const size_t lds = target_lds_bytes(L, log2p);
+    hipLaunchKernelGGL((k_count_target<W>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
+                       log2p, cnt);
+    return hipGetLastError();
+}
+
+template <int W, int PM>
+hipError_t gen_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                        uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot, Planes out,
+                        Flags *flags, hipStream_t st)
+{
+    if (nref == 0)
+        return hipSuccess;
+    const size_t lds = target_lds_bytes(L, log2p);
+    hipLaunchKernelGGL((k_gen_target<W, PM>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
+                       log2p, part, cutoff, off, tot, out, flags);
+    return hipGetLastError();
+}
 }  // namespace
 
 hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
@@ -603,6 +986,31 @@ hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int pm, const
 {
 #define CALL(W, F) \
     gen_compact_t<W, F>(s, L, refs, nref, chunk, log2p, part, cutoff, off, nchunks, cap, out, flags, st)
+    PT2_DISPATCH(s.W, pm, CALL)
+#undef CALL
+}
+
+hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                               uint32_t *cnt, hipStream_t st)
+{
+    if (!target_ok(L, nref, log2p))
+        return hipErrorInvalidValue;
+    switch (s.W) {
+    case 1: return count_target_t<1>(s, L, refs, nref, log2p, cnt, st);
+    case 2: return count_target_t<2>(s, L, refs, nref, log2p, cnt, st);
+    case 3: return count_target_t<3>(s, L, refs, nref, log2p, cnt, st);
+    case 4: return count_target_t<4>(s, L, refs, nref, log2p, cnt, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
+                             int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
+                             Planes out, Flags *flags, hipStream_t st)
+{
+    if (!target_ok(L, nref, log2p))
+        return hipErrorInvalidValue;
+#define CALL(W, F) gen_target_t<W, F>(s, L, refs, nref, log2p, part, cutoff, off, tot, out, flags, st)
     PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }

@@ -179,6 +179,16 @@ hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const 
 // Count pass: cnt[p * nchunks + chunk] = kept terms of chunk in subset p.
 hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                         int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st);
+// Targeted form of the two passes above for a 2^k split (k >= 1), one
+// reference determinant per chunk (chunk = nper, nchunks = nref): the count
+// needs cutoff 0; generation walks only the terms of the subset.
+bool target_ok(const ExcLayout &L, int64_t nref, int log2p);
+size_t target_lds_bytes(const ExcLayout &L, int log2p);
+hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                               uint32_t *cnt, hipStream_t st);
+hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
+                             int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
+                             Planes out, Flags *flags, hipStream_t st);
 // Exclusive scan of cnt[p][*] into off[p][*] for each listed subset; tot[k] = N of parts[k].
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
                              uint64_t *off, uint64_t *tot, hipStream_t st);

@@ -282,20 +282,37 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
     const int64_t rem = n - base;
     const int tile_n = rem < SORT_TILE ? (int)rem : SORT_TILE;
 
+    // plane w of the tile's records, in input order (the digit plane is
+    // already in registers)
+    auto load_plane = [&](int w, uint64_t(&v)[SORT_ITEMS]) {
+#pragma unroll
+        for (int j = 0; j < SORT_ITEMS; j++) {
+            const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
+            uint64_t x = 0;
+            if (w == word)
+                x = kw[j];
+            else if (idx < n)
+                x = w < W ? pl_get<W>(in, w, idx)
+                          : (PB == 8 ? ((const uint64_t *)in.pay)[idx]
+                                     : (uint64_t)((const uint32_t *)in.pay)[idx]);
+            v[j] = x;
+        }
+    };
+    uint64_t cur[SORT_ITEMS];
+    load_plane(0, cur);
+
 #pragma unroll
     for (int w = 0; w < W + 1; w++) {
+        // the next plane's loads are in flight while this one is staged
+        uint64_t nxt[SORT_ITEMS];
+        if (w < W)
+            load_plane(w + 1, nxt);
+        uint64_t(&cv)[SORT_ITEMS] = cur;
 #pragma unroll
         for (int j = 0; j < SORT_ITEMS; j++) {
             const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
             if (idx < n) {
-                uint64_t v;
-                if (w == word)
-                    v = kw[j];
-                else if (w < W)
-                    v = pl_get<W>(in, w, idx);
-                else
-                    v = PB == 8 ? ((const uint64_t *)in.pay)[idx] : (uint64_t)((const uint32_t *)in.pay)[idx];
-                s_stage[lpos[j]] = v;
+                s_stage[lpos[j]] = cv[j];
                 if (w == 0)
                     s_dig[lpos[j]] = (uint8_t)((kw[j] >> shift) & 255u);
             }
@@ -316,6 +333,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
                 ((uint32_t *)out.pay)[dst] = (uint32_t)v;
         }
         __syncthreads();
+        if (w < W) {
+#pragma unroll
+            for (int j = 0; j < SORT_ITEMS; j++)
+                cur[j] = nxt[j];
+        }
     }
 }
 

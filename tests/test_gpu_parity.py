@@ -208,6 +208,24 @@ def test_c1_cutoff(pt2, c1):
     ctx.close()
 
 
+@pytest.mark.parametrize("log2p", [2, 5])
+def test_c1_cutoff_with_split(pt2, c1, log2p):
+    """Cutoff and a hash split together: counts come from the enumerating
+    count pass (the cutoff needs every term's value), generation walks only
+    each subset's terms."""
+    k, v = c1["O"].emit(c1["dets"], c1["c"])
+    cut = float(np.quantile(np.abs(v), 0.3))
+    ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, cutoff=cut, log2_partitions=log2p)
+    got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+    ctx.close()
+    ref, _ = c1["O"].pt2(c1["dets"], c1["c"], c1["e0"], cutoff=cut, log2p=log2p)
+    assert got["n_partitions"] == 1 << log2p
+    assert got["n_after_cutoff"] == ref["n_kept"] and got["n_contrib"] == ref["n_contrib"]
+    assert abs(got["e_pt2"] - ref["e_pt2"]) <= 1e-9
+    for key in ("n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
+        assert got[key] == ref[key]
+
+
 # ---------------------------------------------------------------------------
 # Word-straddling keys and every key width
 
