@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COUNTERS_MD = os.path.join(ROOT, "profiles", "onesweep_c2_fp64_hbm_counters.md")
+COUNTERS_MD = os.path.join(ROOT, "profiles", "radix_scatter_c2_fp64_hbm_counters.md")
 SORT_SRC = os.path.join(ROOT, "paper_1808_02049_amd", "csrc", "sort.hip")
 
 
@@ -154,6 +154,8 @@ def serving_bench(args):
             print(f"bench: open loop submitted {j}", file=sys.stderr, flush=True)
     opened = [f.result() for f in futs]
     lat = [(d - (t0 + a)) * 1e3 for (_, d), a in zip(opened, arrivals)]
+    busy = sorted(((r["ms_total"], j, r["n_partitions"], contrib[j]) for j, (r, _) in enumerate(closed)),
+                  reverse=True)
     span = max(d for _, d in opened) - t0
     same = all(a[0]["e_pt2"] == b[0]["e_pt2"] and a[0]["n_unique"] == b[0]["n_unique"]
                for a, b in zip(closed, opened))
@@ -180,6 +182,9 @@ def serving_bench(args):
         "closed_loop": {"makespan_s": makespan, "contributions_per_s": total / makespan,
                         "requests_per_s": cap_rps},
         "deterministic_across_runs": same,
+        "closed_loop_request_ms_sum": sum(b[0] for b in busy),
+        "slowest_requests": [{"index": j, "ms": round(ms, 1), "subsets": p, "contributions": n}
+                             for ms, j, p, n in busy[:5]],
     }
     print(json.dumps(line), flush=True)
 
