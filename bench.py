@@ -34,17 +34,18 @@ COUNTERS_MD = os.path.join(ROOT, "profiles", "radix_scatter_c2_fp64_hbm_counters
 SORT_SRC = os.path.join(ROOT, "paper_1808_02049_amd", "csrc", "sort.hip")
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per digit pass from the committed rocprofv3 counter summary,
-    or None if the sort kernel source changed since those counters were taken
-    (or the summary covers another workload)."""
+def measured_traffic(workload, precision, record_bytes):
+    """HBM bytes per scatter launch from the committed rocprofv3 counter
+    summary, or None if the sort kernel source changed since those counters
+    were taken, or the summary covers another workload or record format."""
     import hashlib
     import re
     if workload != "c2" or precision != "fp64" or not os.path.exists(COUNTERS_MD):
         return None
-    m = re.search(r"scatter_traffic_bytes_per_launch=(\S+) .*source_sha256_16=([0-9a-f]+)",
-                  open(COUNTERS_MD).read())
-    if not m:
+    text = open(COUNTERS_MD).read()
+    m = re.search(r"scatter_traffic_bytes_per_launch=(\S+) .*source_sha256_16=([0-9a-f]+)", text)
+    r = re.search(r"record_bytes=(\d+)", text)
+    if not m or not r or int(r.group(1)) != record_bytes:
         return None
     cur = hashlib.sha256(open(SORT_SRC, "rb").read()).hexdigest()[:16]
     return float(m.group(1)) if cur == m.group(2) else None
@@ -115,7 +116,7 @@ def serving_bench(args):
         r = reqs[j]
         h, eri, dets, c = inputs[j]
         ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, precision=args.precision,
-                          n_streams=args.serving_streams)
+                          n_streams=args.serving_streams, timing=args.serving_timing)
         res = ctx.wait(ctx.submit(dets, c, stored[r.index]["e0"]))
         done = time.perf_counter()
         with lock:
@@ -139,6 +140,21 @@ def serving_bench(args):
     cap_rps = len(reqs) / makespan
     print(f"bench: closed loop {makespan:.1f} s, {total / makespan:.3e} contributions/s",
           file=sys.stderr, flush=True)
+
+    if args.serving_closed_only:
+        busy = sorted(((r["ms_total"], j, r["n_partitions"], contrib[j]) for j, (r, _) in enumerate(closed)),
+                      reverse=True)
+        print(json.dumps({"closed_loop": {"makespan_s": makespan, "contributions_per_s": total / makespan},
+                          "request_ms_sum": sum(b[0] for b in busy),
+                          "phase_ms_sum": {k: round(sum(r[k] for r, _ in closed), 1)
+                                           for k in ("ms_gen", "ms_hist", "ms_sort", "ms_reduce")},
+                          "sort_passes": sum(r["n_sort_passes"] for r, _ in closed),
+                          "key_bits": sorted({r["key_bits"] for r, _ in closed}),
+                          "streams": args.serving_streams}), flush=True)
+        pool.shutdown()
+        for ctx in keep:
+            ctx.close()
+        return
 
     # open loop at 0.7 x capacity
     lam = 0.7 * cap_rps
@@ -183,6 +199,9 @@ def serving_bench(args):
                         "requests_per_s": cap_rps},
         "deterministic_across_runs": same,
         "closed_loop_request_ms_sum": sum(b[0] for b in busy),
+        "closed_loop_phase_ms_sum": {k: round(sum(r[k] for r, _ in closed), 1)
+                                     for k in ("ms_gen", "ms_hist", "ms_sort", "ms_reduce")},
+        "closed_loop_sort_passes": sum(r["n_sort_passes"] for r, _ in closed),
         "slowest_requests": [{"index": j, "ms": round(ms, 1), "subsets": p, "contributions": n}
                              for ms, j, p, n in busy[:5]],
     }
@@ -200,10 +219,16 @@ def main():
                     help="reference determinants in the oracle's timed sample (0: skip)")
     ap.add_argument("--fp32-form", action="store_true",
                     help="also time the FP32-payload form (outside the timed region)")
+    ap.add_argument("--compress-keys", type=int, default=-1, choices=[-1, 0, 1],
+                    help="record keys: -1 library default, 0 bitstrings, 1 combinatorial ranks")
     ap.add_argument("--serving", action="store_true",
                     help="the serving workload (C4) instead of the single large evaluation")
     ap.add_argument("--serving-count", type=int, default=200)
     ap.add_argument("--serving-streams", type=int, default=4)
+    ap.add_argument("--serving-timing", action="store_true",
+                    help="time each request's phases with HIP events (serving diagnostics)")
+    ap.add_argument("--serving-closed-only", action="store_true",
+                    help="measure the closed loop only (diagnostics)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -225,7 +250,7 @@ def main():
     w, h, eri, dets, c, e0 = load_workload(args.workload)
     stream = torch.cuda.current_stream()
     ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision=args.precision,
-                      stream=stream, allocator="torch", timing=True)
+                      stream=stream, allocator="torch", timing=True, compress_keys=args.compress_keys)
     d_dets = torch.from_numpy(np.ascontiguousarray(dets).view(np.int64)).cuda()
     d_c = torch.from_numpy(np.ascontiguousarray(c)).cuda()
     torch.cuda.synchronize()
@@ -311,7 +336,7 @@ def main():
         "roofline": {"kernel": "k_scatter (radix rank-and-scatter, one per digit pass)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, args.precision),
+                     "traffic": measured_traffic(args.workload, args.precision, rec),
                      "bytes_per_launch": bytes_per_pass, "avg_launch_ms": scatter_ms,
                      "whole_digit_pass": {"avg_ms": pass_ms, "achieved_GBs": pass_gbs}},
         "cpu_baseline": cpu,

@@ -99,6 +99,15 @@ typedef struct {
     void *alloc_user;
     void *stream;                  /* hipStream_t for pt2_evaluate*; NULL = own      */
     int timing;                    /* nonzero: time phases with HIP events            */
+    int compress_keys;             /* -1 (default): stored terms carry the
+                                      combinatorial rank of their determinant
+                                      (per spin, sum_i C(o_i, i) over the ascending
+                                      occupied orbitals o_i; alpha rank above beta
+                                      rank) when both ranks fit 64 bits and this
+                                      saves at least a third of the sort digits;
+                                      it orders terms exactly as the bitstrings,
+                                      so results are unchanged.  0: always the
+                                      bitstring; 1: the rank whenever it fits         */
 } pt2_options;
 
 typedef struct {
@@ -129,6 +138,8 @@ typedef struct {
                                  digit pass: every record read and written once by
                                  the scatter, the digit's key plane read once by
                                  the count)                                          */
+    uint32_t key_bits;        /* bits of the sort key of a stored term (2 norb for
+                                 bitstrings, fewer for rank keys)                    */
 } pt2_result;
 
 /* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */

@@ -160,6 +160,7 @@ struct Workspace {
     Alloc A;
     Buf dets, coef;          // device copies of host inputs
     Buf refA, refB;          // reference planes (W keys + FP64 coefficient)
+    Buf refK;                // the references' rank keys (same order) when records carry them
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -175,7 +176,7 @@ struct Workspace {
 
     void release()
     {
-        buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB);
+        buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB), buf_free(A, refK);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
@@ -245,7 +246,7 @@ struct pt2_ctx {
     int norb, na, nb, W;
     int topb;  // bytes of the last key plane of a record
     Alloc A;
-    Buf h, V, h32, V32, T, R;
+    Buf h, V, h32, V32, T, R, binom;
     DevSys sys;
     ExcLayout L;
     hipStream_t stream = nullptr;
@@ -469,6 +470,7 @@ struct Job {
     double e0;
     int forced_log2p;              // -1 planner
     bool live_budget = false;      // plan against free memory now, not at creation
+    double plan_budget = 0.0;      // > 0: plan against this many bytes
     const uint32_t *parts = nullptr;
     int nparts = 0;
     double *e_parts = nullptr;
@@ -481,8 +483,22 @@ struct Job {
     int64_t *n_out = nullptr;
 };
 
-int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan &P, double cutoff, hipStream_t st,
-               std::vector<uint64_t> &tot_out)
+// Key format of the stored terms of one job: rank keys when the context
+// enables them (not for the inspection dumps, which return bitstrings).
+struct RecLayout {
+    int W, topb, bits;
+    bool rank;
+};
+
+RecLayout rec_layout(const pt2_ctx *c, bool dump)
+{
+    if (c->sys.kc.on && !dump)
+        return {c->sys.kc.kw, c->sys.kc.ktop, c->sys.kc.kbits, true};
+    return {c->W, c->topb, 2 * c->norb, false};
+}
+
+int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws, const Planes &refs, int64_t nref,
+               Plan &P, double cutoff, hipStream_t st, std::vector<uint64_t> &tot_out)
 {
     int rc;
     const int Pn = 1 << P.log2p;
@@ -495,10 +511,9 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
     if (P.target && cutoff <= 0.0)
-        HIPCHK(launch_count_target(c->sys, c->L, refs, nref, P.log2p, (uint32_t *)ws.cnt.p, st));
+        HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (uint32_t *)ws.cnt.p, st));
     else
-        HIPCHK(launch_count(c->sys, c->L, pm, refs, nref, P.chunk, P.log2p, cutoff,
-                            (uint32_t *)ws.cnt.p, P.nchunks, st));
+        HIPCHK(launch_count(sys, L, pm, refs, nref, P.chunk, P.log2p, cutoff, (uint32_t *)ws.cnt.p, P.nchunks, st));
     HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
                              (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
     tot_out.assign(P.parts.size(), 0);
@@ -507,14 +522,15 @@ int count_pass(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, Plan
     return PT2_OK;
 }
 
-int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
+int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout &RL, Workspace &ws,
+             const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
 {
-    const int W = c->W;
+    const int W = RL.W;
     const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
-    const double total = (double)nref * (double)c->L.nper;
+    const double total = (double)nref * (double)L.nper;
     // without an explicit budget: 80% of what is free now plus the record
     // buffers this workspace already holds (they are reused)
-    uint64_t budget = c->budget;
+    uint64_t budget = J.plan_budget > 0.0 ? (uint64_t)J.plan_budget : c->budget;
     if (!c->opt.device_budget_bytes && J.live_budget) {
         size_t freeb = 0, totalb = 0;
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess)
@@ -531,7 +547,7 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
         k = c->opt.log2_partitions;
     else {
         k = 0;
-        while (k < MAX_LOG2P && subset_bytes(W, pb, c->topb, total / (double)(1 << k) * 1.02 + 4096.0) > cap_bytes)
+        while (k < MAX_LOG2P && subset_bytes(W, pb, RL.topb, total / (double)(1 << k) * 1.02 + 4096.0) > cap_bytes)
             k++;
     }
     for (int attempt = 0; attempt < 4; attempt++) {
@@ -551,30 +567,30 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
                 P.parts.push_back(p);
         }
         if (!P.compact) {
-            P.chunk = gen_chunk(c->L, nref, (int64_t)1 << 23);
-            P.nchunks = gen_nchunks(c->L, nref, P.chunk);
-            P.sizes.assign(1, (uint64_t)nref * (uint64_t)c->L.nper);
+            P.chunk = gen_chunk(L, nref, (int64_t)1 << 23);
+            P.nchunks = gen_nchunks(L, nref, P.chunk);
+            P.sizes.assign(1, (uint64_t)nref * (uint64_t)L.nper);
             P.structural = P.sizes;
             return PT2_OK;
         }
-        P.target = target_ok(c->L, nref, k);
+        P.target = target_ok(L, nref, k);
         if (P.target) {
-            P.chunk = std::max<int64_t>(c->L.nper, 1);
+            P.chunk = std::max<int64_t>(L.nper, 1);
             P.nchunks = nref;
         } else {
             const int64_t max_chunks =
                 std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 23, ((int64_t)1 << 27) >> k));
-            P.chunk = gen_chunk(c->L, nref, max_chunks);
-            P.nchunks = gen_nchunks(c->L, nref, P.chunk);
+            P.chunk = gen_chunk(L, nref, max_chunks);
+            P.nchunks = gen_nchunks(L, nref, P.chunk);
         }
         int rc;
         std::vector<uint64_t> tot;
         if (cutoff > 0.0) {
-            if ((rc = count_pass(c, ws, refs, nref, P, 0.0, st, tot)))
+            if ((rc = count_pass(c, sys, L, ws, refs, nref, P, 0.0, st, tot)))
                 return rc;
             P.structural = tot;
         }
-        if ((rc = count_pass(c, ws, refs, nref, P, cutoff, st, tot)))
+        if ((rc = count_pass(c, sys, L, ws, refs, nref, P, cutoff, st, tot)))
             return rc;
         P.sizes = tot;
         if (cutoff <= 0.0)
@@ -582,7 +598,7 @@ int plan_job(pt2_ctx *c, Workspace &ws, const Planes &refs, int64_t nref, const 
         uint64_t mx = 0;
         for (auto t : tot)
             mx = std::max(mx, t);
-        if (subset_bytes(W, pb, c->topb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
+        if (subset_bytes(W, pb, RL.topb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
             return PT2_OK;
         k++;
     }
@@ -605,7 +621,12 @@ void fill_result(pt2_result *out, const Partial &p)
 int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result *out)
 {
     const double t0 = now_ms();
-    const int W = c->W;
+    const RecLayout RL = rec_layout(c, J.dump != 0);
+    const int W = RL.W;  // key words of a stored term
+    DevSys sys = c->sys;
+    ExcLayout L = c->L;
+    if (!RL.rank)
+        sys.kc.on = 0, L.rank = 0;
     const int pm = c->opt.precision;
     const int fp32 = pm != PT2_FP64;  // 4-byte payload plane
     const int pb = fp32 ? 4 : 8;
@@ -630,37 +651,46 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     Planes refs;
     if ((rc = prepare_refs(c, ws, J.dets, J.coeffs, J.n, J.host, st, tm, refs)))
         return rc;
+    // the single pass compares stored keys with reference keys of the same format
+    Planes refs_red = refs;
+    if (RL.rank) {
+        if ((rc = buf_ensure(ws.A, ws.refK, planes_bytes(W, J.n, 8, RL.topb))))
+            return rc;
+        refs_red = planes_of(ws.refK, W, J.n, 8, RL.topb);
+        HIPCHK(launch_refs_rank(sys, refs, J.n, refs_red, st));
+    }
     Plan P;
     Job JJ = J;
     if (J.dump)
         JJ.forced_log2p = 0;
-    if ((rc = plan_job(c, ws, refs, J.n, JJ, st, P)))
+    if ((rc = plan_job(c, sys, L, RL, ws, refs, J.n, JJ, st, P)))
         return rc;
     uint64_t mx = 0;
     for (auto s : P.sizes)
         mx = std::max(mx, s);
-    if ((rc = ensure_records(ws, W, pb, c->topb, (int64_t)std::max<uint64_t>(mx, 1))))
+    if ((rc = ensure_records(ws, W, pb, RL.topb, (int64_t)std::max<uint64_t>(mx, 1))))
         return rc;
-    const double rbytes = record_bytes(W, pb, c->topb);
+    const double rbytes = record_bytes(W, pb, RL.topb);
     res.record_bytes = (uint32_t)rbytes;
+    res.key_bits = (uint32_t)RL.bits;
     Small *ds = ws.dsmall();
     std::vector<Partial> part_res(P.parts.size());
     for (size_t q = 0; q < P.parts.size(); q++) {
         const int64_t n = (int64_t)P.sizes[q];
         res.n_contrib += P.structural[q];
         res.n_after_cutoff += (uint64_t)n;
-        Planes A = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb), B = planes_of(ws.recB, W, ws.rec_cap, pb, c->topb);
+        Planes A = planes_of(ws.recA, W, ws.rec_cap, pb, RL.topb), B = planes_of(ws.recB, W, ws.rec_cap, pb, RL.topb);
         hipEvent_t a;
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
         if (!P.compact)
-            HIPCHK(launch_gen_direct(c->sys, c->L, pm, refs, J.n, P.chunk, A, st));
+            HIPCHK(launch_gen_direct(sys, L, pm, refs, J.n, P.chunk, A, st));
         else if (P.target)
-            HIPCHK(launch_gen_target(c->sys, c->L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
+            HIPCHK(launch_gen_target(sys, L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
                                      (const uint64_t *)ws.off.p + (size_t)q * P.nchunks,
                                      (const uint64_t *)ws.tot.p + q, A, &ds->flags, st));
         else
-            HIPCHK(launch_gen_compact(c->sys, c->L, pm, refs, J.n, P.chunk,
+            HIPCHK(launch_gen_compact(sys, L, pm, refs, J.n, P.chunk,
                                       P.log2p, P.parts[q], c->opt.cutoff,
                                       (const uint64_t *)ws.off.p + (size_t)q * P.nchunks, P.nchunks,
                                       (uint64_t)ws.rec_cap, A, &ds->flags, st));
@@ -669,7 +699,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         res.bytes_gen += (double)n * rbytes;
         if (J.dump == 1)
             break;  // generation order: the records are in recA
-        if ((rc = radix_sort(ws, W, pb, A, B, n, 2 * c->norb, st, tm, &res.n_sort_passes, &res.bytes_sort)))
+        if ((rc = radix_sort(ws, W, pb, A, B, n, RL.bits, st, tm, &res.n_sort_passes, &res.bytes_sort)))
             return rc;
         if (J.dump == 2 || J.dump == 3) {
             // hand the sorted planes to the inspection copy below (it reads recA)
@@ -679,7 +709,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         }
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
-        HIPCHK(launch_reduce(c->sys, fp32, A, n, refs, J.n, J.e0, ds->partials, &ds->flags, st));
+        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, ds->partials, &ds->flags, st));
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;
@@ -697,7 +727,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             if ((rc = buf_alloc(ws.A, kb, (size_t)std::max<int64_t>(m, 1) * W * 8)) ||
                 (rc = buf_alloc(ws.A, vb, (size_t)std::max<int64_t>(m, 1) * 8)))
                 return rc;
-            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb);
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, RL.topb);
             HIPCHK(launch_planes_to_aos(W, pb, S, m, (uint64_t *)kb.p, (double *)vb.p, st));
             if (m > 0) {
                 HIPCHK(hipMemcpyAsync(J.keys_out, kb.p, (size_t)m * W * 8, hipMemcpyDeviceToHost, st));
@@ -711,7 +741,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             if ((rc = buf_alloc(ws.A, kb, (size_t)m * W * 8)) || (rc = buf_alloc(ws.A, vb, (size_t)m * 8)) ||
                 (rc = buf_alloc(ws.A, ib, (size_t)m)))
                 return rc;
-            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, c->topb);
+            Planes S = planes_of(ws.recA, W, ws.rec_cap, pb, RL.topb);
             HIPCHK(launch_zero_u64((uint64_t *)&ds->n_out, 1, st));
             HIPCHK(launch_numerators(W, fp32, S, n, refs, J.n, (uint64_t *)kb.p, (double *)vb.p, (uint8_t *)ib.p,
                                      &ds->n_out, J.cap, st));
@@ -816,6 +846,9 @@ struct Request {
     int64_t n;
     double e0;
     double projected;
+    double cap;          // plan budget: bytes of record buffers one subset may use
+    bool alone = false;  // retried after an allocation failure: run with nothing else
+    int retries = 0;
     bool done = false;
     int rc = PT2_OK;
     std::string err;
@@ -846,13 +879,21 @@ class Scheduler {
         r->e0 = e0;
         const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
         const double total = (double)n * (double)c->L.nper;
-        double cap = (double)(c->opt.max_partition_bytes ? std::min<uint64_t>(c->opt.max_partition_bytes, c->budget)
-                                                         : c->budget);
-        double per = subset_bytes(c->W, pb, c->topb, total * 1.02 + 4096.0);
+        std::unique_lock<std::mutex> lk0(mu_);
+        const double dev_budget = device_budget_locked(c->opt.device);
+        lk0.unlock();
+        // the plan depends on the request and the device budget only, so a
+        // request gives the same result alone and in a mix
+        double cap = c->opt.device_budget_bytes ? (double)c->opt.device_budget_bytes : dev_budget;
+        if (c->opt.max_partition_bytes)
+            cap = std::min(cap, (double)c->opt.max_partition_bytes);
+        r->cap = cap;
+        const RecLayout RL = rec_layout(c, false);
+        double per = subset_bytes(RL.W, pb, RL.topb, total * 1.02 + 4096.0);
         int k = 0;
         while (k < MAX_LOG2P && per > cap) {
             k++;
-            per = subset_bytes(c->W, pb, c->topb, total / (double)(1 << k) * 1.02 + 4096.0);
+            per = subset_bytes(RL.W, pb, RL.topb, total / (double)(1 << k) * 1.02 + 4096.0);
         }
         r->projected = per;
         std::unique_lock<std::mutex> lk(mu_);
@@ -886,12 +927,55 @@ class Scheduler {
         return rc;
     }
 
+    // bytes the scheduler may hand to the record buffers of running requests
+    // on a device: 80% of what was free when it first served the device.
+    // Freed request buffers stay in the device's stream-ordered pool for the
+    // next request (no unmapping and remapping of hundreds of GB).
+    double device_budget_locked(int dev)
+    {
+        auto it = dev_budget_.find(dev);
+        if (it != dev_budget_.end())
+            return it->second;
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(dev);
+        size_t freeb = 0, totalb = 0;
+        double b = 0.0;
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess)
+            b = 0.8 * (double)freeb;
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+        (void)hipSetDevice(prev);
+        dev_budget_[dev] = b;
+        return b;
+    }
+
     // projected bytes of the requests running on a device
     double held(int dev)
     {
         std::lock_guard<std::mutex> lk(mu_);
         auto it = in_use_.find(dev);
         return it == in_use_.end() ? 0.0 : it->second;
+    }
+
+    // return the stream-ordered pool's idle memory of a device when nothing
+    // runs or waits there
+    void trim_if_idle(int dev)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (running_[dev] != 0)
+            return;
+        for (Request *q : queue_)
+            if (q->ctx->opt.device == dev)
+                return;
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+            (void)hipMemPoolTrimTo(pool, 0);
+        (void)hipGetLastError();
     }
 
     int inflight(pt2_ctx *c)
@@ -927,6 +1011,7 @@ class Scheduler {
     int64_t next_id_ = 1;
     std::unordered_map<int, double> in_use_;  // projected bytes of running requests, per device
     std::unordered_map<int, int> running_;    // running requests, per device
+    std::unordered_map<int, double> dev_budget_;
     bool stopping_ = false;
     bool atexit_ = false;
 
@@ -956,7 +1041,8 @@ class Scheduler {
         for (size_t i = 0; i < queue_.size(); i++) {
             Request *r = queue_[i];
             const int dev = r->ctx->opt.device;
-            if (running_[dev] == 0 || in_use_[dev] + r->projected <= (double)r->ctx->budget) {
+            const double limit = std::min(r->cap, device_budget_locked(dev));
+            if (running_[dev] == 0 || (!r->alone && in_use_[dev] + r->projected <= limit)) {
                 queue_.erase(queue_.begin() + (long)i);
                 return r;
             }
@@ -999,6 +1085,7 @@ class Scheduler {
             J.host = true;
             J.e0 = r->e0;
             J.forced_log2p = -1;
+            J.plan_budget = r->cap;
             pt2_result res;
             memset(&res, 0, sizeof res);
             res.struct_size = sizeof res;
@@ -1014,6 +1101,24 @@ class Scheduler {
             if (w->stream)
                 (void)hipStreamSynchronize(w->stream);
             lk.lock();
+            if (rc == PT2_E_NOMEM && r->retries < 2) {
+                // memory held outside the projections (other requests, pool
+                // fragments): run it again with nothing else on the device,
+                // the second time after returning the pool's idle memory
+                r->retries++;
+                r->alone = true;
+                in_use_[c->opt.device] -= r->projected;
+                running_[c->opt.device]--;
+                if (r->retries == 2 && running_[c->opt.device] == 0) {
+                    hipMemPool_t pool;
+                    if (hipDeviceGetDefaultMemPool(&pool, c->opt.device) == hipSuccess)
+                        (void)hipMemPoolTrimTo(pool, 0);
+                    (void)hipGetLastError();
+                }
+                queue_.push_front(r);
+                cv_.notify_all();
+                continue;
+            }
             r->rc = rc;
             r->err = rc != PT2_OK ? g_err : std::string();
             r->res = res;
@@ -1040,6 +1145,7 @@ PT2_API void pt2_default_options(pt2_options *o)
     o->precision = PT2_FP64;
     o->cutoff = 0.0;
     o->log2_partitions = -1;
+    o->compress_keys = -1;
     o->device = 0;
     o->n_streams = 4;
 }
@@ -1074,6 +1180,8 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         return fail(PT2_E_INVALID, "cutoff must be >= 0");
     if (o.log2_partitions > MAX_LOG2P)
         return fail(PT2_E_INVALID, "log2_partitions must be <= %d", MAX_LOG2P);
+    if (o.compress_keys < -1 || o.compress_keys > 1)
+        return fail(PT2_E_INVALID, "compress_keys must be -1, 0 or 1");
     if ((o.alloc == nullptr) != (o.free == nullptr))
         return fail(PT2_E_INVALID, "alloc and free hooks must be given together");
     const size_t n = (size_t)norb;
@@ -1172,6 +1280,50 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.V32 = (const float *)c->V32.p;
     c->sys.T = (const double *)c->T.p;
     c->sys.R = (const uint64_t *)c->R.p;
+
+    // compressed keys: exact binomials C(x, j), x <= norb, j <= max(na, nb)
+    memset(&c->sys.kc, 0, sizeof c->sys.kc);
+    if (o.compress_keys != 0) {
+        const int nmax = std::max(nalpha, nbeta), stride = nmax + 1;
+        std::vector<unsigned __int128> C((size_t)(norb + 1) * stride, 0);
+        bool fits = true;
+        for (int x = 0; x <= norb; x++)
+            for (int j = 0; j < stride; j++) {
+                unsigned __int128 v = j == 0 ? 1 : (x == 0 ? 0 : C[(size_t)(x - 1) * stride + j - 1] +
+                                                                     C[(size_t)(x - 1) * stride + j]);
+                C[(size_t)x * stride + j] = v;
+                if (v > (unsigned __int128)UINT64_MAX)
+                    fits = false;
+            }
+        auto bits_for = [](unsigned __int128 count) {  // bits of values 0 .. count-1
+            int b = 0;
+            while (count > ((unsigned __int128)1 << b))
+                b++;
+            return b;
+        };
+        const int ba = bits_for(C[(size_t)norb * stride + nalpha]);
+        const int bb = bits_for(C[(size_t)norb * stride + nbeta]);
+        const int kbits = ba + bb;
+        const int kw = std::max(1, (kbits + 63) / 64);
+        // automatic only where it removes at least a third of the digit
+        // passes: rank digits are dense, so a scatter tile writes shorter runs
+        // (at (10a,10b)/40, 8 rank passes took longer than 10 bitstring passes)
+        const bool worth = 3 * ((kbits + 7) / 8) <= 2 * ((2 * norb + 7) / 8);
+        if (fits && kw <= 2 && (o.compress_keys == 1 || worth)) {
+            std::vector<uint64_t> C64(C.size());
+            for (size_t i = 0; i < C.size(); i++)
+                C64[i] = (uint64_t)C[i];
+            if ((rc = buf_alloc(c->A, c->binom, C64.size() * 8)))
+                return rc;
+            HIPCHK(hipMemcpy(c->binom.p, C64.data(), C64.size() * 8, hipMemcpyHostToDevice));
+            const int tb = kbits - 64 * (kw - 1);
+            KeyCodec &k = c->sys.kc;
+            k.on = 1, k.kw = kw, k.kbits = kbits, k.bb = bb, k.stride = stride;
+            k.ktop = tb <= 16 ? 2 : (tb <= 32 ? 4 : 8);
+            k.binom = (const uint64_t *)c->binom.p;
+            c->L.rank = 1;
+        }
+    }
     *out = c.release();
     return PT2_OK;
 }
@@ -1320,6 +1472,7 @@ PT2_API int pt2_destroy(pt2_ctx *c)
         return PT2_OK;
     if (Scheduler::get().inflight(c) > 0)
         return fail(PT2_E_BUSY, "requests in flight");
+    Scheduler::get().trim_if_idle(c->opt.device);
     {
         std::lock_guard<std::mutex> lk(c->mu);
         (void)hipSetDevice(c->opt.device);
@@ -1327,7 +1480,7 @@ PT2_API int pt2_destroy(pt2_ctx *c)
             (void)hipStreamSynchronize(c->stream);
         c->ws.release();
         buf_free(c->A, c->h), buf_free(c->A, c->V), buf_free(c->A, c->h32), buf_free(c->A, c->V32);
-        buf_free(c->A, c->T), buf_free(c->A, c->R);
+        buf_free(c->A, c->T), buf_free(c->A, c->R), buf_free(c->A, c->binom);
         if (c->own_stream && c->stream)
             (void)hipStreamDestroy(c->stream);
     }

@@ -29,6 +29,7 @@ namespace {
 struct GenHead {
     uint64_t key[MAXW];
     uint64_t z;
+    uint64_t ra0, rb0;  // spin-string ranks of the determinant (rank keys only)
     double c;
     uint64_t R[2 * MAXORB];
     uint8_t occ[2][MAXORB];   // [spin][k]: spin 0 = alpha, 1 = beta
@@ -40,6 +41,7 @@ struct GenLds {
     int8_t *ph[2];      // [spin][occ_idx * v + vir_idx]
     uint16_t *op[2];    // occupied pairs (i | j << 8), i < j, indices into occ
     uint16_t *vp[2];    // virtual pairs, indices into vir
+    uint64_t *sr[2];    // rank keys only: spin-string rank after each single, [occ_idx * v + vir_idx]
     // select by a runtime spin without indexing the pointer arrays (which
     // would force this struct out of registers)
     __device__ const int8_t *phs(int sp) const { return sp == 0 ? ph[0] : ph[1]; }
@@ -48,7 +50,7 @@ struct GenLds {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, size_t *o_ph1, size_t *o_op0,
-                                             size_t *o_vp0, size_t *o_op1, size_t *o_vp1)
+                                             size_t *o_vp0, size_t *o_op1, size_t *o_vp1, size_t *o_sr = nullptr)
 {
     size_t o = align16(sizeof(GenHead));
     *o_ph0 = o;
@@ -63,6 +65,10 @@ __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, 
     o = align16(o + 2 * (size_t)L.nopb);
     *o_vp1 = o;
     o = align16(o + 2 * (size_t)L.nvpb);
+    if (o_sr)
+        *o_sr = o;
+    if (L.rank)
+        o = align16(o + 8 * (size_t)(L.nSa + L.nSb));
     return o;
 }
 
@@ -74,8 +80,8 @@ __host__ __device__ inline size_t gen_lds_bytes_dev(const ExcLayout &L)
 
 __device__ inline GenLds carve(char *base, const ExcLayout &L)
 {
-    size_t a, b, c, d, e, f;
-    lds_layout(L, &a, &b, &c, &d, &e, &f);
+    size_t a, b, c, d, e, f, r;
+    lds_layout(L, &a, &b, &c, &d, &e, &f, &r);
     GenLds g;
     g.head = (GenHead *)base;
     g.ph[0] = (int8_t *)(base + a);
@@ -84,6 +90,8 @@ __device__ inline GenLds carve(char *base, const ExcLayout &L)
     g.vp[0] = (uint16_t *)(base + d);
     g.op[1] = (uint16_t *)(base + e);
     g.vp[1] = (uint16_t *)(base + f);
+    g.sr[0] = (uint64_t *)(base + r);
+    g.sr[1] = (uint64_t *)(base + r) + L.nSa;
     return g;
 }
 
@@ -121,7 +129,8 @@ __device__ inline void pair_decode(int k, int n, int &i, int &j)
 }
 
 template <int W>
-__device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t det)
+__device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t det,
+                          bool ranks = true)
 {
     GenHead *H = g.head;
     const int tid = threadIdx.x;
@@ -176,6 +185,22 @@ __device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, 
         int i, j;
         pair_decode(idx, L.vb, i, j);
         g.vp[1][idx] = (uint16_t)(i | (j << 8));
+    }
+    if (ranks && s.kc.on && L.rank) {
+        const uint64_t *B = s.kc.binom;
+        const int st = s.kc.stride;
+        if (tid == 0)
+            H->ra0 = rank_edit(H->occ[0], L.na, -1, -1, -1, -1, B, st);
+        else if (tid == 1)
+            H->rb0 = rank_edit(H->occ[1], L.nb, -1, -1, -1, -1, B, st);
+        for (int idx = tid; idx < L.nSa; idx += blockDim.x) {
+            const int oi = idx / L.va, vi = idx - oi * L.va;
+            g.sr[0][idx] = rank_edit(H->occ[0], L.na, oi, -1, H->vir[0][vi], -1, B, st);
+        }
+        for (int idx = tid; idx < L.nSb; idx += blockDim.x) {
+            const int oi = idx / L.vb, vi = idx - oi * L.vb;
+            g.sr[1][idx] = rank_edit(H->occ[1], L.nb, oi, -1, H->vir[1][vi], -1, B, st);
+        }
     }
     __syncthreads();
 }
@@ -351,6 +376,53 @@ __device__ inline void store_keys(const Planes &out, int64_t pos, const uint64_t
         pl_put<W>(out, w, pos, key[w]);
 }
 
+__device__ inline void put_top(void *plane, int topb, int64_t i, uint64_t v)
+{
+    if (topb == 8)
+        ((uint64_t *)plane)[i] = v;
+    else if (topb == 4)
+        ((uint32_t *)plane)[i] = (uint32_t)v;
+    else
+        ((uint16_t *)plane)[i] = (uint16_t)v;
+}
+
+// Record key of an excitation: its bitstring, or its rank key (KeyCodec).
+// Singles and alpha-beta doubles take their spin-string ranks from the
+// per-determinant tables; same-spin doubles rank the edited string.
+template <int W>
+__device__ inline void store_rec_key(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
+                                     const uint64_t (&key)[W], const Planes &out, int64_t pos)
+{
+    if (!s.kc.on) {
+        store_keys<W>(out, pos, key);
+        return;
+    }
+    const GenHead *H = g.head;
+    const uint64_t *B = s.kc.binom;
+    const int st = s.kc.stride;
+    uint64_t ra = H->ra0, rb = H->rb0;
+    if (e.kind == 0) {
+        ra = g.sr[0][e.oi * L.va + e.vi];
+    } else if (e.kind == 1) {
+        rb = g.sr[1][e.oi * L.vb + e.vi];
+    } else if (e.kind == 2) {
+        ra = rank_edit(H->occ[0], L.na, e.oi, e.oj, H->vir[0][e.vi], H->vir[0][e.vj], B, st);
+    } else if (e.kind == 3) {
+        rb = rank_edit(H->occ[1], L.nb, e.oi, e.oj, H->vir[1][e.vi], H->vir[1][e.vj], B, st);
+    } else {
+        ra = g.sr[0][e.oi * L.va + e.vi];
+        rb = g.sr[1][e.oj * L.vb + e.vj];
+    }
+    uint64_t lo, hi;
+    rank_join(ra, rb, s.kc.bb, lo, hi);
+    if (s.kc.kw == 1) {
+        put_top(out.key[0], out.topb, pos, lo);
+    } else {
+        out.key[0][pos] = lo;
+        put_top(out.key[1], out.topb, pos, hi);
+    }
+}
+
 // The payload H_ai * c_i: FP64; FP64 arithmetic rounded once to FP32; or
 // FP32 integrals and arithmetic.
 template <int PM>
@@ -384,7 +456,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        store_keys<W>(out, base + k, key);
+        store_rec_key<W>(g, s, L, e, key, out, base + k);
         store_pay<PM>(g, s, L, e, c, out, base + k);
     }
 }
@@ -421,7 +493,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
         hist[p] = 0;
     const int64_t det = blockIdx.x / cpd;
     const int64_t ch = blockIdx.x - det * cpd;
-    det_setup<W>(g, s, L, refs, det);
+    det_setup<W>(g, s, L, refs, det, false);
     const DivConsts D = div_consts(L);
     const int64_t lo = ch * chunk;
     const int64_t hi = lo + chunk < L.nper ? lo + chunk : L.nper;
@@ -480,7 +552,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
         if (keep) {
             uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
             if (p < cap) {
-                store_keys<W>(out, (int64_t)p, key);
+                store_rec_key<W>(g, s, L, e, key, out, (int64_t)p);
                 store_pay<PM>(g, s, L, e, c, out, (int64_t)p);
             } else {
                 atomicOr(&flags->err, ERR_OVERFLOW);
@@ -537,8 +609,8 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
 // few and are filtered.
 
 struct Tgt {
-    uint32_t *bstart;  // [B + 1] bucket counts, then starts
-    uint32_t *bfill;   // [B] fill cursors
+    uint32_t *bstart;  // [B + 1] bucket counts; after filling, bstart[b] = end of bucket b
+    uint32_t *hist;    // [B] subset counts (count pass only; aliases blist..pre)
     uint16_t *blist;   // [max inner] inner indices grouped by bucket
     uint16_t *tgt;     // [max outer] matching bucket of each outer part
     uint32_t *pre;     // [max outer + 1] prefix of matching inner counts
@@ -560,12 +632,15 @@ __host__ __device__ inline size_t tgt_lds_layout(const ExcLayout &L, int log2p, 
     const size_t B = (size_t)1 << log2p;
     size_t x = 0;
     o[0] = x, x = align16(x + 4 * (B + 1));
-    o[1] = x, x = align16(x + 4 * B);
+    o[5] = x, x = align16(x + 4 * (GEN_THREADS / 64));
+    const size_t rest = x;
     o[2] = x, x = align16(x + 2 * (size_t)(mi > 0 ? mi : 1));
     o[3] = x, x = align16(x + 2 * (size_t)(mo > 0 ? mo : 1));
     o[4] = x, x = align16(x + 4 * ((size_t)mo + 1));
-    o[5] = x, x = align16(x + 4 * (GEN_THREADS / 64));
-    return x;
+    // the count pass keeps its subset counts where generation keeps its lists
+    o[1] = rest;
+    const size_t xc = align16(rest + 4 * B);
+    return x > xc ? x : xc;
 }
 
 __device__ inline Tgt carve_tgt(char *base, const ExcLayout &L, int log2p)
@@ -574,7 +649,7 @@ __device__ inline Tgt carve_tgt(char *base, const ExcLayout &L, int log2p)
     tgt_lds_layout(L, log2p, o);
     Tgt t;
     t.bstart = (uint32_t *)(base + o[0]);
-    t.bfill = (uint32_t *)(base + o[1]);
+    t.hist = (uint32_t *)(base + o[1]);
     t.blist = (uint16_t *)(base + o[2]);
     t.tgt = (uint16_t *)(base + o[3]);
     t.pre = (uint32_t *)(base + o[4]);
@@ -583,6 +658,9 @@ __device__ inline Tgt carve_tgt(char *base, const ExcLayout &L, int log2p)
 }
 
 __device__ inline uint32_t top_bits(uint64_t z, int log2p) { return (uint32_t)(z >> (64 - log2p)); }
+
+// first slot of bucket b once the buckets are filled
+__device__ inline uint32_t bucket_lo(const Tgt &t, int b) { return b ? t.bstart[b - 1] : 0u; }
 
 // In-place exclusive scan of a[0..n) (block-wide); returns the total.
 __device__ uint32_t block_scan_excl(uint32_t *a, int n, uint32_t *wsum)
@@ -661,17 +739,15 @@ __device__ void build_buckets(const GenLds &g, const Tgt &t, const ExcLayout &L,
     if (!fill)
         return;
     block_scan_excl(t.bstart, B + 1, t.wsum);
-    for (int b = tid; b < B; b += GEN_THREADS)
-        t.bfill[b] = t.bstart[b];
-    __syncthreads();
+    // filling advances every start to its bucket's end
     for (int q = tid; q < ni; q += GEN_THREADS) {
-        const uint32_t slot = atomicAdd(&t.bfill[top_bits(inner_hash(g, L, norb, kind, q), log2p)], 1u);
+        const uint32_t slot = atomicAdd(&t.bstart[top_bits(inner_hash(g, L, norb, kind, q), log2p)], 1u);
         t.blist[slot] = (uint16_t)q;
     }
     __syncthreads();
     // the fill order above is arbitrary: sort every bucket (they are small)
     for (int b = tid; b < B; b += GEN_THREADS) {
-        const uint32_t lo = t.bstart[b], hi = t.bstart[b + 1];
+        const uint32_t lo = bucket_lo(t, b), hi = t.bstart[b];
         for (uint32_t i = lo + 1; i < hi; i++) {
             const uint16_t v = t.blist[i];
             uint32_t j = i;
@@ -732,7 +808,7 @@ __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayo
     if (keep) {
         const uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
         if (p < end) {
-            store_keys<W>(out, (int64_t)p, key);
+            store_rec_key<W>(g, s, L, e, key, out, (int64_t)p);
             store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
         } else {
             atomicOr(&flags->err, ERR_OVERFLOW);
@@ -777,7 +853,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
         for (int o = tid; o < no; o += GEN_THREADS) {
             const uint32_t b = part ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p);
             t.tgt[o] = (uint16_t)b;
-            t.pre[o] = t.bstart[b + 1] - t.bstart[b];
+            t.pre[o] = t.bstart[b] - bucket_lo(t, b);
         }
         if (tid == 0)
             t.pre[no] = 0;
@@ -797,7 +873,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
                     else
                         hi = mid;
                 }
-                const int q = t.blist[t.bstart[t.tgt[lo]] + (f - t.pre[lo])];
+                const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
                 e = make_exc(g, L, kind, lo, q);
             }
             emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad);
@@ -818,8 +894,8 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
     Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x, B = 1 << log2p;
-    uint32_t *hist = t.bfill;  // [B]
-    det_setup<W>(g, s, L, refs, det);
+    uint32_t *hist = t.hist;  // [B]
+    det_setup<W>(g, s, L, refs, det, false);
     const DivConsts D = div_consts(L);
     const uint64_t zp = g.head->z;
     for (int b = tid; b < B; b += GEN_THREADS)
@@ -859,6 +935,40 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
     __syncthreads();
     for (int b = tid; b < B; b += GEN_THREADS)
         cnt[(int64_t)b * nref + det] = hist[b];
+}
+
+// Rank keys of the sorted bitstring references, same order, with their
+// coefficients (the single pass matches records against these).
+template <int W>
+__global__ void k_refs_rank(DevSys s, Planes bits, int64_t n, Planes out)
+{
+    const uint64_t *B = s.kc.binom;
+    const int st = s.kc.stride;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t ra = 0, rb = 0;
+        int pa = 1, pb = 1;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            uint64_t m = pl_get<W>(bits, w, i);
+            while (m) {
+                const int b = w * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                if (b < s.norb)
+                    rb += B[b * st + (pb++)];
+                else
+                    ra += B[(b - s.norb) * st + (pa++)];
+            }
+        }
+        uint64_t lo, hi;
+        rank_join(ra, rb, s.kc.bb, lo, hi);
+        if (s.kc.kw == 1) {
+            put_top(out.key[0], out.topb, i, lo);
+        } else {
+            out.key[0][i] = lo;
+            put_top(out.key[1], out.topb, i, hi);
+        }
+        ((double *)out.pay)[i] = ((const double *)bits.pay)[i];
+    }
 }
 
 template <int W, int PM>
@@ -1013,6 +1123,22 @@ hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const 
 #define CALL(W, F) gen_target_t<W, F>(s, L, refs, nref, log2p, part, cutoff, off, tot, out, flags, st)
     PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
+}
+
+hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t gg = (n + 255) / 256;
+    dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_refs_rank<1>), g, b, 0, st, s, bits, n, out); break;
+    case 2: hipLaunchKernelGGL((k_refs_rank<2>), g, b, 0, st, s, bits, n, out); break;
+    case 3: hipLaunchKernelGGL((k_refs_rank<3>), g, b, 0, st, s, bits, n, out); break;
+    case 4: hipLaunchKernelGGL((k_refs_rank<4>), g, b, 0, st, s, bits, n, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts, uint64_t *off,

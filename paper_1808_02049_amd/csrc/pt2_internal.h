@@ -26,6 +26,7 @@ constexpr int RED_TILE = RED_THREADS * RED_ITEMS;     // records per reduce tile
 constexpr int RED_GRID = 4096;                        // fixed -> bit-reproducible sums
 constexpr int RED_LDS_REFS = 64;                      // reference keys staged per tile
 constexpr size_t RED_LDS_TABLE_MAX = 36 * 1024;       // packed diagonal table kept in LDS up to this size
+constexpr size_t RED_LDS_MAX = 64 * 1024;             // dynamic LDS of one single-pass workgroup
 constexpr int GEN_THREADS = 256;
 
 // Device-side error flags (bitmask in Flags::err).
@@ -43,9 +44,26 @@ struct Flags {
     uint32_t pad;
 };
 
+// Compressed record keys.  Per spin, the occupied orbitals o_1 < ... < o_n
+// of a string have the colex rank sum_i C(o_i, i) (the combinatorial number
+// system), a bijection onto [0, C(norb, n)) that orders strings as their
+// bitmasks do.  A record key (rank_alpha << bb) | rank_beta therefore sorts
+// exactly as the determinant bitstring (alpha is the high part of both) in
+// fewer bits: 60 instead of 80 for (10a,10b) in 40 orbitals.
+struct KeyCodec {
+    int on;                 // 1: records carry rank keys
+    int kw;                 // key words of a record (1 or 2)
+    int ktop;               // bytes of the records' top key plane
+    int kbits;              // key bits
+    int bb;                 // bits of the beta rank
+    int stride;             // row length of the binomial table
+    const uint64_t *binom;  // C(x, j) at [x * stride + j], 0 <= x <= norb, 0 <= j < stride (device)
+};
+
 // Device view of the Hamiltonian (all pointers are device memory).
 struct DevSys {
     int norb, na, nb, W;
+    KeyCodec kc;
     const double *h;    // norb x norb
     const double *V;    // norb^4, (pq|rs) row-major
     const float *h32;   // FP32 copies (precision form), else null
@@ -127,7 +145,91 @@ struct ExcLayout {
     int64_t nSa, nSb, nDaa, nDbb, nDab;   // block sizes
     int64_t o1, o2, o3, o4, nper;         // block offsets; nper = total
     int nvpa, nvpb, nopa, nopb;           // virtual / occupied pair counts
+    int rank = 0;                         // records carry rank keys (KeyCodec)
 };
+
+// ---- rank keys (see KeyCodec) ----
+__host__ __device__ inline void rank_join(uint64_t ra, uint64_t rb, int bb, uint64_t &lo, uint64_t &hi)
+{
+    if (bb == 0) {
+        lo = ra, hi = 0;
+    } else if (bb == 64) {
+        lo = rb, hi = ra;
+    } else {
+        lo = rb | (ra << bb), hi = ra >> (64 - bb);
+    }
+}
+
+__host__ __device__ inline void rank_split(uint64_t lo, uint64_t hi, int bb, uint64_t &ra, uint64_t &rb)
+{
+    if (bb == 0) {
+        ra = lo, rb = 0;
+    } else if (bb == 64) {
+        ra = hi, rb = lo;
+    } else {
+        rb = lo & ((1ull << bb) - 1), ra = (lo >> bb) | (hi << (64 - bb));
+    }
+}
+
+// Rank of a spin string given as its ascending occupied list occ[0..n) with
+// the entries at positions skip1, skip2 removed (-1: none) and the orbitals
+// add1 < add2 inserted (-1: none), by merging the two sorted sequences.
+__device__ inline uint64_t rank_edit(const uint8_t *occ, int n, int skip1, int skip2, int add1, int add2,
+                                     const uint64_t *B, int stride)
+{
+    uint64_t r = 0;
+    int pos = 1, i = 0;
+    int ad = add1 >= 0 ? add1 : add2, ad2 = add1 >= 0 ? add2 : -1;
+    while (true) {
+        while (i < n && (i == skip1 || i == skip2))
+            i++;
+        const int x = i < n ? (int)occ[i] : 0x7fffffff;
+        const int y = ad >= 0 ? ad : 0x7fffffff;
+        if (x == 0x7fffffff && y == 0x7fffffff)
+            break;
+        if (x < y) {
+            r += B[x * stride + pos];
+            i++;
+        } else {
+            r += B[y * stride + pos];
+            ad = ad2, ad2 = -1;
+        }
+        pos++;
+    }
+    return r;
+}
+
+// Set the bits of the spin string with rank r (n electrons) at bit offset off.
+template <int WB>
+__device__ inline void unrank_spin(uint64_t r, int n, int norb, int off, const uint64_t *B, int stride,
+                                   uint64_t (&bits)[WB])
+{
+    int x = norb - 1;
+    for (int j = n; j >= 1; j--) {
+        while (B[x * stride + j] > r)
+            x--;
+        r -= B[x * stride + j];
+        const int b = off + x;
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            bits[w] |= (w == (b >> 6)) ? (1ull << (b & 63)) : 0ull;
+        x--;
+    }
+}
+
+// Bitstring of the determinant with rank key (lo, hi).
+template <int WB>
+__device__ inline void unrank_key(uint64_t lo, uint64_t hi, int norb, int na, int nb, int bb, const uint64_t *B,
+                                  int stride, uint64_t (&bits)[WB])
+{
+    uint64_t ra, rb;
+    rank_split(lo, hi, bb, ra, rb);
+#pragma unroll
+    for (int w = 0; w < WB; w++)
+        bits[w] = 0;
+    unrank_spin<WB>(ra, na, norb, norb, B, stride, bits);
+    unrank_spin<WB>(rb, nb, norb, 0, B, stride, bits);
+}
 
 inline ExcLayout make_layout(int norb, int na, int nb)
 {
@@ -220,9 +322,13 @@ hipError_t launch_planes_to_aos(int W, int pay_bytes, const Planes &in, int64_t 
                                 double *pay, hipStream_t st);
 
 // reduce.hip
-hipError_t launch_reduce(const DevSys &s, int fp32, const Planes &sorted, int64_t n,
+// sorted: records with kw key words (rank keys when s.kc.on); refs: the
+// reference keys in the same format, sorted.
+hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n,
                          const Planes &refs, int64_t nref, double e0, Partial *partials, Flags *flags,
                          hipStream_t st);
+// Rank keys of sorted bitstring references (planes of kw words + coefficients).
+hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
 // Inspection: unique keys and numerators (n_out on device).

@@ -266,10 +266,12 @@ struct Anchor {
     double e;
 };
 
-template <int W>
+// k is the record key (W words); the diagonal and the checksum use the
+// bitstring (WB words), which is k itself or, for rank keys, unranked from it.
+template <int W, int WB, bool RK>
 __device__ inline void process_segment(const DevSys &s, const double *Tp, const Anchor &an, const Planes &refs,
                                        const RefSlice &rs, const uint64_t *s_rk, const double *s_rc, double e0,
-                                       const uint64_t (&k)[W], double num, Acc &a)
+                                       const uint64_t (&k)[W], double num, Acc &a, const uint64_t *binom)
 {
     a.n_unique++;
     if (rs.staged) {
@@ -303,7 +305,15 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
             }
         }
     }
-    const double haa = diag_anchor<W>(Tp, 2 * s.norb, s.na + s.nb, k, an.key, an.g, an.e);
+    uint64_t kb[WB];
+    if constexpr (RK) {
+        unrank_key<WB>(k[0], W > 1 ? k[W > 1 ? 1 : 0] : 0ull, s.norb, s.na, s.nb, s.kc.bb, binom, s.kc.stride, kb);
+    } else {
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            kb[w] = k[w < W ? w : 0];
+    }
+    const double haa = diag_anchor<WB>(Tp, 2 * s.norb, s.na + s.nb, kb, an.key, an.g, an.e);
     const double den = e0 - haa;
     a.n_ext++;
     const double ad = fabs(den);
@@ -314,7 +324,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
         a.singular = 1;
     else
         neumaier(a.e_sum, a.e_comp, num * num / den);
-    const uint64_t m = key_mix<W>(k);
+    const uint64_t m = key_mix<WB>(kb);
     a.kx ^= m;
     a.ks += m;
 }
@@ -351,7 +361,7 @@ constexpr int RED_Q = RED_TILE + 1;  // segment ends of one tile plus a continua
 
 // Each workgroup takes a contiguous range of tiles, so the cursor into the
 // sorted reference list only moves forward.
-template <int W, int PB>
+template <int W, int PB, int WB, bool RK>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int64_t n, Planes refs, int64_t nref,
                                                         double e0, int64_t tiles_per_block, int lds_table,
                                                         size_t q_bytes, Partial *partials, Flags *flags)
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ double s_cv;
     __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
-    __shared__ uint64_t s_anc[W];
+    __shared__ uint64_t s_anc[WB];
     __shared__ double s_er[RED_THREADS / 64];
 
     const int nso = 2 * s.norb;
@@ -376,12 +386,20 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     // g vector of the tile's anchor (nso entries) after the queue region
     double *s_g = (double *)(dyn + q_bytes);
     const double *Tp = s.T;
+    const int ntri = nso * (nso + 1) / 2;
     if (lds_table) {
         double *t = (double *)(dyn + q_bytes + (size_t)nso * 8);
-        const int ntri = nso * (nso + 1) / 2;
         for (int i = tid; i < ntri; i += RED_THREADS)
             t[i] = s.T[i];
         Tp = t;
+    }
+    // binomial table for unranking rank keys, after the pair table
+    uint64_t *binom = nullptr;
+    if constexpr (RK) {
+        binom = (uint64_t *)(dyn + q_bytes + (size_t)nso * 8 + (lds_table ? (size_t)ntri * 8 : 0));
+        const int nb = (s.norb + 1) * s.kc.stride;
+        for (int i = tid; i < nb; i += RED_THREADS)
+            binom[i] = s.kc.binom[i];
     }
     Acc a;
     acc_init(a);
@@ -413,9 +431,18 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 s_lo = lo;
                 s_hi = hi;
                 s_cflag = 0;
+                if constexpr (RK) {
+                    uint64_t kb[WB];
+                    unrank_key<WB>(kf[0], W > 1 ? kf[W > 1 ? 1 : 0] : 0ull, s.norb, s.na, s.nb, s.kc.bb, binom,
+                                   s.kc.stride, kb);
 #pragma unroll
-                for (int w = 0; w < W; w++)
-                    s_anc[w] = kf[w];
+                    for (int w = 0; w < WB; w++)
+                        s_anc[w] = kb[w];
+                } else {
+#pragma unroll
+                    for (int w = 0; w < WB; w++)
+                        s_anc[w] = kf[w < W ? w : 0];
+                }
             }
         }
         __syncthreads();
@@ -430,7 +457,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 gx = hx;
                 rowx = occ ? hx : 0.0;
 #pragma unroll
-                for (int w = 0; w < W; w++) {
+                for (int w = 0; w < WB; w++) {
                     uint64_t m = s_anc[w];
                     while (m) {
                         const int c = w * 64 + __builtin_ctzll(m);
@@ -647,7 +674,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
 #pragma unroll
             for (int w = 0; w < W; w++)
                 kk[w] = q_key[w * RED_Q + e];
-            process_segment<W>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a);
+            process_segment<W, WB, RK>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom);
         }
         __syncthreads();
     }
@@ -763,34 +790,60 @@ __global__ void k_numerators(Planes in, int64_t n, Planes refs, int64_t nref, ui
 
 }  // namespace
 
-hipError_t launch_reduce(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &refs, int64_t nref,
-                         double e0, Partial *partials, Flags *flags, hipStream_t st)
+hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n, const Planes &refs,
+                         int64_t nref, double e0, Partial *partials, Flags *flags, hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
     const int nso = 2 * s.norb;
     const size_t tri_bytes = (size_t)nso * (nso + 1) / 2 * 8;
-    const int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
-    size_t q_bytes = (size_t)(s.W + 1) * RED_Q * 8;
+    int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
+    const bool rk = s.kc.on != 0;
+    size_t q_bytes = (size_t)(kw + 1) * RED_Q * 8;
     if (q_bytes < sizeof(Partial) * RED_THREADS)
         q_bytes = sizeof(Partial) * RED_THREADS;
     q_bytes = (q_bytes + 15) & ~(size_t)15;
-    const size_t dyn = q_bytes + (size_t)nso * 8 + (lds_table ? tri_bytes : 0);
+    const size_t binom_bytes = rk ? (size_t)(s.norb + 1) * s.kc.stride * 8 : 0;
+    const size_t fixed = q_bytes + (size_t)nso * 8 + binom_bytes;
+    if (fixed + (lds_table ? tri_bytes : 0) > RED_LDS_MAX)
+        lds_table = 0;  // the pair table is then read through the caches
+    const size_t dyn = fixed + (lds_table ? tri_bytes : 0);
+    if (dyn > RED_LDS_MAX)
+        return hipErrorInvalidValue;
     dim3 g(RED_GRID), b(RED_THREADS);
-#define RD(WW, PB) \
-    hipLaunchKernelGGL((k_reduce<WW, PB>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, q_bytes, \
-                       partials, flags)
-    switch (s.W * 2 + (fp32 ? 0 : 1)) {
-    case 2: RD(1, 4); break;
-    case 3: RD(1, 8); break;
-    case 4: RD(2, 4); break;
-    case 5: RD(2, 8); break;
-    case 6: RD(3, 4); break;
-    case 7: RD(3, 8); break;
-    case 8: RD(4, 4); break;
-    case 9: RD(4, 8); break;
-    default: return hipErrorInvalidValue;
+#define RD(WW, PB, WBB, RKK)                                                                                     \
+    hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, \
+                       q_bytes, partials, flags)
+#define RD2(WW, WBB, RKK)      \
+    do {                       \
+        if (fp32)              \
+            RD(WW, 4, WBB, RKK); \
+        else                   \
+            RD(WW, 8, WBB, RKK); \
+    } while (0)
+    if (!rk) {
+        if (kw != s.W)
+            return hipErrorInvalidValue;
+        switch (kw) {
+        case 1: RD2(1, 1, false); break;
+        case 2: RD2(2, 2, false); break;
+        case 3: RD2(3, 3, false); break;
+        case 4: RD2(4, 4, false); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (kw * 8 + s.W) {
+        case 8 + 1: RD2(1, 1, true); break;
+        case 8 + 2: RD2(1, 2, true); break;
+        case 8 + 3: RD2(1, 3, true); break;
+        case 8 + 4: RD2(1, 4, true); break;
+        case 16 + 2: RD2(2, 2, true); break;
+        case 16 + 3: RD2(2, 3, true); break;
+        case 16 + 4: RD2(2, 4, true); break;
+        default: return hipErrorInvalidValue;
+        }
     }
+#undef RD2
 #undef RD
     return hipGetLastError();
 }

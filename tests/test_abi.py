@@ -85,6 +85,8 @@ def test_bad_options_rejected():
         pt2.Context(h, eri, 4, 2, 2, cutoff=-1.0)
     with pytest.raises(pt2.PT2Error):
         pt2.Context(h, eri, 4, 2, 2, log2_partitions=13)
+    with pytest.raises(pt2.PT2Error):
+        pt2.Context(h, eri, 4, 2, 2, compress_keys=2)
     o = pt2.default_options()
     o.precision = 3
     ctx = pt2._CTX()

@@ -4,6 +4,7 @@ Keys and counts must match bit for bit; FP64 energies within 1e-9 Eh and
 FP32-payload energies within 1e-6 Eh of the FP64 oracle (the stated bars);
 per-term payloads within a few ulp.
 """
+import math
 import os
 
 import numpy as np
@@ -56,13 +57,13 @@ COUNT_KEYS = ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", 
               "n_nonneg_denom")
 
 
-def assert_matches(got, ref, tol=1e-9):
+def assert_matches(got, ref, tol=1e-9, cross_tol=1e-11):
     print(f"E gpu={got['e_pt2']:.15f} oracle={ref['e_pt2']:.15f} dE={got['e_pt2'] - ref['e_pt2']:.2e}",
           flush=True)
     assert abs(got["e_pt2"] - ref["e_pt2"]) <= tol
     for k in COUNT_KEYS:
         assert got[k] == ref[k], (k, got[k], ref[k])
-    assert got["ref_cross"] == pytest.approx(ref["ref_cross"], abs=1e-11)
+    assert got["ref_cross"] == pytest.approx(ref["ref_cross"], abs=cross_tol)
     if ref["n_external"]:
         assert got["min_abs_denom"] == pytest.approx(ref["min_abs_denom"], rel=1e-12)
 
@@ -249,6 +250,46 @@ def test_random_systems_all_widths(pt2, norb, na, nb, nref, log2p):
     assert np.array_equal(gk, ok)
     np.testing.assert_allclose(gv, ov, rtol=0, atol=1e-14)
     ctx.close()
+
+
+ALL_FIELDS = ("e_pt2", "n_contrib", "n_after_cutoff", "n_unique", "n_external", "n_in_ref_hit",
+              "n_nonneg_denom", "key_xor", "key_sum", "ref_cross", "min_abs_denom")
+
+
+@pytest.mark.parametrize("norb,na,nb,nref,log2p,prec", [
+    (12, 4, 4, 40, -1, "fp64"), (20, 6, 3, 60, 3, "fp64"), (33, 3, 2, 25, -1, "fp32"),
+    (40, 10, 10, 30, -1, "fp64"), (40, 4, 4, 50, 4, "fp32"), (64, 3, 3, 10, -1, "fp64"),
+    (76, 5, 5, 12, 2, "fp64"), (100, 4, 3, 8, -1, "fp64"), (128, 3, 3, 6, 1, "fp64"),
+    (9, 9, 0, 1, -1, "fp64"), (10, 0, 3, 20, -1, "fp64")])
+def test_rank_keys_give_identical_results(pt2, norb, na, nb, nref, log2p, prec):
+    """Terms keyed by the combinatorial rank of their determinant sort in the
+    bitstring order, so every result equals the bitstring-keyed run bit for
+    bit; both match the oracle."""
+    h, eri, _ = synth.make_integrals(norb, 6, 8000 + norb)
+    nref = min(nref, math.comb(norb, na) * math.comb(norb, nb))
+    dets = synth.random_determinants(norb, na, nb, nref, norb + 1)
+    c = np.random.default_rng(norb).normal(size=nref)
+    c /= np.linalg.norm(c)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    # E0 below every diagonal element involved: no near-zero denominators,
+    # whose conditioning would amplify last-bit differences of H_aa
+    keys, _ = O.numerators(dets, c)
+    e0 = float(np.concatenate([O.diag(keys), O.diag(dets)]).min()) - 1.0
+    res = {}
+    for mode in (0, 1):
+        ctx = pt2.Context(h, eri, norb, na, nb, log2_partitions=log2p, precision=prec, compress_keys=mode)
+        res[mode] = ctx.evaluate(dets, c, e0)
+        ctx.close()
+    print("key bits", res[0]["key_bits"], "->", res[1]["key_bits"], flush=True)
+    assert res[0]["key_bits"] == 2 * norb
+    assert res[1]["key_bits"] <= 2 * norb
+    for k in ALL_FIELDS:
+        assert res[0][k] == res[1][k], (k, res[0][k], res[1][k])
+    ref, _ = O.pt2(dets, c, e0)
+    if prec == "fp64":
+        assert_matches(res[1], ref)
+    else:  # FP32 terms: sum_i c_i N_i carries their rounding too
+        assert_matches(res[1], ref, tol=1e-6, cross_tol=1e-7)
 
 
 def test_workspace_reuse_with_smaller_reference(pt2):
