@@ -104,7 +104,7 @@ typedef struct {
                                       (per spin, sum_i C(o_i, i) over the ascending
                                       occupied orbitals o_i; alpha rank above beta
                                       rank) when both ranks fit 64 bits and this
-                                      saves at least a third of the sort digits;
+                                      saves at least 30% of the sort digits;
                                       it orders terms exactly as the bitstrings,
                                       so results are unchanged.  0: always the
                                       bitstring; 1: the rank whenever it fits         */

@@ -161,6 +161,7 @@ struct Workspace {
     Buf dets, coef;          // device copies of host inputs
     Buf refA, refB;          // reference planes (W keys + FP64 coefficient)
     Buf refK;                // the references' rank keys (same order) when records carry them
+    Buf tref;                // reference range of every single-pass tile
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -177,6 +178,7 @@ struct Workspace {
     void release()
     {
         buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB), buf_free(A, refK);
+        buf_free(A, tref);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
@@ -709,7 +711,10 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         }
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
-        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, ds->partials, &ds->flags, st));
+        if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
+            return rc;
+        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, ds->partials,
+                             &ds->flags, st));
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;
@@ -1305,10 +1310,12 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         const int bb = bits_for(C[(size_t)norb * stride + nbeta]);
         const int kbits = ba + bb;
         const int kw = std::max(1, (kbits + 63) / 64);
-        // automatic only where it removes at least a third of the digit
-        // passes: rank digits are dense, so a scatter tile writes shorter runs
-        // (at (10a,10b)/40, 8 rank passes took longer than 10 bitstring passes)
-        const bool worth = 3 * ((kbits + 7) / 8) <= 2 * ((2 * norb + 7) / 8);
+        // automatic only where it removes at least 30% of the digit passes:
+        // rank digits are dense, so a scatter tile writes shorter runs, and
+        // ranking costs time in generation and the single pass.  Measured:
+        // (10a,10b)/40, 8 rank passes against 10: 224 ms against 192 ms;
+        // (14a,14b)/76, 13 against 19: 36.1 s against 39.8 s.
+        const bool worth = 10 * ((kbits + 7) / 8) <= 7 * ((2 * norb + 7) / 8);
         if (fits && kw <= 2 && (o.compress_keys == 1 || worth)) {
             std::vector<uint64_t> C64(C.size());
             for (size_t i = 0; i < C.size(); i++)

@@ -359,12 +359,32 @@ __device__ inline int64_t ref_advance(const Planes &refs, int64_t nref, int64_t 
 
 constexpr int RED_Q = RED_TILE + 1;  // segment ends of one tile plus a continuation
 
-// Each workgroup takes a contiguous range of tiles, so the cursor into the
-// sorted reference list only moves forward.
+// Reference range of every tile: [lo, hi) holds the reference keys between
+// the tile's first and last record keys (one thread per tile, ahead of the
+// single pass, so that no workgroup waits on a search between its tiles).
+template <int W>
+__global__ void k_tile_refs(Planes in, int64_t n, Planes refs, int64_t nref, int64_t *range)
+{
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t base = t * RED_TILE;
+        const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
+        uint64_t kf[W], kl[W];
+        load_key<W>(in, base, kf);
+        load_key<W>(in, tend - 1, kl);
+        const int64_t lo = ref_bound<W>(refs, 0, nref, kf, false);
+        range[2 * t] = lo;
+        range[2 * t + 1] = ref_bound<W>(refs, lo, nref, kl, true);
+    }
+}
+
+// Each workgroup takes a contiguous range of tiles.
 template <int W, int PB, int WB, bool RK>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int64_t n, Planes refs, int64_t nref,
                                                         double e0, int64_t tiles_per_block, int lds_table,
-                                                        size_t q_bytes, Partial *partials, Flags *flags)
+                                                        size_t q_bytes, const int64_t *range, Partial *partials,
+                                                        Flags *flags)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ uint8_t s_f[RED_THREADS / 64];
@@ -407,29 +427,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
     const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
-    int64_t cursor = 0;
-    if (t_begin < t_end && tid < 64) {
-        uint64_t kf[W];
-        load_key<W>(in, t_begin * RED_TILE, kf);
-        int64_t lo = 0;
-        if (lane == 0)
-            lo = ref_bound<W>(refs, 0, nref, kf, false);
-        cursor = __shfl(lo, 0);
-    }
-
     for (int64_t tile = t_begin; tile < t_end; tile++) {
         const int64_t base = tile * RED_TILE;
         const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
-        if (tid < 64) {
-            uint64_t kf[W], kl[W];
+        if (tid == 0) {
+            uint64_t kf[W];
             load_key<W>(in, base, kf);
-            load_key<W>(in, tend - 1, kl);
-            const int64_t lo = ref_advance<W>(refs, nref, cursor, kf, false);
-            const int64_t hi = ref_advance<W>(refs, nref, lo, kl, true);
-            cursor = lo;
-            if (lane == 0) {
-                s_lo = lo;
-                s_hi = hi;
+            {
+                s_lo = range[2 * tile];
+                s_hi = range[2 * tile + 1];
                 s_cflag = 0;
                 if constexpr (RK) {
                     uint64_t kb[WB];
@@ -791,7 +797,7 @@ __global__ void k_numerators(Planes in, int64_t n, Planes refs, int64_t nref, ui
 }  // namespace
 
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n, const Planes &refs,
-                         int64_t nref, double e0, Partial *partials, Flags *flags, hipStream_t st)
+                         int64_t nref, double e0, int64_t *range, Partial *partials, Flags *flags, hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
@@ -810,10 +816,21 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     const size_t dyn = fixed + (lds_table ? tri_bytes : 0);
     if (dyn > RED_LDS_MAX)
         return hipErrorInvalidValue;
+    if (ntiles > 0) {
+        const int64_t gt = (ntiles + 255) / 256;
+        dim3 gg((unsigned)(gt < 4096 ? gt : 4096)), bb(256);
+        switch (kw) {
+        case 1: hipLaunchKernelGGL((k_tile_refs<1>), gg, bb, 0, st, sorted, n, refs, nref, range); break;
+        case 2: hipLaunchKernelGGL((k_tile_refs<2>), gg, bb, 0, st, sorted, n, refs, nref, range); break;
+        case 3: hipLaunchKernelGGL((k_tile_refs<3>), gg, bb, 0, st, sorted, n, refs, nref, range); break;
+        case 4: hipLaunchKernelGGL((k_tile_refs<4>), gg, bb, 0, st, sorted, n, refs, nref, range); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RD(WW, PB, WBB, RKK)                                                                                     \
     hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, \
-                       q_bytes, partials, flags)
+                       q_bytes, range, partials, flags)
 #define RD2(WW, WBB, RKK)      \
     do {                       \
         if (fp32)              \
