@@ -63,6 +63,11 @@ enum {
 };
 
 enum {
+    PT2_EXCLUDE_SEARCH = 0,
+    PT2_EXCLUDE_SUBTRACT = 1
+};
+
+enum {
     PT2_FP64 = 0,          /* FP64 integrals and numerator terms                 */
     PT2_FP32_PAYLOAD = 1,  /* H_ai c_i computed in FP64 and stored rounded to
                               FP32 (4 bytes less per record and sort pass);
@@ -108,6 +113,16 @@ typedef struct {
                                       it orders terms exactly as the bitstrings,
                                       so results are unchanged.  0: always the
                                       bitstring; 1: the rank whenever it fits         */
+    int exclusion;                 /* PT2_EXCLUDE_SEARCH (default): drop reference
+                                      determinants by a search of the sorted
+                                      reference (Section V, direct check);
+                                      PT2_EXCLUDE_SUBTRACT: keep them and subtract
+                                      sum_i c_i^2 (E0 - H_ii), exact only when the
+                                      coefficients are an eigenvector of H in the
+                                      reference space with eigenvalue E0 (Section V,
+                                      removal of duplicate contributions).  With
+                                      subtraction the counts and checksums cover
+                                      every distinct determinant                      */
 } pt2_options;
 
 typedef struct {

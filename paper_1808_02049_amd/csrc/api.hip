@@ -87,6 +87,7 @@ struct Alloc {
 struct Buf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;  // a slice of the serving arena: never freed, only dropped
 };
 
 int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
@@ -115,7 +116,7 @@ int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
 
 void buf_free(const Alloc &A, Buf &b)
 {
-    if (b.p) {
+    if (b.p && !b.borrowed) {
         if (A.ff) {
             // an external allocator may hand the block out at once: let every
             // queued kernel that might still use it finish first
@@ -129,6 +130,7 @@ void buf_free(const Alloc &A, Buf &b)
     }
     b.p = nullptr;
     b.bytes = 0;
+    b.borrowed = false;
 }
 
 int buf_ensure(const Alloc &A, Buf &b, size_t bytes)
@@ -325,6 +327,36 @@ int ensure_scan(Workspace &ws, int64_t n)
         ws.scan_tiles = tiles;
     }
     return PT2_OK;
+}
+
+// Record and scan buffers of a request whose largest subset holds cap records
+// (what ensure_records and ensure_scan allocate), as one slice.
+size_t slice_bytes(int W, int pb, int topb, int64_t cap)
+{
+    const int64_t tiles = std::max<int64_t>(1, (cap + SORT_TILE - 1) / SORT_TILE);
+    const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    return 2 * planes_bytes(W, cap, pb, topb) + align256((size_t)tiles * 256 * 4) +
+           align256((size_t)tiles * 256 * 8) + 2 * align256((size_t)chunks * 256 * 8);
+}
+
+// Point a workspace's record and scan buffers into a slice of slice_bytes().
+void carve_slice(Workspace &ws, char *p, int W, int pb, int topb, int64_t cap)
+{
+    const int64_t tiles = std::max<int64_t>(1, (cap + SORT_TILE - 1) / SORT_TILE);
+    const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    auto take = [&](Buf &b, size_t bytes) {
+        buf_free(ws.A, b);
+        b.p = p, b.bytes = bytes, b.borrowed = true;
+        p += bytes;
+    };
+    take(ws.recA, planes_bytes(W, cap, pb, topb));
+    take(ws.recB, planes_bytes(W, cap, pb, topb));
+    take(ws.counts, align256((size_t)tiles * 256 * 4));
+    take(ws.offs, align256((size_t)tiles * 256 * 8));
+    take(ws.csum, align256((size_t)chunks * 256 * 8));
+    take(ws.coff, align256((size_t)chunks * 256 * 8));
+    ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb, ws.rec_topb = topb;
+    ws.scan_tiles = tiles;
 }
 
 // Stable LSD sort of n records held in *src (ping-pong with *dst) on key bits
@@ -625,6 +657,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     const double t0 = now_ms();
     const RecLayout RL = rec_layout(c, J.dump != 0);
     const int W = RL.W;  // key words of a stored term
+    const bool subtract = c->opt.exclusion == PT2_EXCLUDE_SUBTRACT && !J.dump;
     DevSys sys = c->sys;
     ExcLayout L = c->L;
     if (!RL.rank)
@@ -660,6 +693,16 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         refs_red = planes_of(ws.refK, W, J.n, 8, RL.topb);
         HIPCHK(launch_refs_rank(sys, refs, J.n, refs_red, st));
+    }
+    // subtraction form: sum_i c_i^2 (E0 - H_ii), removed from the total below
+    double ref_terms = 0.0;
+    if (subtract) {
+        Small *d0 = ws.dsmall();
+        HIPCHK(launch_ref_terms(sys, refs, J.n, J.e0, d0->partials, &d0->result, st));
+        Partial pr;
+        HIPCHK(hipMemcpyAsync(&pr, &d0->result, sizeof pr, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ref_terms = pr.e_sum + pr.e_comp;
     }
     Plan P;
     Job JJ = J;
@@ -713,8 +756,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
-        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, ds->partials,
-                             &ds->flags, st));
+        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, subtract ? 0 : 1,
+                             ds->partials, &ds->flags, st));
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;
@@ -813,6 +856,14 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         res.key_sum += p.key_sum;
         res.min_abs_denom = std::min(res.min_abs_denom, p.min_abs_denom);
     }
+    if (subtract) {
+        const double x = -ref_terms, t = sum + x;
+        if (fabs(sum) >= fabs(x))
+            comp += (sum - t) + x;
+        else
+            comp += (x - t) + sum;
+        sum = t;
+    }
     res.e_pt2 = sum + comp;
     res.n_partitions = (uint32_t)P.parts.size();
     for (auto &e : tm.evs) {
@@ -853,11 +904,55 @@ struct Request {
     double projected;
     double cap;          // plan budget: bytes of record buffers one subset may use
     bool alone = false;  // retried after an allocation failure: run with nothing else
+    int64_t cap_records = 0;       // projected records of the largest subset
+    size_t arena_off = SIZE_MAX;   // slice of the device arena, if admitted into one
     int retries = 0;
     bool done = false;
     int rc = PT2_OK;
     std::string err;
     pt2_result res;
+};
+
+// One device allocation for the record and scan buffers of served
+// requests, carved into slices first-fit: no allocation, mapping or
+// unmapping per request.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> bytes; disjoint, coalesced
+
+    bool alloc(size_t bytes, size_t &off)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest)
+                    free_[off + bytes] = rest;
+                return true;
+            }
+        return false;
+    }
+
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
 };
 
 struct Worker {
@@ -900,7 +995,8 @@ class Scheduler {
             k++;
             per = subset_bytes(RL.W, pb, RL.topb, total / (double)(1 << k) * 1.02 + 4096.0);
         }
-        r->projected = per;
+        r->cap_records = (int64_t)(total / (double)(1 << k) * 1.02 + 4096.0);
+        r->projected = (double)slice_bytes(RL.W, pb, RL.topb, r->cap_records);
         std::unique_lock<std::mutex> lk(mu_);
         start_workers_locked(c);
         r->id = next_id_++;
@@ -980,6 +1076,12 @@ class Scheduler {
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
             (void)hipMemPoolTrimTo(pool, 0);
+        auto it = arena_.find(dev);
+        if (it != arena_.end()) {
+            if (it->second.base)
+                (void)hipFree(it->second.base);
+            arena_.erase(it);
+        }
         (void)hipGetLastError();
     }
 
@@ -1017,6 +1119,29 @@ class Scheduler {
     std::unordered_map<int, double> in_use_;  // projected bytes of running requests, per device
     std::unordered_map<int, int> running_;    // running requests, per device
     std::unordered_map<int, double> dev_budget_;
+    std::unordered_map<int, Arena> arena_;
+
+    // the device's arena, made at its first use with the device budget
+    Arena &arena_locked(int dev)
+    {
+        auto it = arena_.find(dev);
+        if (it != arena_.end())
+            return it->second;
+        Arena &a = arena_[dev];
+        const size_t bytes = (size_t)device_budget_locked(dev) & ~(size_t)255;
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(dev);
+        void *p = nullptr;
+        if (bytes && hipMalloc(&p, bytes) == hipSuccess) {
+            a.base = (char *)p;
+            a.size = bytes;
+            a.free_[0] = bytes;
+        }
+        (void)hipGetLastError();
+        (void)hipSetDevice(prev);
+        return a;
+    }
     bool stopping_ = false;
     bool atexit_ = false;
 
@@ -1038,16 +1163,27 @@ class Scheduler {
         }
     }
 
-    // first queued request whose projected bytes, added to what runs on its
-    // device, fit its own context's budget (or that would run alone there);
-    // a request bypassed too often blocks the rest
+    // first queued request whose record and scan buffers fit a free slice of
+    // its device's arena (or that would run alone there, with buffers of its
+    // own); a request bypassed too often blocks the rest
     Request *pick_locked()
     {
         for (size_t i = 0; i < queue_.size(); i++) {
             Request *r = queue_[i];
             const int dev = r->ctx->opt.device;
-            const double limit = std::min(r->cap, device_budget_locked(dev));
-            if (running_[dev] == 0 || (!r->alone && in_use_[dev] + r->projected <= limit)) {
+            bool take = false;
+            r->arena_off = SIZE_MAX;
+            if (!r->alone || running_[dev] == 0) {
+                Arena &a = arena_locked(dev);
+                size_t off = 0;
+                if (r->projected <= (double)a.size && a.alloc((size_t)r->projected, off)) {
+                    r->arena_off = off;
+                    take = true;
+                } else if (running_[dev] == 0) {
+                    take = true;
+                }
+            }
+            if (take) {
                 queue_.erase(queue_.begin() + (long)i);
                 return r;
             }
@@ -1076,6 +1212,7 @@ class Scheduler {
             pt2_ctx *c = r->ctx;
             in_use_[c->opt.device] += r->projected;
             running_[c->opt.device]++;
+            char *abase = r->arena_off != SIZE_MAX ? arena_[c->opt.device].base : nullptr;
             lk.unlock();
             (void)hipSetDevice(c->opt.device);
             Alloc A = c->A;
@@ -1083,6 +1220,11 @@ class Scheduler {
             if (!w->ws->A.same_source(A) || w->ws->A.stream != A.stream)
                 w->ws->release();  // buffers go back to the allocator that made them
             w->ws->A = A;
+            if (r->arena_off != SIZE_MAX) {
+                const RecLayout RL = rec_layout(c, false);
+                carve_slice(*w->ws, abase + r->arena_off, RL.W, c->opt.precision != PT2_FP64 ? 4 : 8, RL.topb,
+                            r->cap_records);
+            }
             Job J{};
             J.dets = r->dets.data();
             J.coeffs = r->c.data();
@@ -1106,6 +1248,10 @@ class Scheduler {
             if (w->stream)
                 (void)hipStreamSynchronize(w->stream);
             lk.lock();
+            if (r->arena_off != SIZE_MAX) {
+                arena_[c->opt.device].release(r->arena_off, (size_t)r->projected);
+                r->arena_off = SIZE_MAX;
+            }
             if (rc == PT2_E_NOMEM && r->retries < 2) {
                 // memory held outside the projections (other requests, pool
                 // fragments): run it again with nothing else on the device,
@@ -1151,6 +1297,7 @@ PT2_API void pt2_default_options(pt2_options *o)
     o->cutoff = 0.0;
     o->log2_partitions = -1;
     o->compress_keys = -1;
+    o->exclusion = PT2_EXCLUDE_SEARCH;
     o->device = 0;
     o->n_streams = 4;
 }
@@ -1181,6 +1328,8 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     }
     if (o.precision != PT2_FP64 && o.precision != PT2_FP32_PAYLOAD && o.precision != PT2_FP32_ARITH)
         return fail(PT2_E_INVALID, "unknown precision %d", o.precision);
+    if (o.exclusion != PT2_EXCLUDE_SEARCH && o.exclusion != PT2_EXCLUDE_SUBTRACT)
+        return fail(PT2_E_INVALID, "exclusion must be PT2_EXCLUDE_SEARCH or PT2_EXCLUDE_SUBTRACT");
     if (!(o.cutoff >= 0.0))
         return fail(PT2_E_INVALID, "cutoff must be >= 0");
     if (o.log2_partitions > MAX_LOG2P)

@@ -325,9 +325,14 @@ hipError_t launch_planes_to_aos(int W, int pay_bytes, const Planes &in, int64_t 
 // sorted: records with kw key words (rank keys when s.kc.on); refs: the
 // reference keys in the same format, sorted.
 // range: scratch of 2 int64 per tile of RED_TILE records.
+// search == 0: no reference search (subtraction form of the exclusion).
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n,
-                         const Planes &refs, int64_t nref, double e0, int64_t *range, Partial *partials,
-                         Flags *flags, hipStream_t st);
+                         const Planes &refs, int64_t nref, double e0, int64_t *range, int search,
+                         Partial *partials, Flags *flags, hipStream_t st);
+// out->e_sum + e_comp = sum over the bitstring references of c_i^2 (E0 - H_ii)
+// (partials: 256 entries of scratch).
+hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, double e0, Partial *partials,
+                            Partial *out, hipStream_t st);
 // Rank keys of sorted bitstring references (planes of kw words + coefficients).
 hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).

@@ -271,10 +271,13 @@ struct Anchor {
 template <int W, int WB, bool RK>
 __device__ inline void process_segment(const DevSys &s, const double *Tp, const Anchor &an, const Planes &refs,
                                        const RefSlice &rs, const uint64_t *s_rk, const double *s_rc, double e0,
-                                       const uint64_t (&k)[W], double num, Acc &a, const uint64_t *binom)
+                                       const uint64_t (&k)[W], double num, Acc &a, const uint64_t *binom,
+                                       bool search)
 {
     a.n_unique++;
-    if (rs.staged) {
+    if (!search) {
+        // reference determinants stay in; their terms are subtracted afterwards
+    } else if (rs.staged) {
         int lo = 0, hi = (int)(rs.hi - rs.lo);
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -383,8 +386,8 @@ __global__ void k_tile_refs(Planes in, int64_t n, Planes refs, int64_t nref, int
 template <int W, int PB, int WB, bool RK>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int64_t n, Planes refs, int64_t nref,
                                                         double e0, int64_t tiles_per_block, int lds_table,
-                                                        size_t q_bytes, const int64_t *range, Partial *partials,
-                                                        Flags *flags)
+                                                        size_t q_bytes, const int64_t *range, int search,
+                                                        Partial *partials, Flags *flags)
 {
     extern __shared__ __align__(16) char dyn[];
     __shared__ uint8_t s_f[RED_THREADS / 64];
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         }
         RefSlice rs;
         rs.lo = s_lo, rs.hi = s_hi;
-        rs.staged = (rs.hi - rs.lo) <= RED_LDS_REFS;
+        rs.staged = search && (rs.hi - rs.lo) <= RED_LDS_REFS;
         if (rs.staged)
             for (int i = tid; i < (int)(rs.hi - rs.lo); i += RED_THREADS) {
 #pragma unroll
@@ -680,7 +683,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
 #pragma unroll
             for (int w = 0; w < W; w++)
                 kk[w] = q_key[w * RED_Q + e];
-            process_segment<W, WB, RK>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom);
+            process_segment<W, WB, RK>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom, search != 0);
         }
         __syncthreads();
     }
@@ -712,6 +715,39 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     }
     if (tid == 0)
         partials[blockIdx.x] = s_p[0];
+}
+
+// sum over the reference of c_i^2 (E0 - H_ii), per block (subtraction form
+// of the exclusion); H_ii from scratch, FP64
+template <int W>
+__global__ __launch_bounds__(256) void k_ref_terms(DevSys s, Planes refs, int64_t n, double e0, Partial *partials)
+{
+    __shared__ double s_s[256], s_c[256];
+    double sum = 0.0, comp = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        uint64_t k[W];
+        load_key<W>(refs, i, k);
+        const double ci = ((const double *)refs.pay)[i];
+        neumaier(sum, comp, ci * ci * (e0 - diag_packed<W>(s.T, 2 * s.norb, k)));
+    }
+    s_s[threadIdx.x] = sum;
+    s_c[threadIdx.x] = comp;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            double a = s_s[threadIdx.x], ca = s_c[threadIdx.x] + s_c[threadIdx.x + o];
+            neumaier(a, ca, s_s[threadIdx.x + o]);
+            s_s[threadIdx.x] = a;
+            s_c[threadIdx.x] = ca;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Partial p;
+        p.e_sum = s_s[0], p.e_comp = s_c[0], p.ref_cross = 0.0, p.min_abs_denom = __builtin_inf();
+        p.n_unique = p.n_external = p.n_hit = p.n_nonneg = p.key_xor = p.key_sum = 0;
+        partials[blockIdx.x] = p;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_final(const Partial *partials, int np, Partial *out)
@@ -797,7 +833,8 @@ __global__ void k_numerators(Planes in, int64_t n, Planes refs, int64_t nref, ui
 }  // namespace
 
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n, const Planes &refs,
-                         int64_t nref, double e0, int64_t *range, Partial *partials, Flags *flags, hipStream_t st)
+                         int64_t nref, double e0, int64_t *range, int search, Partial *partials, Flags *flags,
+                         hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
@@ -816,7 +853,7 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     const size_t dyn = fixed + (lds_table ? tri_bytes : 0);
     if (dyn > RED_LDS_MAX)
         return hipErrorInvalidValue;
-    if (ntiles > 0) {
+    if (ntiles > 0 && search) {
         const int64_t gt = (ntiles + 255) / 256;
         dim3 gg((unsigned)(gt < 4096 ? gt : 4096)), bb(256);
         switch (kw) {
@@ -830,7 +867,7 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RD(WW, PB, WBB, RKK)                                                                                     \
     hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, \
-                       q_bytes, range, partials, flags)
+                       q_bytes, range, search, partials, flags)
 #define RD2(WW, WBB, RKK)      \
     do {                       \
         if (fp32)              \
@@ -862,6 +899,21 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     }
 #undef RD2
 #undef RD
+    return hipGetLastError();
+}
+
+hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, double e0, Partial *partials,
+                            Partial *out, hipStream_t st)
+{
+    dim3 g(256), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_ref_terms<1>), g, b, 0, st, s, refs, n, e0, partials); break;
+    case 2: hipLaunchKernelGGL((k_ref_terms<2>), g, b, 0, st, s, refs, n, e0, partials); break;
+    case 3: hipLaunchKernelGGL((k_ref_terms<3>), g, b, 0, st, s, refs, n, e0, partials); break;
+    case 4: hipLaunchKernelGGL((k_ref_terms<4>), g, b, 0, st, s, refs, n, e0, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partials, 256, out);
     return hipGetLastError();
 }
 

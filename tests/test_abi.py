@@ -88,6 +88,14 @@ def test_bad_options_rejected():
     with pytest.raises(pt2.PT2Error):
         pt2.Context(h, eri, 4, 2, 2, compress_keys=2)
     o = pt2.default_options()
+    assert o.exclusion == 0
+    o.exclusion = 2
+    ctx = pt2._CTX()
+    hh = np.ascontiguousarray(h, dtype=np.float64)
+    ee = np.ascontiguousarray(eri, dtype=np.float64).reshape(-1)
+    assert pt2._lib.pt2_create(hh.ctypes.data_as(pt2._f64p), ee.ctypes.data_as(pt2._f64p), 4, 2, 2,
+                               pt2.C.byref(o), pt2.C.byref(ctx)) == pt2.PT2_E_INVALID
+    o = pt2.default_options()
     o.precision = 3
     ctx = pt2._CTX()
     hh = np.ascontiguousarray(h, dtype=np.float64)

@@ -197,6 +197,21 @@ def test_c1_fp32_arith_form(pt2, c1):
         assert got[k] == ref[k]
 
 
+def test_c1_subtraction_exclusion(pt2, c1):
+    """C1's coefficients are an eigenvector of H in the reference space, so
+    keeping the reference determinants and subtracting sum_i c_i^2 (E0 - H_ii)
+    gives the same energy as excluding them by search."""
+    for log2p in (-1, 3):
+        ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, exclusion="subtract", log2_partitions=log2p)
+        got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+        ctx.close()
+        ref = c1["ref"]
+        print("subtraction dE", got["e_pt2"] - ref["e_pt2"], flush=True)
+        assert abs(got["e_pt2"] - ref["e_pt2"]) <= 1e-9
+        assert got["n_in_ref_hit"] == 0 and got["n_unique"] == ref["n_unique"]
+        assert got["n_external"] == ref["n_external"] + ref["n_in_ref_hit"]
+
+
 def test_c1_cutoff(pt2, c1):
     k, v = c1["O"].emit(c1["dets"], c1["c"])
     cut = float(np.quantile(np.abs(v), 0.4))

@@ -104,16 +104,19 @@ def test_poll_semantics_and_busy_destroy(pt2, reqs):
     ctx.close()
 
 
-def test_tight_budget_admits_one_at_a_time(pt2, reqs):
+def test_tight_budget_splits_the_plan(pt2, reqs):
+    """A context budget below one request's record buffers forces a hash
+    split on every request of that context; served results equal the
+    synchronous evaluation under the same budget."""
     r, h, eri, dets, c, e0 = reqs[3]
-    nper = synth.n_excitations_per_det(r.norb, r.nalpha, r.nalpha)
-    need = len(dets) * nper * 2 * 20  # about one request's record buffers
-    ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, device_budget_bytes=int(need * 1.3))
+    total = len(dets) * synth.n_excitations_per_det(r.norb, r.nalpha, r.nalpha)
+    ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, device_budget_bytes=int(total * 20))
     alone = ctx.evaluate(dets, c, e0)
+    assert alone["n_partitions"] > 1
     ids = [ctx.submit(dets, c, e0) for _ in range(4)]
     for rid in ids:
         got = ctx.wait(rid)
-        for k in KEYS:
+        for k in KEYS + ("n_partitions",):
             assert got[k] == alone[k]
     ctx.close()
 
