@@ -112,7 +112,16 @@ typedef struct {
                                       saves at least 30% of the sort digits;
                                       it orders terms exactly as the bitstrings,
                                       so results are unchanged.  0: always the
-                                      bitstring; 1: the rank whenever it fits         */
+                                      bitstring; 1: the rank whenever it fits; 2:
+                                      hash records whenever 2 norb <= 254: the
+                                      64-bit Zobrist hash of the determinant (8
+                                      digit passes whatever norb is) with the parent
+                                      index and the flipped spin-orbitals, from
+                                      which the single pass rebuilds the bitstring
+                                      and separates determinants whose hashes
+                                      collide.  The automatic choice takes the form
+                                      that moves the fewest bytes through the digit
+                                      passes if it saves 30% or more               */
     int exclusion;                 /* PT2_EXCLUDE_SEARCH (default): drop reference
                                       determinants by a search of the sorted
                                       reference (Section V, direct check);
@@ -123,6 +132,9 @@ typedef struct {
                                       removal of duplicate contributions).  With
                                       subtraction the counts and checksums cover
                                       every distinct determinant                      */
+    int hash_bits;                 /* hash records: bits of the hash kept as the sort
+                                      key, 0 = 64.  Fewer bits only make collisions
+                                      common, to test their handling                 */
 } pt2_options;
 
 typedef struct {

@@ -154,6 +154,7 @@ struct Small {  // one device block for small control data
     uint64_t hist[MAX_DIG * 256];
     uint64_t bucket[MAX_DIG * 256];
     Partial partials[RED_GRID];
+    uint32_t coll[RED_GRID];  // hash records: workgroups with collided segments
     Partial result;
     unsigned long long n_out;
 };
@@ -164,6 +165,8 @@ struct Workspace {
     Buf refA, refB;          // reference planes (W keys + FP64 coefficient)
     Buf refK;                // the references' rank keys (same order) when records carry them
     Buf tref;                // reference range of every single-pass tile
+    Buf refH0, refH1;        // hash records: reference hashes with indices (sort ping-pong)
+    Buf hp, gv;              // hash records: energy and g vector of every reference
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -180,7 +183,7 @@ struct Workspace {
     void release()
     {
         buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB), buf_free(A, refK);
-        buf_free(A, tref);
+        buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
@@ -302,7 +305,14 @@ int ensure_small(Workspace &ws)
         int rc = buf_alloc(ws.A, ws.small, sizeof(Small));
         if (rc)
             return rc;
-        HIPCHK(hipMemset(ws.small.p, 0, sizeof(Small)));
+        // cleared in the order of the stream that allocated it: a block of the
+        // stream-ordered pool may have been freed by another stream whose
+        // earlier kernels still use it, which only that stream waits for
+        static_assert(sizeof(Small) % 8 == 0, "Small is cleared in 8-byte words");
+        if (ws.A.stream)
+            HIPCHK(launch_zero_u64((uint64_t *)ws.small.p, (int64_t)(sizeof(Small) / 8), ws.A.stream));
+        else
+            HIPCHK(hipMemset(ws.small.p, 0, sizeof(Small)));
     }
     if (!ws.host_small)
         HIPCHK(hipHostMalloc((void **)&ws.host_small, sizeof(Small), hipHostMallocDefault));
@@ -521,14 +531,17 @@ struct Job {
 // enables them (not for the inspection dumps, which return bitstrings).
 struct RecLayout {
     int W, topb, bits;
-    bool rank;
+    bool rank;  // rank keys
+    bool hash;  // hash records: (hash, parent and flips, payload), sorted on the hash
 };
 
 RecLayout rec_layout(const pt2_ctx *c, bool dump)
 {
+    if (c->sys.kc.hash && !dump)
+        return {2, 8, 64, false, true};
     if (c->sys.kc.on && !dump)
-        return {c->sys.kc.kw, c->sys.kc.ktop, c->sys.kc.kbits, true};
-    return {c->W, c->topb, 2 * c->norb, false};
+        return {c->sys.kc.kw, c->sys.kc.ktop, c->sys.kc.kbits, true, false};
+    return {c->W, c->topb, 2 * c->norb, false, false};
 }
 
 int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws, const Planes &refs, int64_t nref,
@@ -662,6 +675,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     ExcLayout L = c->L;
     if (!RL.rank)
         sys.kc.on = 0, L.rank = 0;
+    if (!RL.hash)
+        sys.kc.hash = 0;
     const int pm = c->opt.precision;
     const int fp32 = pm != PT2_FP64;  // 4-byte payload plane
     const int pb = fp32 ? 4 : 8;
@@ -693,6 +708,26 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         refs_red = planes_of(ws.refK, W, J.n, 8, RL.topb);
         HIPCHK(launch_refs_rank(sys, refs, J.n, refs_red, st));
+    }
+    // hash records: the references' hashes sorted, with their indices, and
+    // every reference's energy and g vector (H_aa is taken from the parent)
+    Planes refs_hash{};
+    if (RL.hash) {
+        if (J.n >= ((int64_t)1 << 32))
+            return fail(PT2_E_INVALID, "hash records take fewer than 2^32 reference determinants");
+        const int nso = 2 * c->norb;
+        if ((rc = buf_ensure(ws.A, ws.refH0, planes_bytes(1, J.n, 8, 8))) ||
+            (rc = buf_ensure(ws.A, ws.refH1, planes_bytes(1, J.n, 8, 8))) ||
+            (rc = buf_ensure(ws.A, ws.hp, (size_t)J.n * 8)) ||
+            (rc = buf_ensure(ws.A, ws.gv, (size_t)J.n * nso * 8)))
+            return rc;
+        Planes h0 = planes_of(ws.refH0, 1, J.n, 8, 8), h1 = planes_of(ws.refH1, 1, J.n, 8, 8);
+        HIPCHK(launch_refs_hash(sys, refs, J.n, h0, st));
+        Timing none;
+        if ((rc = radix_sort(ws, 1, 8, h0, h1, J.n, 64, st, none, nullptr, nullptr)))
+            return rc;
+        refs_hash = h0;
+        HIPCHK(launch_parent_g(sys, refs, J.n, (double *)ws.hp.p, (double *)ws.gv.p, st));
     }
     // subtraction form: sum_i c_i^2 (E0 - H_ii), removed from the total below
     double ref_terms = 0.0;
@@ -756,8 +791,13 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
-        HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, subtract ? 0 : 1,
-                             ds->partials, &ds->flags, st));
+        if (RL.hash)
+            HIPCHK(launch_reduce_hash(sys, fp32, A, n, refs, refs_hash, J.n, (const double *)ws.hp.p,
+                                      (const double *)ws.gv.p, J.e0, subtract ? 0 : 1, ds->partials, ds->coll,
+                                      &ds->flags, st));
+        else
+            HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, subtract ? 0 : 1,
+                                 ds->partials, &ds->flags, st));
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;
@@ -1334,8 +1374,10 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         return fail(PT2_E_INVALID, "cutoff must be >= 0");
     if (o.log2_partitions > MAX_LOG2P)
         return fail(PT2_E_INVALID, "log2_partitions must be <= %d", MAX_LOG2P);
-    if (o.compress_keys < -1 || o.compress_keys > 1)
-        return fail(PT2_E_INVALID, "compress_keys must be -1, 0 or 1");
+    if (o.hash_bits < 0 || o.hash_bits > 64)
+        return fail(PT2_E_INVALID, "hash_bits must be in [0, 64]");
+    if (o.compress_keys < -1 || o.compress_keys > 2)
+        return fail(PT2_E_INVALID, "compress_keys must be -1, 0, 1 or 2");
     if ((o.alloc == nullptr) != (o.free == nullptr))
         return fail(PT2_E_INVALID, "alloc and free hooks must be given together");
     const size_t n = (size_t)norb;
@@ -1435,9 +1477,15 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.T = (const double *)c->T.p;
     c->sys.R = (const uint64_t *)c->R.p;
 
-    // compressed keys: exact binomials C(x, j), x <= norb, j <= max(na, nb)
+    // record keys: the bitstring, the combinatorial rank, or the Zobrist hash
+    // (with the parent and the flips); cost = bytes moved per record by the
+    // digit passes
     memset(&c->sys.kc, 0, sizeof c->sys.kc);
-    if (o.compress_keys != 0) {
+    {
+        const int pb = o.precision != PT2_FP64 ? 4 : 8;
+        const double cost_bits = 2.0 * record_bytes(c->W, pb, c->topb) * ((2 * norb + 7) / 8);
+        double cost_rank = 1e300, cost_hash = 1e300;
+        // ranks: exact binomials C(x, j), x <= norb, j <= max(na, nb)
         const int nmax = std::max(nalpha, nbeta), stride = nmax + 1;
         std::vector<unsigned __int128> C((size_t)(norb + 1) * stride, 0);
         bool fits = true;
@@ -1459,25 +1507,44 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         const int bb = bits_for(C[(size_t)norb * stride + nbeta]);
         const int kbits = ba + bb;
         const int kw = std::max(1, (kbits + 63) / 64);
-        // automatic only where it removes at least 30% of the digit passes:
-        // rank digits are dense, so a scatter tile writes shorter runs, and
-        // ranking costs time in generation and the single pass.  Measured:
-        // (10a,10b)/40, 8 rank passes against 10: 224 ms against 192 ms;
-        // (14a,14b)/76, 13 against 19: 36.1 s against 39.8 s.
-        const bool worth = 10 * ((kbits + 7) / 8) <= 7 * ((2 * norb + 7) / 8);
-        if (fits && kw <= 2 && (o.compress_keys == 1 || worth)) {
+        const int tb = kbits - 64 * (kw - 1);
+        const int ktop = tb <= 16 ? 2 : (tb <= 32 ? 4 : 8);
+        const bool rank_ok = fits && kw <= 2;
+        if (rank_ok)
+            cost_rank = 2.0 * record_bytes(kw, pb, ktop) * ((kbits + 7) / 8);
+        // hash records: a spin-orbital index per byte, 0xFF marks an unused flip
+        const bool hash_ok = 2 * norb <= 254;
+        if (hash_ok)
+            cost_hash = 2.0 * record_bytes(2, pb, 8) * 8;
+        int mode = 0;  // 0 bitstring, 1 rank, 2 hash
+        if (o.compress_keys == 1 && rank_ok)
+            mode = 1;
+        else if (o.compress_keys == 2 && hash_ok)
+            mode = 2;
+        else if (o.compress_keys == -1) {
+            // only a clear saving pays: compressed digits are dense, so a
+            // scatter tile writes shorter runs, and both forms cost time in
+            // generation and the single pass.  Measured: (10a,10b)/40 rank
+            // keys (8 passes against 10) 224 ms against 192 ms; (14a,14b)/76
+            // rank keys (13 against 19) 36.1 s against 39.8 s.
+            const double best = std::min(cost_rank, cost_hash);
+            if (best <= 0.7 * cost_bits)
+                mode = cost_hash <= cost_rank ? 2 : 1;
+        }
+        if (mode == 1) {
             std::vector<uint64_t> C64(C.size());
             for (size_t i = 0; i < C.size(); i++)
                 C64[i] = (uint64_t)C[i];
             if ((rc = buf_alloc(c->A, c->binom, C64.size() * 8)))
                 return rc;
             HIPCHK(hipMemcpy(c->binom.p, C64.data(), C64.size() * 8, hipMemcpyHostToDevice));
-            const int tb = kbits - 64 * (kw - 1);
             KeyCodec &k = c->sys.kc;
-            k.on = 1, k.kw = kw, k.kbits = kbits, k.bb = bb, k.stride = stride;
-            k.ktop = tb <= 16 ? 2 : (tb <= 32 ? 4 : 8);
+            k.on = 1, k.kw = kw, k.kbits = kbits, k.bb = bb, k.stride = stride, k.ktop = ktop;
             k.binom = (const uint64_t *)c->binom.p;
             c->L.rank = 1;
+        } else if (mode == 2) {
+            c->sys.kc.hash = 1;
+            c->sys.kc.hash_mask = o.hash_bits == 0 || o.hash_bits >= 64 ? ~0ull : ((1ull << o.hash_bits) - 1);
         }
     }
     *out = c.release();

@@ -391,8 +391,28 @@ __device__ inline void put_top(void *plane, int topb, int64_t i, uint64_t v)
 // per-determinant tables; same-spin doubles rank the edited string.
 template <int W>
 __device__ inline void store_rec_key(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
-                                     const uint64_t (&key)[W], const Planes &out, int64_t pos)
+                                     const uint64_t (&key)[W], uint64_t z, int64_t det, const Planes &out,
+                                     int64_t pos)
 {
+    if (s.kc.hash) {
+        const GenHead *H = g.head;
+        const int n = s.norb;
+        uint32_t f0, f1, f2 = FLIP_NONE, f3 = FLIP_NONE;
+        if (e.kind <= 1) {
+            const int off = e.kind == 0 ? n : 0;
+            f0 = off + H->occ[e.kind][e.oi], f1 = off + H->vir[e.kind][e.vi];
+        } else if (e.kind <= 3) {
+            const int sp = e.kind - 2, off = sp == 0 ? n : 0;
+            f0 = off + H->occ[sp][e.oi], f1 = off + H->occ[sp][e.oj];
+            f2 = off + H->vir[sp][e.vi], f3 = off + H->vir[sp][e.vj];
+        } else {
+            f0 = n + H->occ[0][e.oi], f1 = n + H->vir[0][e.vi];
+            f2 = H->occ[1][e.oj], f3 = H->vir[1][e.vj];
+        }
+        out.key[0][pos] = z & s.kc.hash_mask;
+        out.key[1][pos] = ((uint64_t)det << 32) | (f0 | (f1 << 8) | (f2 << 16) | (f3 << 24));
+        return;
+    }
     if (!s.kc.on) {
         store_keys<W>(out, pos, key);
         return;
@@ -456,7 +476,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        store_rec_key<W>(g, s, L, e, key, out, base + k);
+        store_rec_key<W>(g, s, L, e, key, z, det, out, base + k);
         store_pay<PM>(g, s, L, e, c, out, base + k);
     }
 }
@@ -552,7 +572,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
         if (keep) {
             uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
             if (p < cap) {
-                store_rec_key<W>(g, s, L, e, key, out, (int64_t)p);
+                store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
                 store_pay<PM>(g, s, L, e, c, out, (int64_t)p);
             } else {
                 atomicOr(&flags->err, ERR_OVERFLOW);
@@ -782,7 +802,8 @@ __device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, int kind, in
 template <int W, int PM>
 __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayout &L, bool have, const Exc &e,
                                  bool filter, int log2p, uint32_t part, double cutoff, uint64_t &pos,
-                                 uint64_t end, const Planes &out, Flags *flags, uint32_t *wtot, bool &bad)
+                                 uint64_t end, const Planes &out, Flags *flags, uint32_t *wtot, bool &bad,
+                                 int64_t det)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -808,7 +829,7 @@ __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayo
     if (keep) {
         const uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
         if (p < end) {
-            store_rec_key<W>(g, s, L, e, key, out, (int64_t)p);
+            store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
             store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
         } else {
             atomicOr(&flags->err, ERR_OVERFLOW);
@@ -842,7 +863,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
         const bool have = k < L.o2;
         if (have)
             e = decode(g, L, D, k);
-        emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad);
+        emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
     }
     // doubles: alpha-alpha, beta-beta, alpha-beta
     for (int kind = 2; kind <= 4; kind++) {
@@ -876,7 +897,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
                 const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
                 e = make_exc(g, L, kind, lo, q);
             }
-            emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad);
+            emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
         }
         __syncthreads();
     }

@@ -51,6 +51,8 @@ struct Flags {
 // exactly as the determinant bitstring (alpha is the high part of both) in
 // fewer bits: 60 instead of 80 for (10a,10b) in 40 orbitals.
 struct KeyCodec {
+    int hash;               // 1: records carry (Zobrist hash, parent and flips) instead (see below)
+    uint64_t hash_mask;     // bits of the hash stored (all 64, fewer only to test collisions)
     int on;                 // 1: records carry rank keys
     int kw;                 // key words of a record (1 or 2)
     int ktop;               // bytes of the records' top key plane
@@ -59,6 +61,13 @@ struct KeyCodec {
     int stride;             // row length of the binomial table
     const uint64_t *binom;  // C(x, j) at [x * stride + j], 0 <= x <= norb, 0 <= j < stride (device)
 };
+
+// Hash records.  A record holds the 64-bit Zobrist hash of its determinant
+// (the sort key), an auxiliary word (parent index << 32 | four flipped
+// spin-orbitals, one byte each, 0xFF unused) and the payload.  The sort takes
+// 8 digit passes whatever norb is; the single pass rebuilds the bitstring from
+// the parent and resolves the rare determinants whose hashes collide.
+constexpr uint32_t FLIP_NONE = 0xFFu;
 
 // Device view of the Hamiltonian (all pointers are device memory).
 struct DevSys {
@@ -335,6 +344,14 @@ hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, doub
                             Partial *out, hipStream_t st);
 // Rank keys of sorted bitstring references (planes of kw words + coefficients).
 hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
+// Hash records: the references' hashes with their indices (planes: 1 key word
+// with 8-byte top, u64 payload), sorted afterwards by hash; per-reference
+// energies Hp and g vectors G (nref x 2 norb); the single pass.
+hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
+hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st);
+hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
+                              const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
+                              int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
 // Inspection: unique keys and numerators (n_out on device).

@@ -750,6 +750,427 @@ __global__ __launch_bounds__(256) void k_ref_terms(DevSys s, Planes refs, int64_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Hash records (KeyCodec::hash): the records are sorted by the 64-bit Zobrist
+// hash of their determinant, so equal determinants are adjacent, but
+// neighbouring determinants are unrelated.  H_aa is therefore taken relative
+// to each record's parent (the anchored form with the parent as anchor,
+// which is the fast diagonal of the Appendix), and the bitstring is rebuilt
+// from the parent and the four flipped spin-orbitals.
+
+// Zobrist hash of every (bitstring-sorted) reference, with its index.
+template <int WB>
+__global__ void k_refs_hash(DevSys s, Planes bits, int64_t n, Planes out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = 0;
+#pragma unroll
+        for (int w = 0; w < WB; w++) {
+            uint64_t m = pl_get<WB>(bits, w, i);
+            while (m) {
+                z ^= s.R[w * 64 + __builtin_ctzll(m)];
+                m &= m - 1;
+            }
+        }
+        out.key[0][i] = z & s.kc.hash_mask;
+        ((uint64_t *)out.pay)[i] = (uint64_t)i;
+    }
+}
+
+// Per reference p: its energy Hp[p] and g[p][x] = h_x + sum_{c in p, c != x} T[x][c]
+// for every spin-orbital x (one workgroup per reference, one thread per x).
+template <int WB>
+__global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t n, double *Hp, double *G)
+{
+    __shared__ uint64_t s_k[WB];
+    __shared__ double s_row[256 / 64];
+    const int nso = 2 * s.norb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
+        if (tid < WB)
+            s_k[tid] = pl_get<WB>(bits, tid, p);
+        __syncthreads();
+        double rowx = 0.0;
+        if (tid < nso) {
+            const int bx = tid;
+            const bool occ = (s_k[bx >> 6] >> (bx & 63)) & 1ull;
+            const double hx = s.T[tri_row(bx, nso) + bx];
+            double gx = hx;
+            rowx = occ ? hx : 0.0;
+#pragma unroll
+            for (int w = 0; w < WB; w++) {
+                uint64_t m = s_k[w];
+                while (m) {
+                    const int c = w * 64 + __builtin_ctzll(m);
+                    m &= m - 1;
+                    if (c == bx)
+                        continue;
+                    const double t = tri_at(s.T, nso, bx, c);
+                    gx += t;
+                    if (occ && c > bx)
+                        rowx += t;
+                }
+            }
+            G[p * nso + bx] = gx;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            rowx += __shfl_down(rowx, o);
+        if (lane == 0)
+            s_row[wave] = rowx;
+        __syncthreads();
+        if (tid == 0) {
+            double e = 0.0;
+            for (int w = 0; w < 256 / 64; w++)
+                e += s_row[w];
+            Hp[p] = e;
+        }
+        __syncthreads();
+    }
+}
+
+// Bitstring of a hash record: its parent's bitstring with the flips applied.
+template <int WB>
+__device__ inline void hash_key(const Planes &bits, uint64_t aux, uint64_t (&k)[WB])
+{
+    const int64_t p = (int64_t)(aux >> 32);
+#pragma unroll
+    for (int w = 0; w < WB; w++)
+        k[w] = pl_get<WB>(bits, w, p);
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const uint32_t b = (uint32_t)(aux >> (8 * f)) & 0xFFu;
+        if (b != FLIP_NONE) {
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                k[w] ^= (w == (int)(b >> 6)) ? (1ull << (b & 63)) : 0ull;
+        }
+    }
+}
+
+// H_aa relative to the parent p (at most two spin-orbitals removed and two
+// added): Hp - sum_R g_r + sum_A g_a + sum_{r<r'} T + sum_{a<a'} T - sum_{a,r} T.
+template <int WB>
+__device__ inline double diag_parent(const double *Tp, int nso, const uint64_t (&k)[WB], const Planes &bits,
+                                     int64_t p, const double *G, double hp)
+{
+    int rm[2], ad[2], nr = 0, na = 0;
+#pragma unroll
+    for (int w = 0; w < WB; w++) {
+        const uint64_t pw = pl_get<WB>(bits, w, p);
+        uint64_t d = k[w] ^ pw;
+        while (d) {
+            const int b = w * 64 + __builtin_ctzll(d);
+            d &= d - 1;
+            if ((pw >> (b & 63)) & 1ull) {
+                if (nr < 2)
+                    rm[nr] = b;
+                nr++;
+            } else {
+                if (na < 2)
+                    ad[na] = b;
+                na++;
+            }
+        }
+    }
+    const double *g = G + p * nso;
+    double e = hp;
+    for (int i = 0; i < nr && i < 2; i++)
+        e -= g[rm[i]];
+    for (int i = 0; i < na && i < 2; i++)
+        e += g[ad[i]];
+    if (nr == 2)
+        e += tri_at(Tp, nso, rm[0], rm[1]);
+    if (na == 2)
+        e += tri_at(Tp, nso, ad[0], ad[1]);
+    for (int i = 0; i < nr && i < 2; i++)
+        for (int j = 0; j < na && j < 2; j++)
+            e -= tri_at(Tp, nso, ad[j], rm[i]);
+    return e;
+}
+
+constexpr int HR_REFS = 256;  // reference hashes staged per workgroup
+
+// One distinct determinant of a hash segment: exclusion, then the term.
+template <int WB>
+__device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const Planes &rh, int64_t lo, int64_t hi,
+                                     const uint64_t *s_rh, const int64_t *s_ri, bool staged, uint64_t h,
+                                     const uint64_t (&k)[WB], int64_t parent, double num, const double *Hp,
+                                     const double *G, double e0, Acc &a, bool search)
+{
+    a.n_unique++;
+    if (!search)
+        lo = hi = 0;  // subtraction form: references stay in
+    // references with hash h: a few at most
+    int64_t j0 = lo, j1 = hi;
+    {
+        int64_t l = lo, r = hi;  // first index with hash >= h
+        while (l < r) {
+            const int64_t m = l + (r - l) / 2;
+            const uint64_t hm = staged ? s_rh[m - lo] : rh.key[0][m];
+            if (hm < h)
+                l = m + 1;
+            else
+                r = m;
+        }
+        j0 = l;
+        j1 = hi;
+    }
+    for (int64_t j = j0; j < j1; j++) {
+        const uint64_t hj = staged ? s_rh[j - lo] : rh.key[0][j];
+        if (hj != h)
+            break;
+        const int64_t idx = staged ? s_ri[j - lo] : (int64_t)((const uint64_t *)rh.pay)[j];
+        bool eq = true;
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            eq = eq && pl_get<WB>(bits, w, idx) == k[w];
+        if (eq) {
+            a.n_hit++;
+            a.ref_cross += ((const double *)bits.pay)[idx] * num;
+            return;
+        }
+    }
+    const double haa = diag_parent<WB>(s.T, 2 * s.norb, k, bits, parent, G, Hp[parent]);
+    const double den = e0 - haa;
+    a.n_ext++;
+    const double ad = fabs(den);
+    a.min_abs = ad < a.min_abs ? ad : a.min_abs;
+    if (den >= 0.0)
+        a.n_nonneg++;
+    if (den == 0.0)
+        a.singular = 1;
+    else
+        neumaier(a.e_sum, a.e_comp, num * num / den);
+    const uint64_t m = key_mix<WB>(k);
+    a.kx ^= m;
+    a.ks += m;
+}
+
+// Partial sums of one workgroup, combined in a fixed order.
+__device__ inline void partial_merge(Partial &x, const Partial &y)
+{
+    double sum = x.e_sum, comp = x.e_comp + y.e_comp;
+    neumaier(sum, comp, y.e_sum);
+    x.e_sum = sum, x.e_comp = comp;
+    x.ref_cross += y.ref_cross;
+    x.min_abs_denom = y.min_abs_denom < x.min_abs_denom ? y.min_abs_denom : x.min_abs_denom;
+    x.n_unique += y.n_unique, x.n_external += y.n_external, x.n_hit += y.n_hit;
+    x.n_nonneg += y.n_nonneg, x.key_xor ^= y.key_xor, x.key_sum += y.key_sum;
+}
+
+__device__ inline Partial acc_partial(const Acc &a)
+{
+    Partial me;
+    me.e_sum = a.e_sum, me.e_comp = a.e_comp, me.ref_cross = a.ref_cross, me.min_abs_denom = a.min_abs;
+    me.n_unique = a.n_unique, me.n_external = a.n_ext, me.n_hit = a.n_hit, me.n_nonneg = a.n_nonneg;
+    me.key_xor = a.kx, me.key_sum = a.ks;
+    return me;
+}
+
+// Tree sum of the workgroup's per-thread partials (s_p holds RED_THREADS).
+__device__ inline void block_partial(Partial *s_p)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+    for (int o = RED_THREADS / 2; o >= 1; o >>= 1) {
+        if (tid < o) {
+            Partial x = s_p[tid];
+            partial_merge(x, s_p[tid + o]);
+            s_p[tid] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// Single pass over hash records.  Each workgroup owns the segments (runs of
+// equal hash) whose first record lies in its contiguous range; a thread owns
+// the segments starting in its records and walks each one.  A segment whose
+// records rebuild to more than one determinant (a hash collision: with a
+// 64-bit hash, a handful in 1e10 determinants) is left to k_reduce_hash_coll,
+// and the workgroup marks itself in coll[].
+template <int WB, int PB>
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits, Planes rh,
+                                                             int64_t nref, const double *Hp, const double *G,
+                                                             double e0, int64_t per_block, int search,
+                                                             Partial *partials, uint32_t *coll, Flags *flags)
+{
+    __shared__ uint64_t s_rh[HR_REFS];
+    __shared__ int64_t s_ri[HR_REFS];
+    __shared__ int64_t s_lo, s_hi;
+    __shared__ uint32_t s_coll;
+    __shared__ Partial s_p[RED_THREADS];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    Acc a;
+    acc_init(a);
+    if (tid == 0)
+        s_coll = 0;
+    if (b0 < b1) {
+        if (tid == 0) {
+            // references whose hash lies between the first and last record's
+            int64_t l = 0, r = nref;
+            const uint64_t h0 = in.key[0][b0], h1 = in.key[0][b1 - 1];
+            while (l < r) {
+                const int64_t m = l + (r - l) / 2;
+                if (rh.key[0][m] < h0)
+                    l = m + 1;
+                else
+                    r = m;
+            }
+            s_lo = l;
+            r = nref;
+            while (l < r) {
+                const int64_t m = l + (r - l) / 2;
+                if (rh.key[0][m] <= h1)
+                    l = m + 1;
+                else
+                    r = m;
+            }
+            s_hi = l;
+        }
+        __syncthreads();
+        const int64_t lo = s_lo, hi = s_hi;
+        const bool staged = hi - lo <= HR_REFS;
+        if (staged)
+            for (int64_t j = tid; j < hi - lo; j += RED_THREADS) {
+                s_rh[j] = rh.key[0][lo + j];
+                s_ri[j] = (int64_t)((const uint64_t *)rh.pay)[lo + j];
+            }
+        __syncthreads();
+        for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
+            const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
+            uint64_t hprev = i0 > 0 && i0 < b1 ? in.key[0][i0 - 1] : 0;
+            for (int j = 0; j < RED_ITEMS; j++) {
+                const int64_t i = i0 + j;
+                if (i >= b1)
+                    break;
+                const uint64_t h = in.key[0][i];
+                const bool head = i == 0 || h != hprev;
+                hprev = h;
+                if (!head)
+                    continue;
+                // walk the segment: sum, and check that every record rebuilds
+                // to the first record's determinant
+                const uint64_t aux0 = in.key[1][i];
+                uint64_t k0[WB];
+                hash_key<WB>(bits, aux0, k0);
+                double num = 0.0;
+                bool collided = false;
+                for (int64_t e = i; e < n && in.key[0][e] == h; e++) {
+                    num += load_pay<PB>(in, e);
+                    if (e > i) {
+                        uint64_t kk[WB];
+                        hash_key<WB>(bits, in.key[1][e], kk);
+                        bool same = true;
+#pragma unroll
+                        for (int w = 0; w < WB; w++)
+                            same = same && kk[w] == k0[w];
+                        collided = collided || !same;
+                    }
+                }
+                if (collided)
+                    s_coll = 1;
+                else
+                    hash_key_term<WB>(s, bits, rh, lo, hi, s_rh, s_ri, staged, h, k0, (int64_t)(aux0 >> 32), num,
+                                      Hp, G, e0, a, search != 0);
+            }
+        }
+    }
+    s_p[tid] = acc_partial(a);
+    if (a.singular)
+        atomicOr(&flags->err, ERR_SINGULAR);
+    block_partial(s_p);
+    if (tid == 0) {
+        partials[blockIdx.x] = s_p[0];
+        coll[blockIdx.x] = s_coll;
+    }
+}
+
+// The collided segments of the workgroups k_reduce_hash marked (same record
+// ranges): each distinct determinant of such a segment, taken at its first
+// record, gets the sum of its records' payloads; the workgroup's partial is
+// merged into the one k_reduce_hash wrote.  Unmarked workgroups return at once.
+template <int WB, int PB>
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
+                                                                  Planes rh, int64_t nref, const double *Hp,
+                                                                  const double *G, double e0, int64_t per_block,
+                                                                  int search, Partial *partials,
+                                                                  const uint32_t *coll, Flags *flags)
+{
+    __shared__ Partial s_p[RED_THREADS];
+    if (coll[blockIdx.x] == 0)
+        return;
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    Acc a;
+    acc_init(a);
+    for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
+        const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t i = i0 + j;
+            if (i >= b1)
+                break;
+            const uint64_t h = in.key[0][i];
+            if (i > 0 && in.key[0][i - 1] == h)
+                continue;  // not a segment head
+            int64_t e = i;
+            while (e < n && in.key[0][e] == h)
+                e++;
+            uint64_t k0[WB];
+            hash_key<WB>(bits, in.key[1][i], k0);
+            bool collided = false;
+            for (int64_t y = i + 1; y < e && !collided; y++) {
+                uint64_t ky[WB];
+                hash_key<WB>(bits, in.key[1][y], ky);
+                for (int w = 0; w < WB; w++)
+                    collided = collided || ky[w] != k0[w];
+            }
+            if (!collided)
+                continue;  // k_reduce_hash took it
+            for (int64_t x = i; x < e; x++) {
+                uint64_t kx[WB];
+                const uint64_t ax = in.key[1][x];
+                hash_key<WB>(bits, ax, kx);
+                bool seen = false;
+                for (int64_t y = i; y < x && !seen; y++) {
+                    uint64_t ky[WB];
+                    hash_key<WB>(bits, in.key[1][y], ky);
+                    bool same = true;
+                    for (int w = 0; w < WB; w++)
+                        same = same && ky[w] == kx[w];
+                    seen = same;
+                }
+                if (seen)
+                    continue;
+                double nx = 0.0;
+                for (int64_t y = x; y < e; y++) {
+                    uint64_t ky[WB];
+                    hash_key<WB>(bits, in.key[1][y], ky);
+                    bool same = true;
+                    for (int w = 0; w < WB; w++)
+                        same = same && ky[w] == kx[w];
+                    if (same)
+                        nx += load_pay<PB>(in, y);
+                }
+                // references searched in global memory over the whole list
+                hash_key_term<WB>(s, bits, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), nx,
+                                  Hp, G, e0, a, search != 0);
+            }
+        }
+    }
+    s_p[tid] = acc_partial(a);
+    if (a.singular)
+        atomicOr(&flags->err, ERR_SINGULAR);
+    block_partial(s_p);
+    if (tid == 0) {
+        Partial x = partials[blockIdx.x];
+        partial_merge(x, s_p[0]);
+        partials[blockIdx.x] = x;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_final(const Partial *partials, int np, Partial *out)
 {
     __shared__ Partial s_p[256];
@@ -914,6 +1335,67 @@ hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, doub
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partials, 256, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t gg = (n + 255) / 256;
+    dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_refs_hash<1>), g, b, 0, st, s, bits, n, out); break;
+    case 2: hipLaunchKernelGGL((k_refs_hash<2>), g, b, 0, st, s, bits, n, out); break;
+    case 3: hipLaunchKernelGGL((k_refs_hash<3>), g, b, 0, st, s, bits, n, out); break;
+    case 4: hipLaunchKernelGGL((k_refs_hash<4>), g, b, 0, st, s, bits, n, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    if (2 * s.norb > 256)
+        return hipErrorInvalidValue;
+    dim3 g((unsigned)(n < 65536 ? n : 65536)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_parent_g<1>), g, b, 0, st, s, bits, n, Hp, G); break;
+    case 2: hipLaunchKernelGGL((k_parent_g<2>), g, b, 0, st, s, bits, n, Hp, G); break;
+    case 3: hipLaunchKernelGGL((k_parent_g<3>), g, b, 0, st, s, bits, n, Hp, G); break;
+    case 4: hipLaunchKernelGGL((k_parent_g<4>), g, b, 0, st, s, bits, n, Hp, G); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
+                              const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
+                              int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st)
+{
+    const int64_t per = (n + RED_GRID - 1) / RED_GRID;
+    dim3 g(RED_GRID), b(RED_THREADS);
+#define RH(WB, PB)                                                                                                 \
+    do {                                                                                                           \
+        hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, rh, nref, Hp, G, e0, per,     \
+                           search, partials, coll, flags);                                                         \
+        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, rh, nref, Hp, G, e0, per, \
+                           search, partials, coll, flags);                                                         \
+    } while (0)
+    switch (s.W * 2 + (fp32 ? 0 : 1)) {
+    case 2: RH(1, 4); break;
+    case 3: RH(1, 8); break;
+    case 4: RH(2, 4); break;
+    case 5: RH(2, 8); break;
+    case 6: RH(3, 4); break;
+    case 7: RH(3, 8); break;
+    case 8: RH(4, 4); break;
+    case 9: RH(4, 8); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef RH
     return hipGetLastError();
 }
 

@@ -201,8 +201,9 @@ def test_c1_subtraction_exclusion(pt2, c1):
     """C1's coefficients are an eigenvector of H in the reference space, so
     keeping the reference determinants and subtracting sum_i c_i^2 (E0 - H_ii)
     gives the same energy as excluding them by search."""
-    for log2p in (-1, 3):
-        ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, exclusion="subtract", log2_partitions=log2p)
+    for log2p, mode in ((-1, 0), (3, 0), (-1, 2), (2, 2)):
+        ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, exclusion="subtract", log2_partitions=log2p,
+                          compress_keys=mode)
         got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
         ctx.close()
         ref = c1["ref"]
@@ -305,6 +306,48 @@ def test_rank_keys_give_identical_results(pt2, norb, na, nb, nref, log2p, prec):
         assert_matches(res[1], ref)
     else:  # FP32 terms: sum_i c_i N_i carries their rounding too
         assert_matches(res[1], ref, tol=1e-6, cross_tol=1e-7)
+
+
+@pytest.mark.parametrize("norb,na,nb,nref,log2p,prec,hash_bits", [
+    (12, 4, 4, 40, -1, "fp64", 0), (12, 4, 4, 40, -1, "fp64", 10), (20, 6, 3, 60, 3, "fp64", 0),
+    (20, 6, 3, 60, 2, "fp64", 12), (33, 3, 2, 25, -1, "fp32", 0), (40, 10, 10, 30, -1, "fp64", 16),
+    (64, 3, 3, 10, 1, "fp64", 0), (76, 5, 5, 12, 2, "fp64", 0), (100, 4, 3, 8, -1, "fp64", 14),
+    (127, 3, 3, 6, -1, "fp64", 0), (10, 0, 3, 20, -1, "fp64", 8)])
+def test_hash_records_match(pt2, norb, na, nb, nref, log2p, prec, hash_bits):
+    """Records keyed by the Zobrist hash (parent and flips carried along)
+    give the bitstring-keyed counts and checksums exactly and the energy to
+    rounding; truncated hashes force many collisions, which the single pass
+    must separate exactly (every key set and count unchanged)."""
+    h, eri, _ = synth.make_integrals(norb, 6, 9000 + norb)
+    nref = min(nref, math.comb(norb, na) * math.comb(norb, nb))
+    dets = synth.random_determinants(norb, na, nb, nref, norb + 2)
+    c = np.random.default_rng(norb + 1).normal(size=nref)
+    c /= np.linalg.norm(c)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    keys, _ = O.numerators(dets, c)
+    e0 = float(np.concatenate([O.diag(keys), O.diag(dets)]).min()) - 1.0
+    res = {}
+    for mode in (0, 2):
+        ctx = pt2.Context(h, eri, norb, na, nb, log2_partitions=log2p, precision=prec, compress_keys=mode,
+                          hash_bits=hash_bits)
+        res[mode] = ctx.evaluate(dets, c, e0)
+        if mode == 2:  # collisions resolved the same way every time: bit-identical repeats
+            again = ctx.evaluate(dets, c, e0)
+            assert again["e_pt2"] == res[2]["e_pt2"] and again["ref_cross"] == res[2]["ref_cross"]
+        ctx.close()
+    print("key bits", res[0]["key_bits"], "->", res[2]["key_bits"], "passes", res[0]["n_sort_passes"], "->",
+          res[2]["n_sort_passes"], flush=True)
+    assert res[2]["key_bits"] == 64
+    for k in ("n_contrib", "n_after_cutoff", "n_unique", "n_external", "n_in_ref_hit", "n_nonneg_denom",
+              "key_xor", "key_sum"):
+        assert res[0][k] == res[2][k], (k, res[0][k], res[2][k])
+    assert res[2]["e_pt2"] == pytest.approx(res[0]["e_pt2"], rel=1e-12, abs=1e-12)
+    assert res[2]["ref_cross"] == pytest.approx(res[0]["ref_cross"], rel=1e-12, abs=1e-14)
+    ref, _ = O.pt2(dets, c, e0)
+    if prec == "fp64":
+        assert_matches(res[2], ref)
+    else:
+        assert_matches(res[2], ref, tol=1e-6, cross_tol=1e-7)
 
 
 def test_workspace_reuse_with_smaller_reference(pt2):
