@@ -982,35 +982,86 @@ __device__ inline void block_partial(Partial *s_p)
     }
 }
 
-// Single pass over hash records.  Each workgroup owns the segments (runs of
-// equal hash) whose first record lies in its contiguous range; a thread owns
-// the segments starting in its records and walks each one.  A segment whose
-// records rebuild to more than one determinant (a hash collision: with a
-// 64-bit hash, a handful in 1e10 determinants) is left to k_reduce_hash_coll,
-// and the workgroup marks itself in coll[].
+// Single pass over hash records.  A fixed grid of workgroups takes
+// contiguous ranges of RED_TILE-record tiles; a tile owns the segments (runs
+// of equal hash) whose first record lies in it.  Every thread loads its
+// RED_ITEMS records and rebuilds their bitstrings at once (the parent reads
+// are independent), marks segment heads and tails and the records whose
+// bitstring differs from the previous record of their segment, and a
+// segmented scan over the tile carries each segment's sum, its first record's
+// parent word and whether it holds more than one determinant.  The owned
+// segment ends are queued in LDS and processed by all threads.  A segment
+// that runs past the tile end is followed by wave 0.  Segments holding more
+// than one determinant (a hash collision) are left to k_reduce_hash_coll and
+// the workgroup marks itself in coll[].
+struct HashScan {
+    int f;       // a segment head was seen
+    double v;    // sum since the last head
+    uint64_t a;  // parent word of the last head
+    int c;       // the segment since the last head holds two determinants
+};
+
+__device__ inline HashScan hscan_op(const HashScan &x, const HashScan &y)
+{
+    HashScan r;
+    r.f = x.f | y.f;
+    r.v = y.f ? y.v : x.v + y.v;
+    r.a = y.f ? y.a : x.a;
+    r.c = y.f ? y.c : (x.c | y.c);
+    return r;
+}
+
+template <int WB>
+__device__ inline bool bits_eq(const uint64_t (&x)[WB], const uint64_t (&y)[WB])
+{
+    bool e = true;
+#pragma unroll
+    for (int w = 0; w < WB; w++)
+        e = e && x[w] == y[w];
+    return e;
+}
+
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits, Planes rh,
                                                              int64_t nref, const double *Hp, const double *G,
-                                                             double e0, int64_t per_block, int search,
+                                                             double e0, int64_t tiles_per_block, int search,
                                                              Partial *partials, uint32_t *coll, Flags *flags)
 {
+    // queue of owned segment ends (hash, parent word, sum, collided); the
+    // block's partials reuse it at the end
+    constexpr size_t QB = (size_t)RED_Q * (8 + 8 + 8 + 4);
+    constexpr size_t LB = QB > sizeof(Partial) * RED_THREADS ? QB : sizeof(Partial) * RED_THREADS;
+    __shared__ __align__(16) char s_q[LB];
+    uint64_t *q_h = (uint64_t *)s_q;
+    uint64_t *q_a = q_h + RED_Q;
+    double *q_v = (double *)(q_a + RED_Q);
+    int *q_c = (int *)(q_v + RED_Q);
     __shared__ uint64_t s_rh[HR_REFS];
     __shared__ int64_t s_ri[HR_REFS];
     __shared__ int64_t s_lo, s_hi;
+    __shared__ HashScan s_w[RED_THREADS / 64];
+    __shared__ uint32_t s_cnt[RED_THREADS / 64];
+    __shared__ HashScan s_cont;
+    __shared__ uint64_t s_ch;
+    __shared__ int s_cflag;
     __shared__ uint32_t s_coll;
-    __shared__ Partial s_p[RED_THREADS];
-    const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * per_block;
-    const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
     Acc a;
     acc_init(a);
     if (tid == 0)
         s_coll = 0;
-    if (b0 < b1) {
+    // references whose hash lies in the workgroup's hash range, staged in LDS
+    // when few
+    int64_t lo = 0, hi = 0;
+    bool staged = false;
+    if (t_begin < t_end) {
         if (tid == 0) {
-            // references whose hash lies between the first and last record's
-            int64_t l = 0, r = nref;
+            const int64_t b0 = t_begin * RED_TILE, b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
             const uint64_t h0 = in.key[0][b0], h1 = in.key[0][b1 - 1];
+            int64_t l = 0, r = nref;
             while (l < r) {
                 const int64_t m = l + (r - l) / 2;
                 if (rh.key[0][m] < h0)
@@ -1030,53 +1081,222 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
             s_hi = l;
         }
         __syncthreads();
-        const int64_t lo = s_lo, hi = s_hi;
-        const bool staged = hi - lo <= HR_REFS;
+        lo = s_lo, hi = s_hi;
+        staged = hi - lo <= HR_REFS;
         if (staged)
             for (int64_t j = tid; j < hi - lo; j += RED_THREADS) {
                 s_rh[j] = rh.key[0][lo + j];
                 s_ri[j] = (int64_t)((const uint64_t *)rh.pay)[lo + j];
             }
-        __syncthreads();
-        for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
-            const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
-            uint64_t hprev = i0 > 0 && i0 < b1 ? in.key[0][i0 - 1] : 0;
-            for (int j = 0; j < RED_ITEMS; j++) {
-                const int64_t i = i0 + j;
-                if (i >= b1)
-                    break;
-                const uint64_t h = in.key[0][i];
-                const bool head = i == 0 || h != hprev;
-                hprev = h;
-                if (!head)
-                    continue;
-                // walk the segment: sum, and check that every record rebuilds
-                // to the first record's determinant
-                const uint64_t aux0 = in.key[1][i];
-                uint64_t k0[WB];
-                hash_key<WB>(bits, aux0, k0);
-                double num = 0.0;
-                bool collided = false;
-                for (int64_t e = i; e < n && in.key[0][e] == h; e++) {
-                    num += load_pay<PB>(in, e);
-                    if (e > i) {
-                        uint64_t kk[WB];
-                        hash_key<WB>(bits, in.key[1][e], kk);
-                        bool same = true;
+    }
+    for (int64_t tile = t_begin; tile < t_end; tile++) {
+        const int64_t base = tile * RED_TILE;
+        const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
+        if (tid == 0)
+            s_cflag = 0;
+        const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
+        uint64_t h[RED_ITEMS], ax[RED_ITEMS], kb[RED_ITEMS][WB];
+        double p[RED_ITEMS];
 #pragma unroll
-                        for (int w = 0; w < WB; w++)
-                            same = same && kk[w] == k0[w];
-                        collided = collided || !same;
-                    }
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            const bool valid = idx < tend;
+            h[j] = valid ? in.key[0][idx] : 0ull;
+            ax[j] = valid ? in.key[1][idx] : 0ull;
+            p[j] = valid ? load_pay<PB>(in, idx) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            if (r0 + j < tend)
+                hash_key<WB>(bits, ax[j], kb[j]);
+            else
+#pragma unroll
+                for (int w = 0; w < WB; w++)
+                    kb[j][w] = 0;
+        }
+        // the previous record (the last of the previous lane, or loaded) and
+        // the next record's hash
+        uint64_t hprev = 0, kprev[WB];
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            kprev[w] = __shfl_up(kb[RED_ITEMS - 1][w], 1);
+        hprev = __shfl_up(h[RED_ITEMS - 1], 1);
+        const bool has_prev = r0 > 0 && r0 < tend;
+        if (lane == 0 && has_prev) {
+            hprev = in.key[0][r0 - 1];
+            if (r0 > base)
+                hash_key<WB>(bits, in.key[1][r0 - 1], kprev);
+        }
+        const uint64_t hnext = r0 + RED_ITEMS < n ? in.key[0][r0 + RED_ITEMS] : 0ull;
+        const bool has_next = r0 + RED_ITEMS < n;
+
+        double run[RED_ITEMS];
+        uint64_t ra[RED_ITEMS];
+        int rc[RED_ITEMS];
+        bool hh[RED_ITEMS], tl[RED_ITEMS];
+        HashScan me;
+        me.f = 0, me.v = 0.0, me.a = 0, me.c = 0;
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            const bool valid = idx < tend;
+            bool head, differs;
+            if (j == 0) {
+                head = idx == 0 || !has_prev || h[0] != hprev;
+                differs = !head && r0 > base && !bits_eq<WB>(kb[0], kprev);
+            } else {
+                head = h[j] != h[j - 1];
+                differs = !head && !bits_eq<WB>(kb[j], kb[j - 1]);
+            }
+            head = head && valid;
+            bool tail;
+            if (j == RED_ITEMS - 1)
+                tail = !has_next || h[j] != hnext;
+            else
+                tail = idx + 1 >= n || h[j] != h[j + 1];
+            tl[j] = tail && valid;
+            if (valid) {
+                if (head) {
+                    me.f = 1, me.v = p[j], me.a = ax[j], me.c = 0;
+                } else {
+                    me.v += p[j];
+                    me.c |= differs ? 1 : 0;
                 }
-                if (collided)
-                    s_coll = 1;
-                else
-                    hash_key_term<WB>(s, bits, rh, lo, hi, s_rh, s_ri, staged, h, k0, (int64_t)(aux0 >> 32), num,
-                                      Hp, G, e0, a, search != 0);
+            }
+            run[j] = me.v, ra[j] = me.a, rc[j] = me.c;
+            hh[j] = me.f != 0;
+        }
+        // inclusive scan within the wavefront, then the earlier wavefronts
+        HashScan x = me;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            HashScan y;
+            y.f = __shfl_up(x.f, o);
+            y.v = __shfl_up(x.v, o);
+            y.a = __shfl_up(x.a, o);
+            y.c = __shfl_up(x.c, o);
+            if (lane >= o)
+                x = hscan_op(y, x);
+        }
+        if (lane == 63)
+            s_w[wave] = x;
+        HashScan ex;  // exclusive within the wavefront
+        ex.f = __shfl_up(x.f, 1);
+        ex.v = __shfl_up(x.v, 1);
+        ex.a = __shfl_up(x.a, 1);
+        ex.c = __shfl_up(x.c, 1);
+        if (lane == 0)
+            ex.f = 0, ex.v = 0.0, ex.a = 0, ex.c = 0;
+        __syncthreads();
+        HashScan cw;
+        cw.f = 0, cw.v = 0.0, cw.a = 0, cw.c = 0;
+        for (int w = 0; w < wave; w++)
+            cw = hscan_op(cw, s_w[w]);
+        const HashScan carry = hscan_op(cw, ex);
+
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            const bool owned = idx < tend && (hh[j] || carry.f);
+            if (owned && tl[j])
+                mine++;
+            if (owned && !tl[j] && idx == tend - 1) {
+                // the segment continues past the tile end
+                s_ch = h[j];
+                s_cont.f = 1;
+                s_cont.v = hh[j] ? run[j] : carry.v + run[j];
+                s_cont.a = hh[j] ? ra[j] : carry.a;
+                s_cont.c = hh[j] ? rc[j] : (carry.c | rc[j]);
+                s_cflag = 1;
             }
         }
+        uint32_t xs = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(xs, o);
+            if (lane >= o)
+                xs += y;
+        }
+        if (lane == 63)
+            s_cnt[wave] = xs;
+        __syncthreads();
+        uint32_t pre = 0, qtot = 0;
+#pragma unroll
+        for (int w = 0; w < RED_THREADS / 64; w++) {
+            const uint32_t t = s_cnt[w];
+            pre += w < wave ? t : 0u;
+            qtot += t;
+        }
+        uint32_t slot = pre + xs - mine;
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            const bool owned = idx < tend && (hh[j] || carry.f);
+            if (owned && tl[j]) {
+                q_h[slot] = h[j];
+                q_v[slot] = hh[j] ? run[j] : carry.v + run[j];
+                q_a[slot] = hh[j] ? ra[j] : carry.a;
+                q_c[slot] = hh[j] ? rc[j] : (carry.c | rc[j]);
+                slot++;
+            }
+        }
+        const int cflag = s_cflag;
+        if (cflag && tid < 64) {
+            // wave 0 follows the continuing segment into the following records
+            const uint64_t ch = s_ch;
+            uint64_t k0[WB];
+            hash_key<WB>(bits, s_cont.a, k0);
+            double total = 0.0;
+            int col = 0;
+            int64_t pos = tend;
+            while (true) {
+                const int64_t idx = pos + lane;
+                bool eq = false;
+                double v = 0.0;
+                if (idx < n && in.key[0][idx] == ch) {
+                    eq = true;
+                    v = load_pay<PB>(in, idx);
+                    uint64_t kk[WB];
+                    hash_key<WB>(bits, in.key[1][idx], kk);
+                    col |= bits_eq<WB>(kk, k0) ? 0 : 1;
+                }
+                const uint64_t m = __ballot(eq);
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    v += __shfl_down(v, o);
+                    col |= __shfl_down(col, o);
+                }
+                total += v;  // lane 0 holds the sum of this step
+                if (m != ~0ull)
+                    break;
+                pos += 64;
+            }
+            if (lane == 0) {
+                q_h[qtot] = ch;
+                q_v[qtot] = s_cont.v + total;
+                q_a[qtot] = s_cont.a;
+                // the tile part compared neighbours, the continuation compares
+                // with the segment's first record
+                q_c[qtot] = s_cont.c | col;
+            }
+        }
+        __syncthreads();
+        const int qn = (int)qtot + cflag;
+        for (int e = tid; e < qn; e += RED_THREADS) {
+            if (q_c[e]) {
+                s_coll = 1;
+                continue;
+            }
+            uint64_t k0[WB];
+            const uint64_t aux = q_a[e];
+            hash_key<WB>(bits, aux, k0);
+            hash_key_term<WB>(s, bits, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32), q_v[e], Hp,
+                              G, e0, a, search != 0);
+        }
+        __syncthreads();
     }
+    Partial *s_p = (Partial *)s_q;
     s_p[tid] = acc_partial(a);
     if (a.singular)
         atomicOr(&flags->err, ERR_SINGULAR);
@@ -1094,16 +1314,19 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
                                                                   Planes rh, int64_t nref, const double *Hp,
-                                                                  const double *G, double e0, int64_t per_block,
-                                                                  int search, Partial *partials,
+                                                                  const double *G, double e0,
+                                                                  int64_t tiles_per_block, int search, Partial *partials,
                                                                   const uint32_t *coll, Flags *flags)
 {
     __shared__ Partial s_p[RED_THREADS];
     if (coll[blockIdx.x] == 0)
         return;
     const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * per_block;
-    const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
+    const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
+    const int64_t b0 = t_begin * RED_TILE;
+    const int64_t b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
     Acc a;
     acc_init(a);
     for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
@@ -1375,7 +1598,8 @@ hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, i
                               const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
                               int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st)
 {
-    const int64_t per = (n + RED_GRID - 1) / RED_GRID;
+    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+    const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RH(WB, PB)                                                                                                 \
     do {                                                                                                           \
