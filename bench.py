@@ -279,8 +279,8 @@ def main():
                     help="reference determinants in the oracle's timed sample (0: skip)")
     ap.add_argument("--fp32-form", action="store_true",
                     help="also time the FP32-payload form (outside the timed region)")
-    ap.add_argument("--compress-keys", type=int, default=-1, choices=[-1, 0, 1],
-                    help="record keys: -1 library default, 0 bitstrings, 1 combinatorial ranks")
+    ap.add_argument("--compress-keys", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="record keys: -1 library default, 0 bitstrings, 1 combinatorial ranks, 2 hash records")
     ap.add_argument("--groups", type=int, default=0,
                     help="evaluate the --log2p split in this many calls (large workloads)")
     ap.add_argument("--log2p", type=int, default=9)

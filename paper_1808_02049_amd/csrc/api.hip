@@ -167,6 +167,7 @@ struct Workspace {
     Buf tref;                // reference range of every single-pass tile
     Buf refH0, refH1;        // hash records: reference hashes with indices (sort ping-pong)
     Buf hp, gv;              // hash records: energy and g vector of every reference
+    Buf refX;                // hash records: reference bitstrings record by record
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -183,7 +184,7 @@ struct Workspace {
     void release()
     {
         buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB), buf_free(A, refK);
-        buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv);
+        buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv), buf_free(A, refX);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
@@ -719,8 +720,10 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = buf_ensure(ws.A, ws.refH0, planes_bytes(1, J.n, 8, 8))) ||
             (rc = buf_ensure(ws.A, ws.refH1, planes_bytes(1, J.n, 8, 8))) ||
             (rc = buf_ensure(ws.A, ws.hp, (size_t)J.n * 8)) ||
-            (rc = buf_ensure(ws.A, ws.gv, (size_t)J.n * nso * 8)))
+            (rc = buf_ensure(ws.A, ws.gv, (size_t)J.n * nso * 8)) ||
+            (rc = buf_ensure(ws.A, ws.refX, (size_t)J.n * (c->W == 3 ? 4 : c->W) * 8)))
             return rc;
+        HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
         Planes h0 = planes_of(ws.refH0, 1, J.n, 8, 8), h1 = planes_of(ws.refH1, 1, J.n, 8, 8);
         HIPCHK(launch_refs_hash(sys, refs, J.n, h0, st));
         Timing none;
@@ -792,7 +795,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
         if (RL.hash)
-            HIPCHK(launch_reduce_hash(sys, fp32, A, n, refs, refs_hash, J.n, (const double *)ws.hp.p,
+            HIPCHK(launch_reduce_hash(sys, fp32, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n, (const double *)ws.hp.p,
                                       (const double *)ws.gv.p, J.e0, subtract ? 0 : 1, ds->partials, ds->coll,
                                       &ds->flags, st));
         else

@@ -14,6 +14,9 @@ constexpr int PM_FP32_PAYLOAD = 1;  // FP64 arithmetic, payload rounded once to 
 constexpr int PM_FP32_ARITH = 2;    // FP32 integrals, arithmetic and payload
 constexpr int MAXORB = 128;
 constexpr int SORT_THREADS = 256;
+#ifndef PT2_XCD_TILES
+#define PT2_XCD_TILES 1
+#endif
 #ifndef PT2_SORT_ITEMS
 #define PT2_SORT_ITEMS 8
 #endif
@@ -349,8 +352,10 @@ hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, cons
 // energies Hp and g vectors G (nref x 2 norb); the single pass.
 hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
 hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st);
+// The references' bitstrings record by record, 2^ceil(log2 W) words each.
+hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ra, hipStream_t st);
 hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
-                              const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
+                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
                               int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);

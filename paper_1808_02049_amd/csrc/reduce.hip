@@ -828,14 +828,48 @@ __global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t
     }
 }
 
+// The references' bitstrings record by record (stride ref_stride<WB>() words,
+// a power of two), so that rebuilding a record from its parent reads one
+// cache line instead of one per key plane.
+template <int WB>
+__host__ __device__ constexpr int ref_stride()
+{
+    return WB == 3 ? 4 : WB;
+}
+
+template <int WB>
+__global__ void k_refs_aos(Planes bits, int64_t n, uint64_t *ra)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int w = 0; w < ref_stride<WB>(); w++)
+            ra[i * ref_stride<WB>() + w] = w < WB ? pl_get<WB>(bits, w, i) : 0ull;
+}
+
+template <int WB>
+__device__ inline void ref_bits(const uint64_t *ra, int64_t p, uint64_t (&k)[WB])
+{
+    const uint64_t *r = ra + p * ref_stride<WB>();
+    if constexpr (WB == 2 || WB == 4) {
+        const ulonglong2 *r2 = (const ulonglong2 *)r;
+#pragma unroll
+        for (int w = 0; w < WB; w += 2) {
+            const ulonglong2 v = r2[w / 2];
+            k[w] = v.x, k[w + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            k[w] = r[w];
+    }
+}
+
 // Bitstring of a hash record: its parent's bitstring with the flips applied.
 template <int WB>
-__device__ inline void hash_key(const Planes &bits, uint64_t aux, uint64_t (&k)[WB])
+__device__ inline void hash_key(const uint64_t *ra, uint64_t aux, uint64_t (&k)[WB])
 {
     const int64_t p = (int64_t)(aux >> 32);
-#pragma unroll
-    for (int w = 0; w < WB; w++)
-        k[w] = pl_get<WB>(bits, w, p);
+    ref_bits<WB>(ra, p, k);
 #pragma unroll
     for (int f = 0; f < 4; f++) {
         const uint32_t b = (uint32_t)(aux >> (8 * f)) & 0xFFu;
@@ -850,13 +884,15 @@ __device__ inline void hash_key(const Planes &bits, uint64_t aux, uint64_t (&k)[
 // H_aa relative to the parent p (at most two spin-orbitals removed and two
 // added): Hp - sum_R g_r + sum_A g_a + sum_{r<r'} T + sum_{a<a'} T - sum_{a,r} T.
 template <int WB>
-__device__ inline double diag_parent(const double *Tp, int nso, const uint64_t (&k)[WB], const Planes &bits,
+__device__ inline double diag_parent(const double *Tp, int nso, const uint64_t (&k)[WB], const uint64_t *ra,
                                      int64_t p, const double *G, double hp)
 {
     int rm[2], ad[2], nr = 0, na = 0;
+    uint64_t pk[WB];
+    ref_bits<WB>(ra, p, pk);
 #pragma unroll
     for (int w = 0; w < WB; w++) {
-        const uint64_t pw = pl_get<WB>(bits, w, p);
+        const uint64_t pw = pk[w];
         uint64_t d = k[w] ^ pw;
         while (d) {
             const int b = w * 64 + __builtin_ctzll(d);
@@ -892,7 +928,8 @@ constexpr int HR_REFS = 256;  // reference hashes staged per workgroup
 
 // One distinct determinant of a hash segment: exclusion, then the term.
 template <int WB>
-__device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const Planes &rh, int64_t lo, int64_t hi,
+__device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const uint64_t *ra, const Planes &rh,
+                                     int64_t lo, int64_t hi,
                                      const uint64_t *s_rh, const int64_t *s_ri, bool staged, uint64_t h,
                                      const uint64_t (&k)[WB], int64_t parent, double num, const double *Hp,
                                      const double *G, double e0, Acc &a, bool search)
@@ -920,17 +957,19 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const 
         if (hj != h)
             break;
         const int64_t idx = staged ? s_ri[j - lo] : (int64_t)((const uint64_t *)rh.pay)[j];
+        uint64_t rk[WB];
+        ref_bits<WB>(ra, idx, rk);
         bool eq = true;
 #pragma unroll
         for (int w = 0; w < WB; w++)
-            eq = eq && pl_get<WB>(bits, w, idx) == k[w];
+            eq = eq && rk[w] == k[w];
         if (eq) {
             a.n_hit++;
             a.ref_cross += ((const double *)bits.pay)[idx] * num;
             return;
         }
     }
-    const double haa = diag_parent<WB>(s.T, 2 * s.norb, k, bits, parent, G, Hp[parent]);
+    const double haa = diag_parent<WB>(s.T, 2 * s.norb, k, ra, parent, G, Hp[parent]);
     const double den = e0 - haa;
     a.n_ext++;
     const double ad = fabs(den);
@@ -1022,7 +1061,8 @@ __device__ inline bool bits_eq(const uint64_t (&x)[WB], const uint64_t (&y)[WB])
 }
 
 template <int WB, int PB>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits, Planes rh,
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits,
+                                                             const uint64_t *ra, Planes rh,
                                                              int64_t nref, const double *Hp, const double *G,
                                                              double e0, int64_t tiles_per_block, int search,
                                                              Partial *partials, uint32_t *coll, Flags *flags)
@@ -1108,7 +1148,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
 #pragma unroll
         for (int j = 0; j < RED_ITEMS; j++) {
             if (r0 + j < tend)
-                hash_key<WB>(bits, ax[j], kb[j]);
+                hash_key<WB>(ra, ax[j], kb[j]);
             else
 #pragma unroll
                 for (int w = 0; w < WB; w++)
@@ -1125,13 +1165,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
         if (lane == 0 && has_prev) {
             hprev = in.key[0][r0 - 1];
             if (r0 > base)
-                hash_key<WB>(bits, in.key[1][r0 - 1], kprev);
+                hash_key<WB>(ra, in.key[1][r0 - 1], kprev);
         }
         const uint64_t hnext = r0 + RED_ITEMS < n ? in.key[0][r0 + RED_ITEMS] : 0ull;
         const bool has_next = r0 + RED_ITEMS < n;
 
         double run[RED_ITEMS];
-        uint64_t ra[RED_ITEMS];
+        uint64_t rha[RED_ITEMS];
         int rc[RED_ITEMS];
         bool hh[RED_ITEMS], tl[RED_ITEMS];
         HashScan me;
@@ -1163,7 +1203,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                     me.c |= differs ? 1 : 0;
                 }
             }
-            run[j] = me.v, ra[j] = me.a, rc[j] = me.c;
+            run[j] = me.v, rha[j] = me.a, rc[j] = me.c;
             hh[j] = me.f != 0;
         }
         // inclusive scan within the wavefront, then the earlier wavefronts
@@ -1206,7 +1246,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 s_ch = h[j];
                 s_cont.f = 1;
                 s_cont.v = hh[j] ? run[j] : carry.v + run[j];
-                s_cont.a = hh[j] ? ra[j] : carry.a;
+                s_cont.a = hh[j] ? rha[j] : carry.a;
                 s_cont.c = hh[j] ? rc[j] : (carry.c | rc[j]);
                 s_cflag = 1;
             }
@@ -1236,7 +1276,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
             if (owned && tl[j]) {
                 q_h[slot] = h[j];
                 q_v[slot] = hh[j] ? run[j] : carry.v + run[j];
-                q_a[slot] = hh[j] ? ra[j] : carry.a;
+                q_a[slot] = hh[j] ? rha[j] : carry.a;
                 q_c[slot] = hh[j] ? rc[j] : (carry.c | rc[j]);
                 slot++;
             }
@@ -1246,7 +1286,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
             // wave 0 follows the continuing segment into the following records
             const uint64_t ch = s_ch;
             uint64_t k0[WB];
-            hash_key<WB>(bits, s_cont.a, k0);
+            hash_key<WB>(ra, s_cont.a, k0);
             double total = 0.0;
             int col = 0;
             int64_t pos = tend;
@@ -1258,7 +1298,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                     eq = true;
                     v = load_pay<PB>(in, idx);
                     uint64_t kk[WB];
-                    hash_key<WB>(bits, in.key[1][idx], kk);
+                    hash_key<WB>(ra, in.key[1][idx], kk);
                     col |= bits_eq<WB>(kk, k0) ? 0 : 1;
                 }
                 const uint64_t m = __ballot(eq);
@@ -1290,8 +1330,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
             }
             uint64_t k0[WB];
             const uint64_t aux = q_a[e];
-            hash_key<WB>(bits, aux, k0);
-            hash_key_term<WB>(s, bits, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32), q_v[e], Hp,
+            hash_key<WB>(ra, aux, k0);
+            hash_key_term<WB>(s, bits, ra, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32), q_v[e], Hp,
                               G, e0, a, search != 0);
         }
         __syncthreads();
@@ -1313,7 +1353,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
 // merged into the one k_reduce_hash wrote.  Unmarked workgroups return at once.
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
-                                                                  Planes rh, int64_t nref, const double *Hp,
+                                                                  const uint64_t *ra, Planes rh, int64_t nref, const double *Hp,
                                                                   const double *G, double e0,
                                                                   int64_t tiles_per_block, int search, Partial *partials,
                                                                   const uint32_t *coll, Flags *flags)
@@ -1342,11 +1382,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Plan
             while (e < n && in.key[0][e] == h)
                 e++;
             uint64_t k0[WB];
-            hash_key<WB>(bits, in.key[1][i], k0);
+            hash_key<WB>(ra, in.key[1][i], k0);
             bool collided = false;
             for (int64_t y = i + 1; y < e && !collided; y++) {
                 uint64_t ky[WB];
-                hash_key<WB>(bits, in.key[1][y], ky);
+                hash_key<WB>(ra, in.key[1][y], ky);
                 for (int w = 0; w < WB; w++)
                     collided = collided || ky[w] != k0[w];
             }
@@ -1355,11 +1395,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Plan
             for (int64_t x = i; x < e; x++) {
                 uint64_t kx[WB];
                 const uint64_t ax = in.key[1][x];
-                hash_key<WB>(bits, ax, kx);
+                hash_key<WB>(ra, ax, kx);
                 bool seen = false;
                 for (int64_t y = i; y < x && !seen; y++) {
                     uint64_t ky[WB];
-                    hash_key<WB>(bits, in.key[1][y], ky);
+                    hash_key<WB>(ra, in.key[1][y], ky);
                     bool same = true;
                     for (int w = 0; w < WB; w++)
                         same = same && ky[w] == kx[w];
@@ -1370,7 +1410,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Plan
                 double nx = 0.0;
                 for (int64_t y = x; y < e; y++) {
                     uint64_t ky[WB];
-                    hash_key<WB>(bits, in.key[1][y], ky);
+                    hash_key<WB>(ra, in.key[1][y], ky);
                     bool same = true;
                     for (int w = 0; w < WB; w++)
                         same = same && ky[w] == kx[w];
@@ -1378,7 +1418,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Plan
                         nx += load_pay<PB>(in, y);
                 }
                 // references searched in global memory over the whole list
-                hash_key_term<WB>(s, bits, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), nx,
+                hash_key_term<WB>(s, bits, ra, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), nx,
                                   Hp, G, e0, a, search != 0);
             }
         }
@@ -1577,6 +1617,22 @@ hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, cons
     return hipGetLastError();
 }
 
+hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ra, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t gg = (n + 255) / 256;
+    dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_refs_aos<1>), g, b, 0, st, bits, n, ra); break;
+    case 2: hipLaunchKernelGGL((k_refs_aos<2>), g, b, 0, st, bits, n, ra); break;
+    case 3: hipLaunchKernelGGL((k_refs_aos<3>), g, b, 0, st, bits, n, ra); break;
+    case 4: hipLaunchKernelGGL((k_refs_aos<4>), g, b, 0, st, bits, n, ra); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st)
 {
     if (n <= 0)
@@ -1595,7 +1651,7 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
 }
 
 hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
-                              const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
+                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
                               int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
@@ -1603,9 +1659,9 @@ hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, i
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RH(WB, PB)                                                                                                 \
     do {                                                                                                           \
-        hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, rh, nref, Hp, G, e0, per,     \
+        hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per,     \
                            search, partials, coll, flags);                                                         \
-        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, rh, nref, Hp, G, e0, per, \
+        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per, \
                            search, partials, coll, flags);                                                         \
     } while (0)
     switch (s.W * 2 + (fp32 ? 0 : 1)) {

@@ -222,7 +222,16 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (int i = tid; i < 4 * 256; i += SORT_THREADS)
         (&s_wc[0][0])[i] = 0;
+#if PT2_XCD_TILES
+    // Workgroups are dealt to the 8 XCDs in turn; give each XCD a contiguous
+    // range of tiles, so that the runs consecutive tiles write into a bucket
+    // meet in one L2.  A bijection of [0, ntiles) for any ntiles.
+    const int64_t nt = gridDim.x, q = nt >> 3, r = nt & 7;
+    const int64_t x = blockIdx.x & 7, i = blockIdx.x >> 3;
+    const int64_t tile = x * q + (x < r ? x : r) + i;
+#else
     const int64_t tile = blockIdx.x;
+#endif
     const int64_t base = tile * SORT_TILE;
     const int word = dig >> 3, shift = (dig & 7) * 8;
     const uint64_t my_off = offs[tile * 256 + tid];
