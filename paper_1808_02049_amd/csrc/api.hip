@@ -373,7 +373,7 @@ void carve_slice(Workspace &ws, char *p, int W, int pb, int topb, int64_t cap)
 // Stable LSD sort of n records held in *src (ping-pong with *dst) on key bits
 // [0, nbits).  On return *src holds the sorted records.
 int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n, int nbits, hipStream_t st,
-               Timing &tm, uint32_t *passes_out, double *bytes_out)
+               Timing &tm, uint32_t *passes_out, double *bytes_out, int items = SORT_ITEMS)
 {
     if (n <= 1)
         return PT2_OK;
@@ -410,7 +410,7 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
             return fail(PT2_E_DEVICE, "hipEventCreate failed");
         HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint32_t *)ws.counts.p,
                                  (uint64_t *)ws.csum.p, (uint64_t *)ws.coff.p, (uint64_t *)ws.offs.p, &ds->flags,
-                                 st, mid));
+                                 st, mid, items));
         if (tm.on) {
             if ((rc = timed_end(ws, tm, st, mid, 1)))
                 return rc;
@@ -782,7 +782,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         res.bytes_gen += (double)n * rbytes;
         if (J.dump == 1)
             break;  // generation order: the records are in recA
-        if ((rc = radix_sort(ws, W, pb, A, B, n, RL.bits, st, tm, &res.n_sort_passes, &res.bytes_sort)))
+        if ((rc = radix_sort(ws, W, pb, A, B, n, RL.bits, st, tm, &res.n_sort_passes, &res.bytes_sort,
+                             RL.hash ? SORT_ITEMS_WIDE : SORT_ITEMS)))
             return rc;
         if (J.dump == 2 || J.dump == 3) {
             // hand the sorted planes to the inspection copy below (it reads recA)

@@ -22,6 +22,9 @@ constexpr int SORT_THREADS = 256;
 #endif
 constexpr int SORT_ITEMS = PT2_SORT_ITEMS;
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;   // records per radix tile
+// Records per thread for keys whose digits are uniform (hash records): every
+// digit value takes a share of each tile, so longer tiles give longer runs.
+constexpr int SORT_ITEMS_WIDE = 2 * SORT_ITEMS;
 constexpr int SCAN_CHUNK = 256;                        // tiles per chunk of the offset scan
 constexpr int RED_THREADS = 256;
 constexpr int RED_ITEMS = 4;
@@ -322,7 +325,8 @@ hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hi
 // the counting/scan kernels and the scatter.
 hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
                              const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
-                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid);
+                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid,
+                             int items = SORT_ITEMS);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t st);
 // AoS dets + coeffs -> SoA planes, with input checks.

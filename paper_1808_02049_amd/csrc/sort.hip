@@ -118,23 +118,24 @@ __global__ __launch_bounds__(256) void k_hist_scan(const unsigned long long *his
 // Step 1: digit counts of every tile (counts[tile * 256 + digit]).  Each
 // thread reads SORT_ITEMS consecutive records, merges runs of equal digits,
 // and adds them to its wavefront's LDS histogram.
-template <int W>
+template <int W, int IT>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t n, int dig, uint32_t *counts)
 {
+    constexpr int TILE = SORT_THREADS * IT;
     __shared__ uint32_t h[SORT_THREADS / 64][256];
     const int tid = threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < (SORT_THREADS / 64) * 256; i += SORT_THREADS)
         (&h[0][0])[i] = 0;
     __syncthreads();
     const int word = dig >> 3, shift = (dig & 7) * 8;
-    const int64_t r0 = (int64_t)blockIdx.x * SORT_TILE + (int64_t)tid * SORT_ITEMS;
-    uint64_t v[SORT_ITEMS];
+    const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)tid * IT;
+    uint64_t v[IT];
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; j++)
+    for (int j = 0; j < IT; j++)
         v[j] = r0 + j < n ? pl_get<W>(in, word, r0 + j) : 0ull;
     uint32_t last = 0xFFFFFFFFu, cnt = 0;
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; j++) {
+    for (int j = 0; j < IT; j++) {
         if (r0 + j < n) {
             const uint32_t d = (uint32_t)(v[j] >> shift) & 255u;
             if (d == last) {
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const uint32_t *counts, in
 }
 
 // Step 3: rank and scatter one tile.
-template <int W, int PB>
+template <int W, int PB, int IT>
 __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out, int64_t n, int dig,
                                                           const uint64_t *offs, Flags *flags)
 {
@@ -215,8 +216,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
     __shared__ uint32_t s_tstart[256];
     __shared__ int64_t s_gbase[256];
     __shared__ uint32_t s_sc[4];
-    __shared__ uint64_t s_stage[SORT_TILE];
-    __shared__ uint8_t s_dig[SORT_TILE];
+    constexpr int TILE = SORT_THREADS * IT;
+    __shared__ uint64_t s_stage[TILE];
+    __shared__ uint8_t s_dig[TILE];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -232,22 +234,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
 #else
     const int64_t tile = blockIdx.x;
 #endif
-    const int64_t base = tile * SORT_TILE;
+    const int64_t base = tile * TILE;
     const int word = dig >> 3, shift = (dig & 7) * 8;
     const uint64_t my_off = offs[tile * 256 + tid];
 
-    uint64_t kw[SORT_ITEMS];
-    uint32_t rank[SORT_ITEMS];
+    uint64_t kw[IT];
+    uint32_t rank[IT];
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; j++) {
-        const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
+    for (int j = 0; j < IT; j++) {
+        const int64_t idx = base + (int64_t)wave * 64 * IT + j * 64 + lane;
         kw[j] = idx < n ? pl_get<W>(in, word, idx) : 0ull;
     }
     __syncthreads();
     // rank within the wave: peers = lanes with the same digit (stable)
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; j++) {
-        const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
+    for (int j = 0; j < IT; j++) {
+        const int64_t idx = base + (int64_t)wave * 64 * IT + j * 64 + lane;
         const bool valid = idx < n;
         const uint32_t d = (uint32_t)(kw[j] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
@@ -282,21 +284,21 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
     }
     __syncthreads();
 
-    uint32_t lpos[SORT_ITEMS];
+    uint32_t lpos[IT];
 #pragma unroll
-    for (int j = 0; j < SORT_ITEMS; j++) {
+    for (int j = 0; j < IT; j++) {
         const uint32_t d = (uint32_t)(kw[j] >> shift) & 255u;
         lpos[j] = s_tstart[d] + s_wc[wave][d] + rank[j];
     }
     const int64_t rem = n - base;
-    const int tile_n = rem < SORT_TILE ? (int)rem : SORT_TILE;
+    const int tile_n = rem < TILE ? (int)rem : TILE;
 
     // plane w of the tile's records, in input order (the digit plane is
     // already in registers)
-    auto load_plane = [&](int w, uint64_t(&v)[SORT_ITEMS]) {
+    auto load_plane = [&](int w, uint64_t(&v)[IT]) {
 #pragma unroll
-        for (int j = 0; j < SORT_ITEMS; j++) {
-            const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
+        for (int j = 0; j < IT; j++) {
+            const int64_t idx = base + (int64_t)wave * 64 * IT + j * 64 + lane;
             uint64_t x = 0;
             if (w == word)
                 x = kw[j];
@@ -307,19 +309,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
             v[j] = x;
         }
     };
-    uint64_t cur[SORT_ITEMS];
+    uint64_t cur[IT];
     load_plane(0, cur);
 
 #pragma unroll
     for (int w = 0; w < W + 1; w++) {
         // the next plane's loads are in flight while this one is staged
-        uint64_t nxt[SORT_ITEMS];
+        uint64_t nxt[IT];
         if (w < W)
             load_plane(w + 1, nxt);
-        uint64_t(&cv)[SORT_ITEMS] = cur;
+        uint64_t(&cv)[IT] = cur;
 #pragma unroll
-        for (int j = 0; j < SORT_ITEMS; j++) {
-            const int64_t idx = base + (int64_t)wave * 64 * SORT_ITEMS + j * 64 + lane;
+        for (int j = 0; j < IT; j++) {
+            const int64_t idx = base + (int64_t)wave * 64 * IT + j * 64 + lane;
             if (idx < n) {
                 s_stage[lpos[j]] = cv[j];
                 if (w == 0)
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
         __syncthreads();
         if (w < W) {
 #pragma unroll
-            for (int j = 0; j < SORT_ITEMS; j++)
+            for (int j = 0; j < IT; j++)
                 cur[j] = nxt[j];
         }
     }
@@ -455,28 +457,43 @@ hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hi
 
 hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
                              const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
-                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid)
+                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid, int items)
 {
     if (n <= 0)
         return hipSuccess;
-    const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if (items != SORT_ITEMS && items != SORT_ITEMS_WIDE)
+        return hipErrorInvalidValue;
+    const int64_t tile = (int64_t)SORT_THREADS * items;
+    const int64_t ntiles = (n + tile - 1) / tile;
     const int64_t nchunks = (ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     if (ntiles > 0x7FFFFFFFll)
         return hipErrorInvalidValue;
     dim3 g((unsigned)ntiles), b(SORT_THREADS);
-    switch (W) {
-    case 1: hipLaunchKernelGGL((k_tile_count<1>), g, b, 0, st, in, n, dig, counts); break;
-    case 2: hipLaunchKernelGGL((k_tile_count<2>), g, b, 0, st, in, n, dig, counts); break;
-    case 3: hipLaunchKernelGGL((k_tile_count<3>), g, b, 0, st, in, n, dig, counts); break;
-    case 4: hipLaunchKernelGGL((k_tile_count<4>), g, b, 0, st, in, n, dig, counts); break;
+#define TC(WW, IT) hipLaunchKernelGGL((k_tile_count<WW, IT>), g, b, 0, st, in, n, dig, counts)
+    switch (W * 2 + (items == SORT_ITEMS ? 0 : 1)) {
+    case 2: TC(1, SORT_ITEMS); break;
+    case 3: TC(1, SORT_ITEMS_WIDE); break;
+    case 4: TC(2, SORT_ITEMS); break;
+    case 5: TC(2, SORT_ITEMS_WIDE); break;
+    case 6: TC(3, SORT_ITEMS); break;
+    case 7: TC(3, SORT_ITEMS_WIDE); break;
+    case 8: TC(4, SORT_ITEMS); break;
+    case 9: TC(4, SORT_ITEMS_WIDE); break;
     default: return hipErrorInvalidValue;
     }
+#undef TC
     hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, csum);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, csum, nchunks, bucket, coff);
     hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, coff, offs);
     if (mid)
         (void)hipEventRecord(mid, st);
-#define SC(WW, PB) hipLaunchKernelGGL((k_scatter<WW, PB>), g, b, 0, st, in, out, n, dig, offs, flags)
+#define SC(WW, PB)                                                                                            \
+    do {                                                                                                      \
+        if (items == SORT_ITEMS)                                                                              \
+            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS>), g, b, 0, st, in, out, n, dig, offs, flags);      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS_WIDE>), g, b, 0, st, in, out, n, dig, offs, flags); \
+    } while (0)
     switch (W * 2 + (pay_bytes == 8 ? 1 : 0)) {
     case 2: SC(1, 4); break;
     case 3: SC(1, 8); break;
