@@ -17,6 +17,9 @@ constexpr int SORT_THREADS = 256;
 #ifndef PT2_XCD_TILES
 #define PT2_XCD_TILES 1
 #endif
+#ifndef PT2_WIDE_PIPE
+#define PT2_WIDE_PIPE 1
+#endif
 #ifndef PT2_SORT_ITEMS
 #define PT2_SORT_ITEMS 8
 #endif

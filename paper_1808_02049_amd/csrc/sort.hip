@@ -309,15 +309,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
             v[j] = x;
         }
     };
+    // narrow tiles keep the next plane's loads in flight while one plane is
+    // staged; wide tiles load each plane when it is staged (registers)
+    constexpr bool PIPE = IT <= SORT_ITEMS || PT2_WIDE_PIPE;
     uint64_t cur[IT];
-    load_plane(0, cur);
+    if constexpr (PIPE)
+        load_plane(0, cur);
 
 #pragma unroll
     for (int w = 0; w < W + 1; w++) {
-        // the next plane's loads are in flight while this one is staged
         uint64_t nxt[IT];
-        if (w < W)
-            load_plane(w + 1, nxt);
+        if constexpr (PIPE) {
+            if (w < W)
+                load_plane(w + 1, nxt);
+        } else {
+            load_plane(w, cur);
+        }
         uint64_t(&cv)[IT] = cur;
 #pragma unroll
         for (int j = 0; j < IT; j++) {
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
                 ((uint32_t *)out.pay)[dst] = (uint32_t)v;
         }
         __syncthreads();
-        if (w < W) {
+        if (PIPE && w < W) {
 #pragma unroll
             for (int j = 0; j < IT; j++)
                 cur[j] = nxt[j];
