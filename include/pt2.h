@@ -135,6 +135,18 @@ typedef struct {
     int hash_bits;                 /* hash records: bits of the hash kept as the sort
                                       key, 0 = 64.  Fewer bits only make collisions
                                       common, to test their handling                 */
+    int spin_flip;                 /* 1: use the alpha/beta swap symmetry of an S_z = 0
+                                      reference (Section V, spin symmetry): only
+                                      determinants whose alpha string is not below
+                                      their beta string are generated, and the term
+                                      of each with alpha != beta counts twice.  Needs
+                                      nalpha == nbeta (else PT2_E_INVALID at create)
+                                      and a reference closed under the swap with
+                                      c(swap(D)) = c(D) for all D, or = -c(D) for all
+                                      D (else PT2_E_INVALID at evaluation).  Counts
+                                      and checksums then cover the generated half;
+                                      n_contrib stays the structural count of all
+                                      terms.  Default 0                              */
 } pt2_options;
 
 typedef struct {

@@ -558,7 +558,7 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    if (P.target && cutoff <= 0.0)
+    if (P.target && cutoff <= 0.0 && !sys.z2)
         HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (uint32_t *)ws.cnt.p, st));
     else
         HIPCHK(launch_count(sys, L, pm, refs, nref, P.chunk, P.log2p, cutoff, (uint32_t *)ws.cnt.p, P.nchunks, st));
@@ -602,7 +602,9 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
         if (k > MAX_LOG2P)
             return fail(PT2_E_NOMEM, "no split of at most 2^%d subsets fits the device budget", MAX_LOG2P);
         P.log2p = k;
-        P.compact = k > 0 || cutoff > 0.0;
+        // a cutoff or the spin flip filter terms: counted by enumeration
+        const bool filtered = cutoff > 0.0 || sys.z2;
+        P.compact = k > 0 || filtered;
         P.parts.clear();
         if (J.parts) {
             for (int i = 0; i < J.nparts; i++) {
@@ -633,15 +635,18 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
         }
         int rc;
         std::vector<uint64_t> tot;
-        if (cutoff > 0.0) {
-            if ((rc = count_pass(c, sys, L, ws, refs, nref, P, 0.0, st, tot)))
+        if (filtered) {
+            // structural count: every term, no cutoff, no spin flip filter
+            DevSys s0 = sys;
+            s0.z2 = 0;
+            if ((rc = count_pass(c, s0, L, ws, refs, nref, P, 0.0, st, tot)))
                 return rc;
             P.structural = tot;
         }
         if ((rc = count_pass(c, sys, L, ws, refs, nref, P, cutoff, st, tot)))
             return rc;
         P.sizes = tot;
-        if (cutoff <= 0.0)
+        if (!filtered)
             P.structural = tot;
         uint64_t mx = 0;
         for (auto t : tot)
@@ -702,6 +707,19 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     Planes refs;
     if ((rc = prepare_refs(c, ws, J.dets, J.coeffs, J.n, J.host, st, tm, refs)))
         return rc;
+    if (sys.z2) {
+        // the spin flip is exact only for a reference closed under the swap
+        Small *d0 = ws.dsmall();
+        HIPCHK(launch_zero_u32(&d0->flags.err, 2, st));
+        HIPCHK(launch_check_swap(sys, refs, J.n, &d0->flags, st));
+        HIPCHK(hipMemcpyAsync(&ws.host_small->flags, &d0->flags, sizeof(Flags), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const uint32_t f = ws.host_small->flags.err;
+        if ((f & ERR_SWAP_MISSING) || ((f & SWAP_SAME) && (f & SWAP_NEG)))
+            return fail(PT2_E_INVALID, "spin_flip needs a reference closed under the alpha/beta swap, with "
+                                       "c(swap(D)) = c(D) for all D or -c(D) for all D");
+        HIPCHK(launch_zero_u32(&d0->flags.err, 2, st));
+    }
     // the single pass compares stored keys with reference keys of the same format
     Planes refs_red = refs;
     if (RL.rank) {
@@ -1380,6 +1398,10 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         return fail(PT2_E_INVALID, "log2_partitions must be <= %d", MAX_LOG2P);
     if (o.hash_bits < 0 || o.hash_bits > 64)
         return fail(PT2_E_INVALID, "hash_bits must be in [0, 64]");
+    if (o.spin_flip != 0 && o.spin_flip != 1)
+        return fail(PT2_E_INVALID, "spin_flip must be 0 or 1");
+    if (o.spin_flip && nalpha != nbeta)
+        return fail(PT2_E_INVALID, "spin_flip needs nalpha == nbeta (S_z = 0)");
     if (o.compress_keys < -1 || o.compress_keys > 2)
         return fail(PT2_E_INVALID, "compress_keys must be -1, 0, 1 or 2");
     if ((o.alloc == nullptr) != (o.free == nullptr))
@@ -1480,6 +1502,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.V32 = (const float *)c->V32.p;
     c->sys.T = (const double *)c->T.p;
     c->sys.R = (const uint64_t *)c->R.p;
+    c->sys.z2 = o.spin_flip;
 
     // record keys: the bitstring, the combinatorial rank, or the Zobrist hash
     // (with the parent and the flips); cost = bytes moved per record by the

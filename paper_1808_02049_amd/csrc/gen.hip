@@ -485,8 +485,10 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
 // the integrals and the arithmetic are FP32).
 template <int W, int PM>
 __device__ inline bool keep_term(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
-                                 double cutoff)
+                                 double cutoff, const uint64_t (&key)[W])
 {
+    if (s.z2 && !alpha_not_below_beta<W>(key, s.norb))
+        return false;  // the swap partner stands for it
     if (cutoff <= 0.0)
         return true;
     if (PM == PM_FP32_ARITH) {
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count(DevSys s, ExcLayout L, co
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        if (keep_term<W, PM>(g, s, L, e, cutoff))
+        if (keep_term<W, PM>(g, s, L, e, cutoff, key))
             atomicAdd(&hist[part_of(z, log2p)], 1u);
     }
     __syncthreads();
@@ -557,7 +559,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
         if (k < hi) {
             e = decode(g, L, D, k);
             exc_key<W>(g, s.norb, e, key, z);
-            keep = part_of(z, log2p) == part && keep_term<W, PM>(g, s, L, e, cutoff);
+            keep = part_of(z, log2p) == part && keep_term<W, PM>(g, s, L, e, cutoff, key);
         }
         uint64_t m = __ballot(keep);
         if (lane == 0)
@@ -814,7 +816,7 @@ __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayo
         const bool in = part_of(z, log2p) == part;
         if (!in && !filter)
             bad = true;  // a walked candidate outside the subset: bucketing is inconsistent
-        keep = in && keep_term<W, PM>(g, s, L, e, cutoff);
+        keep = in && keep_term<W, PM>(g, s, L, e, cutoff, key);
     }
     const uint64_t m = __ballot(keep);
     if (lane == 0)

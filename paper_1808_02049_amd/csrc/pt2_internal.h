@@ -45,7 +45,11 @@ enum : uint32_t {
     ERR_DUPLICATE = 4u,     // two equal reference determinants
     ERR_BOUNDS = 8u,        // a radix scatter destination fell outside the buffer
     ERR_SINGULAR = 16u,     // E0 - H_aa == 0 for an external determinant
-    ERR_OVERFLOW = 32u      // a compacted write ran past its planned range
+    ERR_OVERFLOW = 32u,     // a compacted write ran past its planned range
+    ERR_SWAP_MISSING = 64u, // spin flip: a reference's swap partner is absent or
+                            // has a coefficient of another magnitude
+    SWAP_SAME = 128u,       // spin flip: some c(swap(D)) == c(D) (not an error)
+    SWAP_NEG = 256u         // spin flip: some c(swap(D)) == -c(D), D != swap(D)
 };
 
 struct Flags {
@@ -90,7 +94,56 @@ struct DevSys {
                         // diagonal, row b1 at b1*nso - b1*(b1-1)/2 - b1, column b2 >= b1:
                         // T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin](pq|qp)
     const uint64_t *R;  // Zobrist words, one per bit (2 norb)
+    int z2;             // spin flip: generate alpha >= beta only, weight alpha != beta by 2
 };
+
+// The alpha string (bits norb..2norb-1) and the beta string (bits 0..norb-1)
+// of a bitstring, each as a 128-bit number (hi, lo); norb <= 127.
+template <int W>
+__host__ __device__ inline uint64_t bits64_at(const uint64_t (&k)[W], int start)
+{
+    const int w = start >> 6, sh = start & 63;
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        if (i == w)
+            lo = k[i] >> sh;
+        if (sh && i == w + 1)
+            hi = k[i] << (64 - sh);
+    }
+    return lo | hi;
+}
+
+__host__ __device__ inline uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1); }
+
+template <int W>
+__host__ __device__ inline void spin_strings(const uint64_t (&k)[W], int norb, uint64_t &alo, uint64_t &ahi,
+                                             uint64_t &blo, uint64_t &bhi)
+{
+    blo = bits64_at<W>(k, 0) & low_mask(norb);
+    bhi = norb > 64 ? bits64_at<W>(k, 64) & low_mask(norb - 64) : 0ull;
+    alo = bits64_at<W>(k, norb) & low_mask(norb);
+    ahi = norb > 64 ? bits64_at<W>(k, norb + 64) & low_mask(norb - 64) : 0ull;
+}
+
+// alpha string >= beta string (the half the spin flip generates)
+template <int W>
+__host__ __device__ inline bool alpha_not_below_beta(const uint64_t (&k)[W], int norb)
+{
+    uint64_t alo, ahi, blo, bhi;
+    spin_strings<W>(k, norb, alo, ahi, blo, bhi);
+    return ahi != bhi ? ahi > bhi : alo >= blo;
+}
+
+// weight of a generated determinant's term under the spin flip: 2 when its
+// swap partner is a different determinant (not generated), else 1
+template <int W>
+__host__ __device__ inline double swap_weight(const uint64_t (&k)[W], int norb)
+{
+    uint64_t alo, ahi, blo, bhi;
+    spin_strings<W>(k, norb, alo, ahi, blo, bhi);
+    return alo == blo && ahi == bhi ? 1.0 : 2.0;
+}
 
 // Structure-of-arrays record buffer: W key planes then one payload plane.
 // Planes 0..W-2 hold uint64 words; the last key plane holds `topb`-byte
@@ -352,6 +405,10 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
 // (partials: 256 entries of scratch).
 hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, double e0, Partial *partials,
                             Partial *out, hipStream_t st);
+// Spin flip: check that every sorted reference's alpha/beta swap is present
+// with a coefficient of equal magnitude (flags: ERR_SWAP_MISSING, SWAP_SAME,
+// SWAP_NEG).
+hipError_t launch_check_swap(const DevSys &s, const Planes &refs, int64_t n, Flags *flags, hipStream_t st);
 // Rank keys of sorted bitstring references (planes of kw words + coefficients).
 hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
 // Hash records: the references' hashes with their indices (planes: 1 key word

@@ -275,6 +275,21 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
                                        bool search)
 {
     a.n_unique++;
+    // spin flip: the weight of a generated determinant (2 unless alpha == beta)
+    auto weight = [&]() -> double {
+        if (!s.z2)
+            return 1.0;
+        uint64_t kw[WB];
+        if constexpr (RK) {
+            unrank_key<WB>(k[0], W > 1 ? k[W > 1 ? 1 : 0] : 0ull, s.norb, s.na, s.nb, s.kc.bb, binom,
+                           s.kc.stride, kw);
+        } else {
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                kw[w] = k[w < W ? w : 0];
+        }
+        return swap_weight<WB>(kw, s.norb);
+    };
     if (!search) {
         // reference determinants stay in; their terms are subtracted afterwards
     } else if (rs.staged) {
@@ -288,7 +303,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
             const int c = key_cmp<W>(r, k);
             if (c == 0) {
                 a.n_hit++;
-                a.ref_cross += s_rc[mid] * num;
+                a.ref_cross += weight() * (s_rc[mid] * num);
                 return;
             }
             if (c < 0)
@@ -303,7 +318,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
             load_key<W>(refs, i, r);
             if (key_eq<W>(r, k)) {
                 a.n_hit++;
-                a.ref_cross += ((const double *)refs.pay)[i] * num;
+                a.ref_cross += weight() * (((const double *)refs.pay)[i] * num);
                 return;
             }
         }
@@ -326,7 +341,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
     if (den == 0.0)
         a.singular = 1;
     else
-        neumaier(a.e_sum, a.e_comp, num * num / den);
+        neumaier(a.e_sum, a.e_comp, (s.z2 ? swap_weight<WB>(kb, s.norb) : 1.0) * (num * num / den));
     const uint64_t m = key_mix<WB>(kb);
     a.kx ^= m;
     a.ks += m;
@@ -965,7 +980,7 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const 
             eq = eq && rk[w] == k[w];
         if (eq) {
             a.n_hit++;
-            a.ref_cross += ((const double *)bits.pay)[idx] * num;
+            a.ref_cross += (s.z2 ? swap_weight<WB>(k, s.norb) : 1.0) * (((const double *)bits.pay)[idx] * num);
             return;
         }
     }
@@ -979,7 +994,7 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const 
     if (den == 0.0)
         a.singular = 1;
     else
-        neumaier(a.e_sum, a.e_comp, num * num / den);
+        neumaier(a.e_sum, a.e_comp, (s.z2 ? swap_weight<WB>(k, s.norb) : 1.0) * (num * num / den));
     const uint64_t m = key_mix<WB>(k);
     a.kx ^= m;
     a.ks += m;
@@ -1598,6 +1613,70 @@ hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, doub
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, partials, 256, out);
+    return hipGetLastError();
+}
+
+// Spin flip: each sorted reference's alpha/beta swap must be present with a
+// coefficient of equal magnitude; the signs must agree for all references or
+// be opposite for all (an eigenfunction of the swap).
+template <int W>
+__global__ void k_check_swap(DevSys s, Planes refs, int64_t n, Flags *flags)
+{
+    const int norb = s.norb;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k[W], sw[W];
+        load_key<W>(refs, i, k);
+        uint64_t alo, ahi, blo, bhi;
+        spin_strings<W>(k, norb, alo, ahi, blo, bhi);
+        // swapped: beta part <- alpha string, alpha part <- beta string
+#pragma unroll
+        for (int w = 0; w < W; w++)
+            sw[w] = 0;
+        auto put = [&](int start, uint64_t v, int len) {
+            for (int b = 0; b < len; b++)
+                if ((v >> b) & 1ull) {
+                    const int bit = start + b;
+#pragma unroll
+                    for (int w = 0; w < W; w++)
+                        sw[w] |= (w == (bit >> 6)) ? (1ull << (bit & 63)) : 0ull;
+                }
+        };
+        const int l0 = norb < 64 ? norb : 64;
+        put(0, alo, l0);
+        put(64, ahi, norb - l0);
+        put(norb, blo, l0);
+        put(norb + 64, bhi, norb - l0);
+        const int64_t j = ref_bound<W>(refs, 0, n, sw, false);
+        uint64_t r[W];
+        bool found = false;
+        if (j < n) {
+            load_key<W>(refs, j, r);
+            found = key_eq<W>(r, sw);
+        }
+        const double ci = ((const double *)refs.pay)[i];
+        const double cj = found ? ((const double *)refs.pay)[j] : 0.0;
+        if (!found || fabs(ci) != fabs(cj))
+            atomicOr(&flags->err, ERR_SWAP_MISSING);
+        else if (ci == cj)
+            atomicOr(&flags->err, SWAP_SAME);
+        else
+            atomicOr(&flags->err, SWAP_NEG);
+    }
+}
+
+hipError_t launch_check_swap(const DevSys &s, const Planes &refs, int64_t n, Flags *flags, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t gg = (n + 255) / 256;
+    dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_check_swap<1>), g, b, 0, st, s, refs, n, flags); break;
+    case 2: hipLaunchKernelGGL((k_check_swap<2>), g, b, 0, st, s, refs, n, flags); break;
+    case 3: hipLaunchKernelGGL((k_check_swap<3>), g, b, 0, st, s, refs, n, flags); break;
+    case 4: hipLaunchKernelGGL((k_check_swap<4>), g, b, 0, st, s, refs, n, flags); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ __all__ = [
     "Workload", "WORKLOADS", "key_words", "pack_keys", "unpack_keys",
     "hf_key", "make_integrals", "excitation_pool", "decaying_coefficients",
     "draw_signs", "select_lowest", "random_determinants", "n_excitations_per_det",
+    "swap_symmetric_references",
     "ladder_references", "Request", "serving_requests", "request_inputs",
 ]
 
@@ -205,6 +206,31 @@ def decaying_coefficients(n: int, decay: float, signs: np.ndarray) -> np.ndarray
     """c_rank = sign * exp(-decay * rank), normalised to unit length."""
     c = signs[:n] * np.exp(-decay * np.arange(n, dtype=np.float64))
     return c / math.sqrt(float(np.dot(c, c)))
+
+
+def swap_symmetric_references(norb: int, n_el: int, n: int, seed: int, sign: int = 1):
+    """A reference closed under the alpha/beta swap (S_z = 0, n_el electrons of
+    each spin): n random determinants, their swap partners added, and
+    coefficients with c(swap(D)) = sign * c(D) (a determinant equal to its own
+    swap gets 0 when sign is -1), normalised.  Returns (dets (m, W) uint64, c)."""
+    base = random_determinants(norb, n_el, n_el, n, seed)
+    a, b = unpack_keys(base, norb)
+    both = np.concatenate([base, pack_keys(b, a, norb)])
+    keys, inv = np.unique(both, axis=0, return_inverse=True)
+    inv = np.asarray(inv).reshape(-1)
+    rng = np.random.default_rng(seed + 1)
+    c = np.zeros(len(keys))
+    draw = rng.normal(size=n)
+    for i in range(n):
+        d, s_ = inv[i], inv[n + i]
+        if d == s_:
+            c[d] = draw[i] if sign > 0 else 0.0
+        else:
+            c[d] = draw[i]
+            c[s_] = sign * draw[i]
+    keep = c != 0.0
+    keys, c = keys[keep], c[keep]
+    return np.ascontiguousarray(keys), c / np.linalg.norm(c)
 
 
 def random_determinants(norb: int, na: int, nb: int, n: int, seed: int) -> np.ndarray:

@@ -487,3 +487,57 @@ def test_c2_split_total_equals_single_subset(c2):
     assert got["e_pt2"] == pytest.approx(tot["e_pt2"], abs=1e-9)
     for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
         assert got[k] == tot[k]
+
+
+@pytest.mark.parametrize("norb,n_el,nref,log2p,mode,prec,sign", [
+    (10, 3, 30, -1, 0, "fp64", 1), (10, 3, 30, 2, 0, "fp64", -1), (36, 5, 40, -1, 1, "fp64", 1),
+    (36, 5, 40, 3, 2, "fp64", 1), (40, 4, 30, -1, 2, "fp64", -1), (70, 4, 12, 1, 0, "fp64", 1),
+    (12, 4, 50, -1, 0, "fp32", 1)])
+def test_spin_flip_matches_full_sum(pt2, norb, n_el, nref, log2p, mode, prec, sign):
+    """spin_flip on a swap-symmetric reference: only alpha >= beta determinants
+    are generated and the alpha != beta terms count twice; the energy and the
+    in-reference cross term equal the oracle's full sums, the structural count
+    is unchanged, and about half the distinct determinants are visited."""
+    h, eri, _ = synth.make_integrals(norb, 6, 5200 + norb)
+    dets, c = synth.swap_symmetric_references(norb, n_el, nref, 41 + norb, sign)
+    O = oracle.Oracle(h, eri, norb, n_el, n_el)
+    keys, _ = O.numerators(dets, c)
+    e0 = float(np.concatenate([O.diag(keys), O.diag(dets)]).min()) - 1.0
+    ref, _ = O.pt2(dets, c, e0)
+    ctx = pt2.Context(h, eri, norb, n_el, n_el, log2_partitions=log2p, precision=prec, compress_keys=mode,
+                      spin_flip=True)
+    got = ctx.evaluate(dets, c, e0)
+    again = ctx.evaluate(dets, c, e0)
+    ctx.close()
+    print("spin flip", got["e_pt2"], ref["e_pt2"], got["e_pt2"] - ref["e_pt2"], got["n_unique"], ref["n_unique"],
+          flush=True)
+    tol = 1e-9 if prec == "fp64" else 1e-6
+    assert abs(got["e_pt2"] - ref["e_pt2"]) <= tol * max(1.0, abs(ref["e_pt2"]))
+    assert got["ref_cross"] == pytest.approx(ref["ref_cross"], abs=1e-11 if prec == "fp64" else 1e-7)
+    assert got["n_contrib"] == ref["n_contrib"]
+    assert ref["n_unique"] / 2 <= got["n_unique"] < ref["n_unique"] / 2 + ref["n_unique"] / 50 + 10
+    assert again["e_pt2"] == got["e_pt2"]
+
+
+def test_spin_flip_rejects_unsymmetric_input(pt2):
+    """spin_flip needs nalpha == nbeta at creation, and at evaluation a
+    reference closed under the swap with one sign relation throughout."""
+    norb, n_el = 10, 3
+    h, eri, _ = synth.make_integrals(norb, 6, 5210)
+    with pytest.raises(pt2.PT2Error):
+        pt2.Context(h, eri, norb, 3, 2, spin_flip=True)
+    ctx = pt2.Context(h, eri, norb, n_el, n_el, spin_flip=True)
+    dets, c = synth.swap_symmetric_references(norb, n_el, 20, 57)
+    with pytest.raises(pt2.PT2Error):  # a partner missing
+        ctx.evaluate(dets[1:], c[1:], -10.0)
+    c2 = c.copy()
+    a, b = synth.unpack_keys(dets, norb)
+    sw = synth.pack_keys(b, a, norb)
+    i = next(i for i in range(len(dets)) if not np.array_equal(sw[i], dets[i]))
+    j = next(j for j in range(len(dets)) if np.array_equal(dets[j], sw[i]))
+    c2[j] = -c2[i]  # one pair with the opposite sign relation
+    with pytest.raises(pt2.PT2Error):
+        ctx.evaluate(dets, c2, -10.0)
+    got = ctx.evaluate(dets, c, -10.0)  # the context is still usable
+    assert np.isfinite(got["e_pt2"])
+    ctx.close()

@@ -431,3 +431,34 @@ def test_empty_reference():
     w, h, eri, dets, c, e0 = load_c1()
     res, _ = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta).pt2(dets[:0], c[:0], e0)
     assert res["e_pt2"] == 0.0 and res["n_contrib"] == 0
+
+
+@pytest.mark.parametrize("norb,n_el,nref,sign", [(10, 3, 25, 1), (10, 3, 25, -1), (36, 3, 12, 1)])
+def test_spin_flip_identity(norb, n_el, nref, sign):
+    """Section V, spin symmetry: for a reference closed under the alpha/beta
+    swap with c(swap(D)) = +-c(D), every numerator satisfies
+    |N_swap(a)| = |N_a| and H_swap(a)swap(a) = H_aa, so the sum over the
+    determinants with alpha >= beta, the alpha != beta ones counted twice,
+    equals the full E_PT2 (the premise of the engine's spin_flip option)."""
+    h, eri, _ = synth.make_integrals(norb, 6, 5100 + norb)
+    dets, c = synth.swap_symmetric_references(norb, n_el, nref, 31 + norb, sign)
+    O = oracle.Oracle(h, eri, norb, n_el, n_el)
+    keys, nums = O.numerators(dets, c)
+    diag = O.diag(keys)
+    e0 = float(min(diag.min(), O.diag(dets).min())) - 0.5
+    a, b = synth.unpack_keys(keys, norb)
+    idx = {tuple(int(x) for x in k): i for i, k in enumerate(keys)}
+    swapped = synth.pack_keys(b, a, norb)
+    refset = {tuple(int(x) for x in k) for k in dets}
+    half = 0.0
+    for i, k in enumerate(keys):
+        j = idx[tuple(int(x) for x in swapped[i])]
+        assert abs(abs(nums[j]) - abs(nums[i])) <= 1e-14 * max(1.0, abs(nums[i]))
+        assert abs(diag[j] - diag[i]) <= 1e-12 * max(1.0, abs(diag[i]))
+        # the alpha and beta strings as numbers (orbital p is bit p)
+        ka = sum(1 << p for p in range(norb) if a[i][p])
+        kb = sum(1 << p for p in range(norb) if b[i][p])
+        if ka >= kb and tuple(int(x) for x in k) not in refset:
+            half += (1.0 if ka == kb else 2.0) * nums[i] ** 2 / (e0 - diag[i])
+    full, _ = O.pt2(dets, c, e0)
+    assert half == pytest.approx(full["e_pt2"], rel=1e-12, abs=1e-14)
