@@ -50,6 +50,44 @@ __device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t *sh4, uint32_
 }
 
 // ---------------------------------------------------------------------------
+// N consecutive keys of plane w from record r0 (0 past n), in 16-byte loads
+// when all N exist: plane bases are 256-byte aligned and r0 is a multiple of N.
+template <int W, int N>
+__device__ inline void load_keys_run(const Planes &in, int w, int64_t r0, int64_t n, uint64_t (&v)[N])
+{
+    static_assert(N % 8 == 0, "8 two-byte keys per 16-byte load");
+    if (r0 + N <= n) {
+        const int eb = w == W - 1 ? in.topb : 8;
+        const char *b = (const char *)plane_ptr<W>(in, w) + r0 * eb;
+        if (eb == 8) {
+#pragma unroll
+            for (int j = 0; j < N; j += 2) {
+                const ulonglong2 x = ((const ulonglong2 *)b)[j / 2];
+                v[j] = x.x, v[j + 1] = x.y;
+            }
+        } else if (eb == 4) {
+#pragma unroll
+            for (int j = 0; j < N; j += 4) {
+                const uint4 x = ((const uint4 *)b)[j / 4];
+                v[j] = x.x, v[j + 1] = x.y, v[j + 2] = x.z, v[j + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < N; j += 8) {
+                const uint4 x = ((const uint4 *)b)[j / 8];
+                const uint32_t u[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    v[j + 2 * q] = u[q] & 0xFFFFu, v[j + 2 * q + 1] = u[q] >> 16;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; j++)
+            v[j] = r0 + j < n ? pl_get<W>(in, w, r0 + j) : 0ull;
+    }
+}
+
 // Digit histograms of every digit position (one read of the key planes).
 template <int W>
 __global__ __launch_bounds__(256) void k_hist(Planes in, int64_t n, int ndig, unsigned long long *hist)
@@ -64,9 +102,7 @@ __global__ __launch_bounds__(256) void k_hist(Planes in, int64_t n, int ndig, un
 #pragma unroll
         for (int w = 0; w < W; w++) {
             uint64_t v[RI];
-#pragma unroll
-            for (int j = 0; j < RI; j++)
-                v[j] = r0 + j < n ? pl_get<W>(in, w, r0 + j) : 0;
+            load_keys_run<W, RI>(in, w, r0, n, v);
 #pragma unroll
             for (int dd = 0; dd < 8; dd++) {
                 const int d = w * 8 + dd;
@@ -130,9 +166,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t 
     const int word = dig >> 3, shift = (dig & 7) * 8;
     const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)tid * IT;
     uint64_t v[IT];
-#pragma unroll
-    for (int j = 0; j < IT; j++)
-        v[j] = r0 + j < n ? pl_get<W>(in, word, r0 + j) : 0ull;
+    load_keys_run<W, IT>(in, word, r0, n, v);
     uint32_t last = 0xFFFFFFFFu, cnt = 0;
 #pragma unroll
     for (int j = 0; j < IT; j++) {
