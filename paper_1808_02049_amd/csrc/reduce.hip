@@ -1531,12 +1531,29 @@ __global__ void k_numerators(Planes in, int64_t n, Planes refs, int64_t nref, ui
 
 }  // namespace
 
+// Workgroups of a single pass that take tiles: the largest whole number of
+// rounds of the workgroups that fit on the device at once, at most RED_GRID
+// (the rest of the fixed grid writes empty partials).  Equal work per
+// workgroup then leaves no partly filled last round.
+static int64_t red_workers(const void *kernel, size_t dyn)
+{
+    int dev = 0, cus = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, RED_THREADS, dyn) != hipSuccess || nb <= 0 ||
+        cus <= 0) {
+        (void)hipGetLastError();
+        return RED_GRID;
+    }
+    const int64_t resident = (int64_t)nb * cus;
+    return resident >= RED_GRID ? RED_GRID : (RED_GRID / resident) * resident;
+}
+
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n, const Planes &refs,
                          int64_t nref, double e0, int64_t *range, int search, Partial *partials, Flags *flags,
                          hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
-    const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
     const int nso = 2 * s.norb;
     const size_t tri_bytes = (size_t)nso * (nso + 1) / 2 * 8;
     int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
@@ -1564,9 +1581,13 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
         }
     }
     dim3 g(RED_GRID), b(RED_THREADS);
-#define RD(WW, PB, WBB, RKK)                                                                                     \
-    hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per, lds_table, \
-                       q_bytes, range, search, partials, flags)
+#define RD(WW, PB, WBB, RKK)                                                                                   \
+    do {                                                                                                       \
+        const int64_t ge = red_workers((const void *)&k_reduce<WW, PB, WBB, RKK>, dyn);                         \
+        const int64_t per = (ntiles + ge - 1) / ge;                                                            \
+        hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per,        \
+                           lds_table, q_bytes, range, search, partials, flags);                                 \
+    } while (0)
 #define RD2(WW, WBB, RKK)      \
     do {                       \
         if (fp32)              \
@@ -1734,10 +1755,11 @@ hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, i
                               int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
-    const int64_t per = (ntiles + RED_GRID - 1) / RED_GRID;
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RH(WB, PB)                                                                                                 \
     do {                                                                                                           \
+        const int64_t ge = red_workers((const void *)&k_reduce_hash<WB, PB>, 0);                                    \
+        const int64_t per = (ntiles + ge - 1) / ge;                                                                \
         hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per,     \
                            search, partials, coll, flags);                                                         \
         hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per, \
