@@ -296,7 +296,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
-              "(subsets of the hash split are independent, see DESIGN.md for sharding)",
+              "(the subsets of the hash split are independent units of work)",
               file=sys.stderr)
         sys.exit(2)
 

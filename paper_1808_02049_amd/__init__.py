@@ -7,8 +7,7 @@ streams; arrays may be numpy (host) or torch CUDA tensors (device-resident
 inputs go through ``pt2_evaluate_device``).
 
 There is no CPU fallback: importing this package fails if the shared
-library has not been built (``python -m paper_1808_02049_amd.build`` or
-``__graft_entry__.build()``).
+library has not been built (``python paper_1808_02049_amd/build.py``).
 """
 from __future__ import annotations
 
