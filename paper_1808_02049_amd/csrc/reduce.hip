@@ -416,11 +416,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ int s_cflag;
     __shared__ uint64_t s_anc[WB];
     __shared__ double s_er[RED_THREADS / 64];
+    __shared__ Partial s_wp[RED_THREADS / 64];
 
     const int nso = 2 * s.norb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint64_t *q_key = (uint64_t *)dyn;                       // [W][RED_Q]
-    double *q_num = (double *)(dyn + (size_t)W * RED_Q * 8); // [RED_Q]
+    // queue of owned segment ends: the numerator and the record's index in
+    // its tile (the key is read back from the tile, which is in the caches)
+    double *q_num = (double *)dyn;                            // [RED_Q]
+    uint32_t *q_idx = (uint32_t *)(dyn + (size_t)RED_Q * 8);  // [RED_Q]
     // g vector of the tile's anchor (nso entries) after the queue region
     double *s_g = (double *)(dyn + q_bytes);
     const double *Tp = s.T;
@@ -641,9 +644,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             const int64_t idx = r0 + j;
             const bool owned = idx < tend && (hh[j] || cf);
             if (owned && tl[j]) {
-#pragma unroll
-                for (int w = 0; w < W; w++)
-                    q_key[w * RED_Q + slot] = k[j][w];
+                q_idx[slot] = (uint32_t)(idx - base);
                 q_num[slot] = hh[j] ? run[j] : cv + run[j];
                 slot++;
             }
@@ -678,9 +679,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 pos += 64;
             }
             if (lane == 0) {
-#pragma unroll
-                for (int w = 0; w < W; w++)
-                    q_key[w * RED_Q + qtot] = ck[w];
+                q_idx[qtot] = (uint32_t)(tend - 1 - base);  // a record of that segment
                 q_num[qtot] = s_cv + total;
             }
         }
@@ -695,28 +694,50 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             an.e += s_er[w];
         for (int e = tid; e < qn; e += RED_THREADS) {
             uint64_t kk[W];
-#pragma unroll
-            for (int w = 0; w < W; w++)
-                kk[w] = q_key[w * RED_Q + e];
+            load_key<W>(in, base + q_idx[e], kk);
             process_segment<W, WB, RK>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom, search != 0);
         }
         __syncthreads();
     }
 
-    // block reduction of the accumulators (fixed tree); the queue region is
-    // free now and holds the partials
-    Partial *s_p = (Partial *)dyn;
+    // block reduction of the accumulators in a fixed order: a shuffle tree
+    // within each wavefront, then the wavefronts in order
+    if (a.singular)
+        atomicOr(&flags->err, ERR_SINGULAR);
     Partial me;
     me.e_sum = a.e_sum, me.e_comp = a.e_comp, me.ref_cross = a.ref_cross, me.min_abs_denom = a.min_abs;
     me.n_unique = a.n_unique, me.n_external = a.n_ext, me.n_hit = a.n_hit, me.n_nonneg = a.n_nonneg;
     me.key_xor = a.kx, me.key_sum = a.ks;
-    s_p[tid] = me;
-    if (a.singular)
-        atomicOr(&flags->err, ERR_SINGULAR);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        Partial y;
+        y.e_sum = __shfl_down(me.e_sum, o);
+        y.e_comp = __shfl_down(me.e_comp, o);
+        y.ref_cross = __shfl_down(me.ref_cross, o);
+        y.min_abs_denom = __shfl_down(me.min_abs_denom, o);
+        y.n_unique = __shfl_down(me.n_unique, o);
+        y.n_external = __shfl_down(me.n_external, o);
+        y.n_hit = __shfl_down(me.n_hit, o);
+        y.n_nonneg = __shfl_down(me.n_nonneg, o);
+        y.key_xor = __shfl_down(me.key_xor, o);
+        y.key_sum = __shfl_down(me.key_sum, o);
+        if (lane < o) {
+            double sum = me.e_sum, comp = me.e_comp + y.e_comp;
+            neumaier(sum, comp, y.e_sum);
+            me.e_sum = sum, me.e_comp = comp;
+            me.ref_cross += y.ref_cross;
+            me.min_abs_denom = y.min_abs_denom < me.min_abs_denom ? y.min_abs_denom : me.min_abs_denom;
+            me.n_unique += y.n_unique, me.n_external += y.n_external, me.n_hit += y.n_hit;
+            me.n_nonneg += y.n_nonneg, me.key_xor ^= y.key_xor, me.key_sum += y.key_sum;
+        }
+    }
+    if (lane == 0)
+        s_wp[wave] = me;
     __syncthreads();
-    for (int o = RED_THREADS / 2; o >= 1; o >>= 1) {
-        if (tid < o) {
-            Partial x2 = s_p[tid], y = s_p[tid + o];
+    if (tid == 0) {
+        Partial x2 = s_wp[0];
+        for (int w = 1; w < RED_THREADS / 64; w++) {
+            const Partial y = s_wp[w];
             double sum = x2.e_sum, comp = x2.e_comp + y.e_comp;
             neumaier(sum, comp, y.e_sum);
             x2.e_sum = sum, x2.e_comp = comp;
@@ -724,12 +745,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
             x2.min_abs_denom = y.min_abs_denom < x2.min_abs_denom ? y.min_abs_denom : x2.min_abs_denom;
             x2.n_unique += y.n_unique, x2.n_external += y.n_external, x2.n_hit += y.n_hit;
             x2.n_nonneg += y.n_nonneg, x2.key_xor ^= y.key_xor, x2.key_sum += y.key_sum;
-            s_p[tid] = x2;
         }
-        __syncthreads();
+        partials[blockIdx.x] = x2;
     }
-    if (tid == 0)
-        partials[blockIdx.x] = s_p[0];
 }
 
 // sum over the reference of c_i^2 (E0 - H_ii), per block (subtraction form
@@ -1558,9 +1576,7 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     const size_t tri_bytes = (size_t)nso * (nso + 1) / 2 * 8;
     int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
     const bool rk = s.kc.on != 0;
-    size_t q_bytes = (size_t)(kw + 1) * RED_Q * 8;
-    if (q_bytes < sizeof(Partial) * RED_THREADS)
-        q_bytes = sizeof(Partial) * RED_THREADS;
+    size_t q_bytes = (size_t)RED_Q * (8 + 4);
     q_bytes = (q_bytes + 15) & ~(size_t)15;
     const size_t binom_bytes = rk ? (size_t)(s.norb + 1) * s.kc.stride * 8 : 0;
     const size_t fixed = q_bytes + (size_t)nso * 8 + binom_bytes;
