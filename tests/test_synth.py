@@ -136,3 +136,18 @@ def test_stored_serving_e0_regenerates():
         s = stored[r.index]
         assert abs(e0 - s["e0"]) <= 1e-12 * abs(s["e0"])
         assert float.fromhex(s["e0_hex"]) == s["e0"]
+
+
+@pytest.mark.parametrize("norb,n_el,sign", [(10, 3, 1), (10, 3, -1), (40, 5, 1), (70, 4, -1)])
+def test_swap_symmetric_references_are_closed(norb, n_el, sign):
+    """Every determinant's alpha/beta swap is in the set, with coefficient
+    sign * c, and the coefficients are normalised."""
+    dets, c = synth.swap_symmetric_references(norb, n_el, 25, 3 + norb, sign)
+    a, b = synth.unpack_keys(dets, norb)
+    assert (a.sum(axis=1) == n_el).all() and (b.sum(axis=1) == n_el).all()
+    index = {tuple(int(x) for x in k): i for i, k in enumerate(dets)}
+    assert len(index) == len(dets)
+    for i, k in enumerate(synth.pack_keys(b, a, norb)):
+        j = index[tuple(int(x) for x in k)]
+        assert c[j] == sign * c[i] or (i == j and sign > 0)
+    assert np.linalg.norm(c) == pytest.approx(1.0, abs=1e-15)
