@@ -133,8 +133,13 @@ typedef struct {
                                       subtraction the counts and checksums cover
                                       every distinct determinant                      */
     int hash_bits;                 /* hash records: bits of the hash kept as the sort
-                                      key, 0 = 64.  Fewer bits only make collisions
-                                      common, to test their handling                 */
+                                      key.  0 (default): per evaluation, the fewest
+                                      of 32, 40, 48, 56, 64 for which the expected
+                                      number of colliding pairs in the largest
+                                      subset, N^2 / 2^(bits+1), is 256 or fewer
+                                      (collided runs are resolved exactly).  1-64:
+                                      exactly that many (few bits make collisions
+                                      common, to test their handling)               */
     int spin_flip;                 /* 1: use the alpha/beta swap symmetry of an S_z = 0
                                       reference (Section V, spin symmetry): only
                                       determinants whose alpha string is not below
@@ -178,7 +183,8 @@ typedef struct {
                                  the scatter, the digit's key plane read once by
                                  the count)                                          */
     uint32_t key_bits;        /* bits of the sort key of a stored term (2 norb for
-                                 bitstrings, fewer for rank keys)                    */
+                                 bitstrings, fewer for rank keys, the hash bits
+                                 kept for hash records)                              */
 } pt2_result;
 
 /* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */

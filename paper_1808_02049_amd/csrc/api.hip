@@ -742,12 +742,6 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             (rc = buf_ensure(ws.A, ws.refX, (size_t)J.n * (c->W == 3 ? 4 : c->W) * 8)))
             return rc;
         HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
-        Planes h0 = planes_of(ws.refH0, 1, J.n, 8, 8), h1 = planes_of(ws.refH1, 1, J.n, 8, 8);
-        HIPCHK(launch_refs_hash(sys, refs, J.n, h0, st));
-        Timing none;
-        if ((rc = radix_sort(ws, 1, 8, h0, h1, J.n, 64, st, none, nullptr, nullptr)))
-            return rc;
-        refs_hash = h0;
         HIPCHK(launch_parent_g(sys, refs, J.n, (double *)ws.hp.p, (double *)ws.gv.p, st));
     }
     // subtraction form: sum_i c_i^2 (E0 - H_ii), removed from the total below
@@ -769,11 +763,35 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     uint64_t mx = 0;
     for (auto s : P.sizes)
         mx = std::max(mx, s);
+    uint32_t key_bits = (uint32_t)RL.bits;
+    if (RL.hash) {
+        // sort on as few hash bits as keep the expected number of colliding
+        // pairs in the largest subset, N^2 / 2^(b+1), at 256 or fewer: each
+        // byte less is a digit pass less, and collided runs are resolved
+        // exactly (a few workgroups revisited)
+        int b = 64;
+        if (c->opt.hash_bits == 0) {
+            b = 32;
+            while (b < 64 && (double)mx * (double)mx / std::ldexp(1.0, b + 1) > 256.0)
+                b += 8;
+            sys.kc.hash_mask = b >= 64 ? ~0ull : ((1ull << b) - 1);
+        } else {
+            b = c->opt.hash_bits >= 64 ? 64 : c->opt.hash_bits;
+        }
+        key_bits = (uint32_t)b;
+        // the references' hashes (same bits), sorted, with their indices
+        Planes h0 = planes_of(ws.refH0, 1, J.n, 8, 8), h1 = planes_of(ws.refH1, 1, J.n, 8, 8);
+        HIPCHK(launch_refs_hash(sys, refs, J.n, h0, st));
+        Timing none;
+        if ((rc = radix_sort(ws, 1, 8, h0, h1, J.n, 64, st, none, nullptr, nullptr)))
+            return rc;
+        refs_hash = h0;
+    }
     if ((rc = ensure_records(ws, W, pb, RL.topb, (int64_t)std::max<uint64_t>(mx, 1))))
         return rc;
     const double rbytes = record_bytes(W, pb, RL.topb);
     res.record_bytes = (uint32_t)rbytes;
-    res.key_bits = (uint32_t)RL.bits;
+    res.key_bits = key_bits;
     Small *ds = ws.dsmall();
     std::vector<Partial> part_res(P.parts.size());
     for (size_t q = 0; q < P.parts.size(); q++) {

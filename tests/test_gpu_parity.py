@@ -337,7 +337,11 @@ def test_hash_records_match(pt2, norb, na, nb, nref, log2p, prec, hash_bits):
         ctx.close()
     print("key bits", res[0]["key_bits"], "->", res[2]["key_bits"], "passes", res[0]["n_sort_passes"], "->",
           res[2]["n_sort_passes"], flush=True)
-    assert res[2]["key_bits"] == 64
+    # hash bits: as given, or as few as keep the expected collisions small
+    if hash_bits:
+        assert res[2]["key_bits"] == min(hash_bits, 64)
+    else:
+        assert res[2]["key_bits"] in (32, 40, 48, 56, 64)
     for k in ("n_contrib", "n_after_cutoff", "n_unique", "n_external", "n_in_ref_hit", "n_nonneg_denom",
               "key_xor", "key_sum"):
         assert res[0][k] == res[2][k], (k, res[0][k], res[2][k])
