@@ -867,7 +867,9 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
             e = decode(g, L, D, k);
         emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
     }
-    // doubles: alpha-alpha, beta-beta, alpha-beta
+    // doubles: alpha-alpha, beta-beta, alpha-beta; without a cutoff or the
+    // spin flip every candidate the bucket walk visits is kept
+    const bool direct = cutoff <= 0.0 && !s.z2;
     for (int kind = 2; kind <= 4; kind++) {
         const int no = n_outer(L, kind);
         if (no == 0 || n_inner(L, kind) == 0)
@@ -899,8 +901,28 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
                 const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
                 e = make_exc(g, L, kind, lo, q);
             }
-            emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
+            if (direct) {
+                // every walked candidate is kept: its slot is its walk index
+                if (have) {
+                    uint64_t key[W], z;
+                    exc_key<W>(g, s.norb, e, key, z);
+                    if (part_of(z, log2p) != part)
+                        bad = true;  // bucketing is inconsistent
+                    const uint64_t p = pos + f;
+                    if (p < end) {
+                        store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
+                        store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
+                    } else {
+                        atomicOr(&flags->err, ERR_OVERFLOW);
+                    }
+                }
+            } else {
+                emit_step<W, PM>(g, s, L, have, e, false, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad,
+                                 det);
+            }
         }
+        if (direct)
+            pos += T;
         __syncthreads();
     }
     if (bad || (tid == 0 && pos != end))
