@@ -87,6 +87,12 @@ def test_bad_options_rejected():
         pt2.Context(h, eri, 4, 2, 2, log2_partitions=13)
     with pytest.raises(pt2.PT2Error):
         pt2.Context(h, eri, 4, 2, 2, compress_keys=2)
+    with pytest.raises(pt2.PT2Error, match="hash_bits"):
+        pt2.Context(h, eri, 4, 2, 2, hash_bits=65)
+    with pytest.raises(pt2.PT2Error, match="hash_bits"):
+        pt2.Context(h, eri, 4, 2, 2, hash_bits=-1)
+    with pytest.raises(pt2.PT2Error, match="nalpha == nbeta"):
+        pt2.Context(h, eri, 4, 2, 1, spin_flip=True)
     o = pt2.default_options()
     assert o.exclusion == 0
     o.exclusion = 2
@@ -103,6 +109,13 @@ def test_bad_options_rejected():
     rc = pt2._lib.pt2_create(hh.ctypes.data_as(pt2._f64p), ee.ctypes.data_as(pt2._f64p), 4, 2, 2,
                              pt2.C.byref(o), pt2.C.byref(ctx))
     assert rc == pt2.PT2_E_INVALID
+    o = pt2.default_options()
+    o.spin_flip = 2
+    ctx = pt2._CTX()
+    rc = pt2._lib.pt2_create(hh.ctypes.data_as(pt2._f64p), ee.ctypes.data_as(pt2._f64p), 4, 2, 2,
+                             pt2.C.byref(o), pt2.C.byref(ctx))
+    assert rc == pt2.PT2_E_INVALID
+    assert b"spin_flip" in pt2._lib.pt2_last_error()
 
 
 def test_evaluate_null_context_rejected():
