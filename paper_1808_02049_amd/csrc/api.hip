@@ -171,7 +171,7 @@ struct Workspace {
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
-    Buf counts, csum, coff, offs;  // per-tile digit counts and scanned offsets
+    Buf counts, csum, coff, offs;  // per-tile digit counts (u16), chunk offsets (u64), in-chunk offsets (u32)
     int64_t scan_tiles = 0;
     Buf small;
     Buf cnt, off, tot, parts_dev;
@@ -330,8 +330,8 @@ int ensure_scan(Workspace &ws, int64_t n)
         ws.scan_tiles = 0;
         const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
         int rc;
-        if ((rc = buf_alloc(ws.A, ws.counts, (size_t)tiles * 256 * 4)) ||
-            (rc = buf_alloc(ws.A, ws.offs, (size_t)tiles * 256 * 8)) ||
+        if ((rc = buf_alloc(ws.A, ws.counts, (size_t)tiles * 256 * 2)) ||
+            (rc = buf_alloc(ws.A, ws.offs, (size_t)tiles * 256 * 4)) ||
             (rc = buf_alloc(ws.A, ws.csum, (size_t)chunks * 256 * 8)) ||
             (rc = buf_alloc(ws.A, ws.coff, (size_t)chunks * 256 * 8)))
             return rc;
@@ -346,8 +346,8 @@ size_t slice_bytes(int W, int pb, int topb, int64_t cap)
 {
     const int64_t tiles = std::max<int64_t>(1, (cap + SORT_TILE - 1) / SORT_TILE);
     const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    return 2 * planes_bytes(W, cap, pb, topb) + align256((size_t)tiles * 256 * 4) +
-           align256((size_t)tiles * 256 * 8) + 2 * align256((size_t)chunks * 256 * 8);
+    return 2 * planes_bytes(W, cap, pb, topb) + align256((size_t)tiles * 256 * 2) +
+           align256((size_t)tiles * 256 * 4) + 2 * align256((size_t)chunks * 256 * 8);
 }
 
 // Point a workspace's record and scan buffers into a slice of slice_bytes().
@@ -362,8 +362,8 @@ void carve_slice(Workspace &ws, char *p, int W, int pb, int topb, int64_t cap)
     };
     take(ws.recA, planes_bytes(W, cap, pb, topb));
     take(ws.recB, planes_bytes(W, cap, pb, topb));
-    take(ws.counts, align256((size_t)tiles * 256 * 4));
-    take(ws.offs, align256((size_t)tiles * 256 * 8));
+    take(ws.counts, align256((size_t)tiles * 256 * 2));
+    take(ws.offs, align256((size_t)tiles * 256 * 4));
     take(ws.csum, align256((size_t)chunks * 256 * 8));
     take(ws.coff, align256((size_t)chunks * 256 * 8));
     ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb, ws.rec_topb = topb;
@@ -408,8 +408,8 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
             return rc;
         if (tm.on && !(mid = ws.event()))
             return fail(PT2_E_DEVICE, "hipEventCreate failed");
-        HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint32_t *)ws.counts.p,
-                                 (uint64_t *)ws.csum.p, (uint64_t *)ws.coff.p, (uint64_t *)ws.offs.p, &ds->flags,
+        HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint16_t *)ws.counts.p,
+                                 (uint64_t *)ws.csum.p, (uint64_t *)ws.coff.p, (uint32_t *)ws.offs.p, &ds->flags,
                                  st, mid, items));
         if (tm.on) {
             if ((rc = timed_end(ws, tm, st, mid, 1)))
@@ -490,11 +490,11 @@ int ensure_records(Workspace &ws, int W, int pb, int topb, int64_t cap)
 }
 
 // projected device bytes for one subset of n records
-// (two record buffers, plus per-tile counts and offsets: 12 B per digit value
+// (two record buffers, plus per-tile counts and offsets: 6 B per digit value
 // per tile of SORT_TILE records)
 double subset_bytes(int W, int pb, int topb, double n)
 {
-    return n * (2.0 * record_bytes(W, pb, topb) + 12.0 * 256.0 / SORT_TILE) + 65536.0;
+    return n * (2.0 * record_bytes(W, pb, topb) + 6.0 * 256.0 / SORT_TILE) + 65536.0;
 }
 
 struct Plan {

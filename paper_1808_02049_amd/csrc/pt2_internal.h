@@ -376,12 +376,13 @@ hipError_t launch_hist(int W, const Planes &in, int64_t n, int ndig, uint64_t *h
 // bucket[d*256 + v] = exclusive scan of hist[d][*].
 hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hipStream_t st);
 // One stable LSD digit pass: per-tile counts, offset scan, rank and scatter
-// (in -> out by digit `dig`).  counts: ntiles*256 u32; csum, coff:
-// nchunks*256 u64; offs: ntiles*256 u64.  `mid` (optional) is recorded between
-// the counting/scan kernels and the scatter.
+// (in -> out by digit `dig`).  counts: ntiles*256 u16; csum, coff:
+// nchunks*256 u64; rel: ntiles*256 u32 (offset within the chunk of
+// SCAN_CHUNK tiles).  `mid` (optional) is recorded between the counting/scan
+// kernels and the scatter.
 hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
-                             const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
-                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid,
+                             const uint64_t *bucket, uint16_t *counts, uint64_t *csum, uint64_t *coff,
+                             uint32_t *rel, Flags *flags, hipStream_t st, hipEvent_t mid,
                              int items = SORT_ITEMS);
 hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t st);

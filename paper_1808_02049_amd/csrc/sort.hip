@@ -7,7 +7,10 @@
 //   1. k_tile_count: every tile of SORT_TILE records counts its digits (one
 //      read of the plane holding the digit, LDS histograms per wavefront);
 //   2. k_chunk_sum / k_chunk_scan / k_tile_offsets: exclusive scan of the
-//      counts over tiles, per digit value, added to the digit's bucket start;
+//      counts over tiles, per digit value: the offset of every chunk of
+//      SCAN_CHUNK tiles from the digit's bucket start (u64), and of every tile
+//      within its chunk (u32; counts are u16, a tile holding at most 4096
+//      records), so the per-tile arrays move 6 B per digit value, not 12;
 //   3. k_scatter: every tile ranks its records by digit with wavefront
 //      ballots (stable), stages each plane through LDS in digit order and
 //      writes it out in runs of consecutive addresses.
@@ -155,9 +158,10 @@ __global__ __launch_bounds__(256) void k_hist_scan(const unsigned long long *his
 // thread reads SORT_ITEMS consecutive records, merges runs of equal digits,
 // and adds them to its wavefront's LDS histogram.
 template <int W, int IT>
-__global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t n, int dig, uint32_t *counts)
+__global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t n, int dig, uint16_t *counts)
 {
     constexpr int TILE = SORT_THREADS * IT;
+    static_assert(TILE <= 65535, "tile counts are u16");
     __shared__ uint32_t h[SORT_THREADS / 64][256];
     const int tid = threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < (SORT_THREADS / 64) * 256; i += SORT_THREADS)
@@ -189,11 +193,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t 
 #pragma unroll
     for (int w = 0; w < SORT_THREADS / 64; w++)
         t += h[w][tid];
-    counts[(int64_t)blockIdx.x * 256 + tid] = t;
+    counts[(int64_t)blockIdx.x * 256 + tid] = (uint16_t)t;
 }
 
 // Step 2a: per chunk of SCAN_CHUNK tiles, the sum of each digit's counts.
-__global__ __launch_bounds__(256) void k_chunk_sum(const uint32_t *counts, int64_t ntiles, uint64_t *csum)
+__global__ __launch_bounds__(256) void k_chunk_sum(const uint16_t *counts, int64_t ntiles, uint64_t *csum)
 {
     const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
     const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
@@ -228,15 +232,17 @@ __global__ __launch_bounds__(256) void k_chunk_scan(const uint64_t *csum, int64_
     }
 }
 
-// Step 2c: output offset of each tile's first record of each digit.
-__global__ __launch_bounds__(256) void k_tile_offsets(const uint32_t *counts, int64_t ntiles, const uint64_t *coff,
-                                                      uint64_t *offs)
+static_assert((int64_t)SCAN_CHUNK * SORT_THREADS * SORT_ITEMS_WIDE <= 0xFFFFFFFFll, "in-chunk offsets are u32");
+
+// Step 2c: offset of each tile's first record of each digit from its chunk's
+// (the record goes to coff[chunk][digit] + rel[tile][digit]).
+__global__ __launch_bounds__(256) void k_tile_offsets(const uint16_t *counts, int64_t ntiles, uint32_t *rel)
 {
     const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
     const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
-    uint64_t run = coff[(int64_t)blockIdx.x * 256 + threadIdx.x];
+    uint32_t run = 0;
     for (int64_t t = t0; t < t1; t++) {
-        offs[t * 256 + threadIdx.x] = run;
+        rel[t * 256 + threadIdx.x] = run;
         run += counts[t * 256 + threadIdx.x];
     }
 }
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const uint32_t *counts, in
 // Step 3: rank and scatter one tile.
 template <int W, int PB, int IT>
 __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out, int64_t n, int dig,
-                                                          const uint64_t *offs, Flags *flags)
+                                                          const uint64_t *coff, const uint32_t *rel, Flags *flags)
 {
     __shared__ uint32_t s_wc[4][256];
     __shared__ uint32_t s_tstart[256];
@@ -270,7 +276,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
 #endif
     const int64_t base = tile * TILE;
     const int word = dig >> 3, shift = (dig & 7) * 8;
-    const uint64_t my_off = offs[tile * 256 + tid];
+    const uint64_t my_off = coff[(tile / SCAN_CHUNK) * 256 + tid] + rel[tile * 256 + tid];
 
     uint64_t kw[IT];
     uint32_t rank[IT];
@@ -497,8 +503,8 @@ hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hi
 }
 
 hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,
-                             const uint64_t *bucket, uint32_t *counts, uint64_t *csum, uint64_t *coff,
-                             uint64_t *offs, Flags *flags, hipStream_t st, hipEvent_t mid, int items)
+                             const uint64_t *bucket, uint16_t *counts, uint64_t *csum, uint64_t *coff,
+                             uint32_t *rel, Flags *flags, hipStream_t st, hipEvent_t mid, int items)
 {
     if (n <= 0)
         return hipSuccess;
@@ -525,15 +531,15 @@ hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Plane
 #undef TC
     hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, csum);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, csum, nchunks, bucket, coff);
-    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, coff, offs);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, rel);
     if (mid)
         (void)hipEventRecord(mid, st);
 #define SC(WW, PB)                                                                                            \
     do {                                                                                                      \
         if (items == SORT_ITEMS)                                                                              \
-            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS>), g, b, 0, st, in, out, n, dig, offs, flags);      \
+            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS>), g, b, 0, st, in, out, n, dig, coff, rel, flags);      \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS_WIDE>), g, b, 0, st, in, out, n, dig, offs, flags); \
+            hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS_WIDE>), g, b, 0, st, in, out, n, dig, coff, rel, flags); \
     } while (0)
     switch (W * 2 + (pay_bytes == 8 ? 1 : 0)) {
     case 2: SC(1, 4); break;
