@@ -451,6 +451,31 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     for (int64_t tile = t_begin; tile < t_end; tile++) {
         const int64_t base = tile * RED_TILE;
         const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
+        // this thread's records and their neighbours' keys, requested first so
+        // that the loads overlap the anchor set-up below
+        const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
+        uint64_t k[RED_ITEMS][W];
+        double p[RED_ITEMS];
+#pragma unroll
+        for (int j = 0; j < RED_ITEMS; j++) {
+            const int64_t idx = r0 + j;
+            if (idx < tend) {
+                load_key<W>(in, idx, k[j]);
+                p[j] = load_pay<PB>(in, idx);
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; w++)
+                    k[j][w] = 0;
+                p[j] = 0.0;
+            }
+        }
+        uint64_t kp[W], kn[W];
+        const bool has_prev = r0 > 0 && r0 < tend;
+        const bool has_next = r0 + RED_ITEMS < n;
+        if (has_prev)
+            load_key<W>(in, r0 - 1, kp);
+        if (has_next)
+            load_key<W>(in, r0 + RED_ITEMS, kn);
         if (tid == 0) {
             uint64_t kf[W];
             load_key<W>(in, base, kf);
@@ -516,29 +541,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
                 s_rc[i] = ((const double *)refs.pay)[rs.lo + i];
             }
 
-        const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
-        uint64_t k[RED_ITEMS][W];
-        double p[RED_ITEMS];
-#pragma unroll
-        for (int j = 0; j < RED_ITEMS; j++) {
-            const int64_t idx = r0 + j;
-            if (idx < tend) {
-                load_key<W>(in, idx, k[j]);
-                p[j] = load_pay<PB>(in, idx);
-            } else {
-#pragma unroll
-                for (int w = 0; w < W; w++)
-                    k[j][w] = 0;
-                p[j] = 0.0;
-            }
-        }
-        uint64_t kp[W], kn[W];
-        const bool has_prev = r0 > 0 && r0 < tend;
-        const bool has_next = r0 + RED_ITEMS < n;
-        if (has_prev)
-            load_key<W>(in, r0 - 1, kp);
-        if (has_next)
-            load_key<W>(in, r0 + RED_ITEMS, kn);
 
         double run[RED_ITEMS];
         bool hh[RED_ITEMS], tl[RED_ITEMS];

@@ -91,6 +91,44 @@ __device__ inline void load_keys_run(const Planes &in, int w, int64_t r0, int64_
     }
 }
 
+// Digit counts of N consecutive keys into an LDS histogram.  Most lanes of a
+// wavefront usually see the same digit value, and LDS atomics from many lanes
+// on one address serialise.  So the keys equal to a wavefront-wide reference
+// value (the digit of the first active lane's first key) are counted in a
+// register and added by one lane; runs of other values are merged per thread
+// and added one atomic per run.  All lanes of the wavefront must call this.
+// (The all-digits histogram pass keeps plain run merging: there the wavefront
+// sums of ten digit positions cost more than the conflicts they remove.)
+template <int N>
+__device__ inline void count_digits(const uint64_t (&v)[N], int shift, int64_t r0, int64_t n, uint32_t *h)
+{
+    const uint32_t ref = __builtin_amdgcn_readfirstlane((uint32_t)(v[0] >> shift) & 255u);
+    uint32_t nref = 0, last = 0xFFFFFFFFu, cnt = 0;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (r0 + j < n) {
+            const uint32_t d = (uint32_t)(v[j] >> shift) & 255u;
+            if (d == ref) {
+                nref++;
+            } else if (d == last) {
+                cnt++;
+            } else {
+                if (cnt)
+                    atomicAdd(&h[last], cnt);
+                last = d;
+                cnt = 1;
+            }
+        }
+    }
+    if (cnt)
+        atomicAdd(&h[last], cnt);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        nref += __shfl_xor(nref, o);
+    if ((threadIdx.x & 63) == 0 && nref)
+        atomicAdd(&h[ref], nref);
+}
+
 // Digit histograms of every digit position (one read of the key planes).
 template <int W>
 __global__ __launch_bounds__(256) void k_hist(Planes in, int64_t n, int ndig, unsigned long long *hist)
@@ -155,8 +193,8 @@ __global__ __launch_bounds__(256) void k_hist_scan(const unsigned long long *his
 
 // ---------------------------------------------------------------------------
 // Step 1: digit counts of every tile (counts[tile * 256 + digit]).  Each
-// thread reads SORT_ITEMS consecutive records, merges runs of equal digits,
-// and adds them to its wavefront's LDS histogram.
+// thread reads SORT_ITEMS consecutive records and counts their digits into its
+// wavefront's LDS histogram.
 template <int W, int IT>
 __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t n, int dig, uint16_t *counts)
 {
@@ -171,23 +209,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t 
     const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)tid * IT;
     uint64_t v[IT];
     load_keys_run<W, IT>(in, word, r0, n, v);
-    uint32_t last = 0xFFFFFFFFu, cnt = 0;
-#pragma unroll
-    for (int j = 0; j < IT; j++) {
-        if (r0 + j < n) {
-            const uint32_t d = (uint32_t)(v[j] >> shift) & 255u;
-            if (d == last) {
-                cnt++;
-            } else {
-                if (cnt)
-                    atomicAdd(&h[wave][last], cnt);
-                last = d;
-                cnt = 1;
-            }
-        }
-    }
-    if (cnt)
-        atomicAdd(&h[wave][last], cnt);
+    count_digits<IT>(v, shift, r0, n, h[wave]);
     __syncthreads();
     uint32_t t = 0;
 #pragma unroll
