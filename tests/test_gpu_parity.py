@@ -420,7 +420,9 @@ def test_invalid_references_rejected(pt2, c1):
 @pytest.mark.parametrize("W,bits,n,pb,skew", [
     (1, 24, 1000, 8, False), (1, 64, 70_001, 4, False), (2, 80, 123_457, 8, True),
     (3, 152, 50_000, 8, False), (4, 200, 9_000, 4, True), (2, 72, 4096, 8, False),
-    (2, 80, 4097, 8, True), (1, 8, 300_000, 8, True)])
+    (2, 80, 4097, 8, True), (1, 8, 300_000, 8, True),
+    # several chunks of 256 tiles: offsets within a chunk and across chunks
+    (1, 16, 1_200_001, 8, True), (2, 80, 1_100_000, 4, True)])
 def test_sort_records_matches_stable_sort(pt2, W, bits, n, pb, skew):
     rng = np.random.default_rng(W * 1000 + n)
     keys = rng.integers(0, 2 ** 63, size=(n, W), dtype=np.uint64) * np.uint64(2) + \
@@ -437,6 +439,22 @@ def test_sort_records_matches_stable_sort(pt2, W, bits, n, pb, skew):
     pay = np.arange(n, dtype=np.float64 if pb == 8 else np.uint32)
     sk, sp = pt2.sort_records(keys.copy(), pay.copy(), bits)
     idx = np.lexsort(tuple(keys[:, w] for w in range(W)))
+    assert np.array_equal(sk, keys[idx])
+    assert np.array_equal(sp, pay[idx])
+
+
+def test_sort_records_near_constant_digits(pt2):
+    """Digits that take one value in all but a few records: most tiles hold a
+    whole tile of one digit value, and that value's offsets within a chunk run
+    up to the chunk's full length, over three chunks of tiles."""
+    rng = np.random.default_rng(77)
+    n = 1_500_000
+    keys = np.full((n, 1), 0x5A5A, dtype=np.uint64)
+    odd = rng.choice(n, size=12, replace=False)
+    keys[odd, 0] = rng.integers(0, 1 << 16, size=12, dtype=np.uint64)
+    pay = np.arange(n, dtype=np.float64)
+    sk, sp = pt2.sort_records(keys.copy(), pay.copy(), 16)
+    idx = np.argsort(keys[:, 0], kind="stable")
     assert np.array_equal(sk, keys[idx])
     assert np.array_equal(sp, pay[idx])
 
