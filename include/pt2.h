@@ -152,6 +152,16 @@ typedef struct {
                                       and checksums then cover the generated half;
                                       n_contrib stays the structural count of all
                                       terms.  Default 0                              */
+    int alpha_reuse;               /* 1 (default): when every term of every
+                                      reference is generated (one subset, no cutoff,
+                                      no spin flip) with bitstring keys, the
+                                      alpha-alpha doubles and their matrix elements
+                                      are computed once per group of up to 32
+                                      references sharing an alpha string and written
+                                      for each of them (Section V, data reuse for
+                                      unique alpha strings); the records, and so
+                                      every result, are identical.  0: each
+                                      reference computes its own                   */
 } pt2_options;
 
 typedef struct {
@@ -185,6 +195,9 @@ typedef struct {
     uint32_t key_bits;        /* bits of the sort key of a stored term (2 norb for
                                  bitstrings, fewer for rank keys, the hash bits
                                  kept for hash records)                              */
+    uint64_t n_alpha_groups;  /* groups of references sharing an alpha string whose
+                                 alpha-alpha doubles were generated once for the
+                                 group (alpha_reuse); 0 when not used              */
 } pt2_result;
 
 /* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */

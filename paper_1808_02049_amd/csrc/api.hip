@@ -175,6 +175,9 @@ struct Workspace {
     int64_t scan_tiles = 0;
     Buf small;
     Buf cnt, off, tot, parts_dev;
+    Buf agrp;                              // (first, count) groups of references sharing an alpha string
+    std::vector<uint64_t> agrp_keys;       // host copy of the sorted reference keys, for grouping
+    std::vector<uint32_t> agrp_host;       // source of the last upload of agrp
     Small *host_small = nullptr;  // pinned mirror
     std::vector<hipEvent_t> evpool;
     size_t ev_used = 0;
@@ -187,7 +190,7 @@ struct Workspace {
         buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv), buf_free(A, refX);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
-        buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev);
+        buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev), buf_free(A, agrp);
         rec_cap = scan_tiles = 0;
         if (host_small) {
             (void)hipHostFree(host_small);
@@ -671,6 +674,43 @@ void fill_result(pt2_result *out, const Partial &p)
     out->key_sum = p.key_sum;
 }
 
+// Groups of at most ALPHA_GROUP consecutive sorted references that share
+// their alpha string (bits [norb, 2 norb) of the key), uploaded to ws.agrp as
+// (first, count) pairs for k_gen_alpha.
+int alpha_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, hipStream_t st, int64_t &ngrp)
+{
+    ngrp = 0;
+    if (n <= 0 || n > 0xFFFFFFFFll)
+        return PT2_OK;
+    ws.agrp_keys.resize((size_t)n * W);
+    for (int w = 0; w < W; w++)
+        HIPCHK(hipMemcpyAsync(ws.agrp_keys.data() + (size_t)w * n, refs.key[w], (size_t)n * 8,
+                              hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    uint64_t am[MAXW] = {};
+    for (int b = norb; b < 2 * norb; b++)
+        am[b >> 6] |= 1ull << (b & 63);
+    const uint64_t *K = ws.agrp_keys.data();
+    ws.agrp_host.clear();
+    int64_t first = 0;
+    for (int64_t i = 1; i <= n; i++) {
+        bool same = i < n && i - first < ALPHA_GROUP;
+        for (int w = 0; same && w < W; w++)
+            same = ((K[(size_t)w * n + i] ^ K[(size_t)w * n + first]) & am[w]) == 0;
+        if (!same) {
+            ws.agrp_host.push_back((uint32_t)first);
+            ws.agrp_host.push_back((uint32_t)(i - first));
+            first = i;
+        }
+    }
+    ngrp = (int64_t)ws.agrp_host.size() / 2;
+    int rc;
+    if ((rc = buf_ensure(ws.A, ws.agrp, ws.agrp_host.size() * 4)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(ws.agrp.p, ws.agrp_host.data(), ws.agrp_host.size() * 4, hipMemcpyHostToDevice, st));
+    return PT2_OK;
+}
+
 int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result *out)
 {
     const double t0 = now_ms();
@@ -793,6 +833,13 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     res.record_bytes = (uint32_t)rbytes;
     res.key_bits = key_bits;
     Small *ds = ws.dsmall();
+    // alpha-alpha doubles shared between references of one alpha string
+    // (direct generation with bitstring keys)
+    int64_t ngrp = 0;
+    const bool reuse = !P.compact && c->opt.alpha_reuse && !sys.kc.on && !sys.kc.hash && L.nDaa > 0 && alpha_ok(L, W);
+    if (reuse && (rc = alpha_groups(ws, refs, W, c->norb, J.n, st, ngrp)))
+        return rc;
+    res.n_alpha_groups = (uint64_t)ngrp;
     std::vector<Partial> part_res(P.parts.size());
     for (size_t q = 0; q < P.parts.size(); q++) {
         const int64_t n = (int64_t)P.sizes[q];
@@ -802,8 +849,11 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         hipEvent_t a;
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
-        if (!P.compact)
-            HIPCHK(launch_gen_direct(sys, L, pm, refs, J.n, P.chunk, A, st));
+        if (!P.compact) {
+            HIPCHK(launch_gen_direct(sys, L, pm, refs, J.n, P.chunk, ngrp > 0 ? 1 : 0, A, st));
+            if (ngrp > 0)
+                HIPCHK(launch_gen_alpha(sys, L, pm, refs, (const uint32_t *)ws.agrp.p, ngrp, A, st));
+        }
         else if (P.target)
             HIPCHK(launch_gen_target(sys, L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
                                      (const uint64_t *)ws.off.p + (size_t)q * P.nchunks,
@@ -1380,6 +1430,7 @@ PT2_API void pt2_default_options(pt2_options *o)
     o->exclusion = PT2_EXCLUDE_SEARCH;
     o->device = 0;
     o->n_streams = 4;
+    o->alpha_reuse = 1;
 }
 
 PT2_API int pt2_key_words(int norb) { return (2 * norb + 63) / 64; }
@@ -1420,6 +1471,8 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         return fail(PT2_E_INVALID, "spin_flip must be 0 or 1");
     if (o.spin_flip && nalpha != nbeta)
         return fail(PT2_E_INVALID, "spin_flip needs nalpha == nbeta (S_z = 0)");
+    if (o.alpha_reuse != 0 && o.alpha_reuse != 1)
+        return fail(PT2_E_INVALID, "alpha_reuse must be 0 or 1");
     if (o.compress_keys < -1 || o.compress_keys > 2)
         return fail(PT2_E_INVALID, "compress_keys must be -1, 0, 1 or 2");
     if ((o.alloc == nullptr) != (o.free == nullptr))

@@ -414,6 +414,53 @@ def test_invalid_references_rejected(pt2, c1):
     assert_matches(ctx.evaluate(c1["dets"], c1["c"], c1["e0"]), c1["ref"])
 
 
+@pytest.mark.parametrize("norb,na,nb,n_alpha,per_alpha,prec", [
+    (12, 4, 4, 3, 70, "fp64"), (40, 10, 10, 6, 45, "fp32"), (33, 5, 3, 4, 40, "fp32-arith"),
+    (70, 4, 4, 3, 33, "fp64")])
+def test_alpha_reuse_gives_identical_results(pt2, norb, na, nb, n_alpha, per_alpha, prec):
+    """References sharing alpha strings, in groups larger than the 32 a
+    workgroup takes: generating the alpha-alpha doubles once per group gives
+    every result bit for bit as generating them per reference, with the group
+    count that the sorted reference implies; the smallest case also matches
+    the oracle."""
+    rng = np.random.default_rng(norb * 100 + n_alpha)
+    A, B, seen_a = [], [], set()
+    while len(seen_a) < n_alpha:
+        a = tuple(sorted(rng.choice(norb, na, replace=False)))
+        if a in seen_a:
+            continue
+        seen_a.add(a)
+        seen_b = set()
+        while len(seen_b) < per_alpha:
+            seen_b.add(tuple(sorted(rng.choice(norb, nb, replace=False))))
+        for b in seen_b:
+            ra, rb = np.zeros(norb, bool), np.zeros(norb, bool)
+            ra[list(a)], rb[list(b)] = True, True
+            A.append(ra)
+            B.append(rb)
+    dets = synth.pack_keys(np.array(A), np.array(B), norb)
+    dets = dets[rng.permutation(len(dets))]
+    c = rng.normal(size=len(dets))
+    c /= np.linalg.norm(c)
+    h, eri, _ = synth.make_integrals(norb, 6, 9100 + norb)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    e0 = float(O.diag(dets).min()) - 5.0
+    res = {}
+    for reuse in (True, False):
+        ctx = pt2.Context(h, eri, norb, na, nb, precision=prec, compress_keys=0, alpha_reuse=reuse)
+        res[reuse] = ctx.evaluate(dets, c, e0)
+        ctx.close()
+    groups = n_alpha * ((per_alpha + 31) // 32)
+    print("alpha groups", res[True]["n_alpha_groups"], "expected", groups, flush=True)
+    assert res[True]["n_alpha_groups"] == groups
+    assert res[False]["n_alpha_groups"] == 0
+    for k in ALL_FIELDS:
+        assert res[True][k] == res[False][k], (k, res[True][k], res[False][k])
+    if norb <= 12:
+        ref, _ = O.pt2(dets, c, e0)
+        assert_matches(res[True], ref)
+
+
 # ---------------------------------------------------------------------------
 # The radix sort on its own
 
