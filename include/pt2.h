@@ -152,16 +152,18 @@ typedef struct {
                                       and checksums then cover the generated half;
                                       n_contrib stays the structural count of all
                                       terms.  Default 0                              */
-    int alpha_reuse;               /* 1 (default): when every term of every
-                                      reference is generated (one subset, no cutoff,
-                                      no spin flip) with bitstring keys, the
-                                      alpha-alpha doubles and their matrix elements
-                                      are computed once per group of up to 32
-                                      references sharing an alpha string and written
-                                      for each of them (Section V, data reuse for
-                                      unique alpha strings); the records, and so
-                                      every result, are identical.  0: each
-                                      reference computes its own                   */
+    int string_reuse;              /* when every term of every reference is
+                                      generated (one subset, no cutoff, no spin
+                                      flip) with bitstring keys, same-spin doubles
+                                      and their matrix elements are computed once
+                                      per group of up to 32 references sharing the
+                                      spin string they excite and written for each
+                                      of them (Section V, data reuse for unique
+                                      alpha and beta strings); the records, and so
+                                      every result, are identical.  1 (default):
+                                      alpha-alpha doubles, grouped by alpha string;
+                                      2: also beta-beta doubles, grouped by beta
+                                      string; 0: each reference computes its own   */
 } pt2_options;
 
 typedef struct {
@@ -197,7 +199,8 @@ typedef struct {
                                  kept for hash records)                              */
     uint64_t n_alpha_groups;  /* groups of references sharing an alpha string whose
                                  alpha-alpha doubles were generated once for the
-                                 group (alpha_reuse); 0 when not used              */
+                                 group (string_reuse); 0 when not used             */
+    uint64_t n_beta_groups;   /* the same for beta strings and beta-beta doubles    */
 } pt2_result;
 
 /* Fills *opt with defaults (FP64, cutoff 0, planner-chosen split, device 0). */

@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
                 ("stream", C.c_void_p), ("timing", C.c_int), ("compress_keys", C.c_int),
                 ("exclusion", C.c_int), ("hash_bits", C.c_int), ("spin_flip", C.c_int),
-                ("alpha_reuse", C.c_int)]
+                ("string_reuse", C.c_int)]
 
 
 class Result(C.Structure):
@@ -60,7 +60,7 @@ class Result(C.Structure):
                 ("ms_sort_scatter", C.c_double), ("ms_reduce", C.c_double), ("ms_hist", C.c_double),
                 ("ms_sort_pass_max", C.c_double), ("bytes_gen", C.c_double),
                 ("bytes_sort", C.c_double), ("bytes_reduce", C.c_double), ("key_bits", C.c_uint32),
-                ("n_alpha_groups", C.c_uint64)]
+                ("n_alpha_groups", C.c_uint64), ("n_beta_groups", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
@@ -169,7 +169,7 @@ class Context:
     def __init__(self, h, eri, norb, nalpha, nbeta, precision="fp64", cutoff=0.0,
                  log2_partitions=-1, device=0, n_streams=4, device_budget_bytes=0,
                  max_partition_bytes=0, timing=False, stream=None, allocator=None, compress_keys=-1,
-                 exclusion="search", hash_bits=0, spin_flip=False, alpha_reuse=True):
+                 exclusion="search", hash_bits=0, spin_flip=False, string_reuse=1):
         self.norb, self.nalpha, self.nbeta = int(norb), int(nalpha), int(nbeta)
         self.W = key_words(self.norb)
         o = default_options()
@@ -186,7 +186,7 @@ class Context:
         o.exclusion = {"search": 0, "subtract": 1}[exclusion]
         o.hash_bits = int(hash_bits)
         o.spin_flip = 1 if spin_flip else 0
-        o.alpha_reuse = 1 if alpha_reuse else 0
+        o.string_reuse = int(string_reuse)
         if stream is not None:
             o.stream = int(getattr(stream, "cuda_stream", stream))
         self._alloc = None

@@ -175,9 +175,10 @@ struct Workspace {
     int64_t scan_tiles = 0;
     Buf small;
     Buf cnt, off, tot, parts_dev;
-    Buf agrp;                              // (first, count) groups of references sharing an alpha string
+    Buf agrp;                              // groups of references sharing a spin string (spin_groups)
     std::vector<uint64_t> agrp_keys;       // host copy of the sorted reference keys, for grouping
     std::vector<uint32_t> agrp_host;       // source of the last upload of agrp
+    int64_t agrp_ngrp = 0;                 // alpha plus beta groups in agrp
     Small *host_small = nullptr;  // pinned mirror
     std::vector<hipEvent_t> evpool;
     size_t ev_used = 0;
@@ -674,36 +675,64 @@ void fill_result(pt2_result *out, const Partial &p)
     out->key_sum = p.key_sum;
 }
 
-// Groups of at most ALPHA_GROUP consecutive sorted references that share
-// their alpha string (bits [norb, 2 norb) of the key), uploaded to ws.agrp as
-// (first, count) pairs for k_gen_alpha.
-int alpha_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, hipStream_t st, int64_t &ngrp)
+// Groups of at most ALPHA_GROUP references that share their alpha string
+// (bits [norb, 2 norb) of the key; consecutive in the sorted reference) and
+// groups that share their beta string (bits [0, norb); from a stable sort of
+// the reference by beta string), for k_gen_spin.  Uploaded to ws.agrp as u32:
+// the nga alpha (start, count) pairs, the ngb beta pairs, then the alpha and
+// the beta member lists (n indices each) that the starts point into.
+int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, hipStream_t st, int64_t &nga,
+                int64_t &ngb)
 {
-    ngrp = 0;
-    if (n <= 0 || n > 0xFFFFFFFFll)
+    nga = ngb = 0;
+    if (n <= 0 || n > 0x7FFFFFFFll)
         return PT2_OK;
     ws.agrp_keys.resize((size_t)n * W);
     for (int w = 0; w < W; w++)
         HIPCHK(hipMemcpyAsync(ws.agrp_keys.data() + (size_t)w * n, refs.key[w], (size_t)n * 8,
                               hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    uint64_t am[MAXW] = {};
-    for (int b = norb; b < 2 * norb; b++)
-        am[b >> 6] |= 1ull << (b & 63);
+    uint64_t am[MAXW] = {}, bm[MAXW] = {};
+    for (int b = 0; b < 2 * norb; b++)
+        (b < norb ? bm : am)[b >> 6] |= 1ull << (b & 63);
     const uint64_t *K = ws.agrp_keys.data();
-    ws.agrp_host.clear();
-    int64_t first = 0;
-    for (int64_t i = 1; i <= n; i++) {
-        bool same = i < n && i - first < ALPHA_GROUP;
-        for (int w = 0; same && w < W; w++)
-            same = ((K[(size_t)w * n + i] ^ K[(size_t)w * n + first]) & am[w]) == 0;
-        if (!same) {
-            ws.agrp_host.push_back((uint32_t)first);
-            ws.agrp_host.push_back((uint32_t)(i - first));
+    auto word = [&](int64_t i, int w) { return K[(size_t)w * n + i]; };
+    auto same = [&](int64_t i, int64_t j, const uint64_t *mask) {
+        for (int w = 0; w < W; w++)
+            if ((word(i, w) ^ word(j, w)) & mask[w])
+                return false;
+        return true;
+    };
+    std::vector<uint32_t> ia((size_t)n), ib((size_t)n);
+    for (int64_t i = 0; i < n; i++)
+        ia[(size_t)i] = ib[(size_t)i] = (uint32_t)i;
+    std::stable_sort(ib.begin(), ib.end(), [&](uint32_t x, uint32_t y) {
+        for (int w = W - 1; w >= 0; w--) {
+            const uint64_t a = word(x, w) & bm[w], b = word(y, w) & bm[w];
+            if (a != b)
+                return a < b;
+        }
+        return false;
+    });
+    std::vector<uint32_t> ga, gb;
+    auto cut = [&](const std::vector<uint32_t> &ord, const uint64_t *mask, std::vector<uint32_t> &grp) {
+        int64_t first = 0;
+        for (int64_t i = 1; i <= n; i++) {
+            if (i < n && i - first < ALPHA_GROUP && same(ord[(size_t)i], ord[(size_t)first], mask))
+                continue;
+            grp.push_back((uint32_t)first);
+            grp.push_back((uint32_t)(i - first));
             first = i;
         }
-    }
-    ngrp = (int64_t)ws.agrp_host.size() / 2;
+    };
+    cut(ia, am, ga);
+    cut(ib, bm, gb);
+    nga = (int64_t)ga.size() / 2, ngb = (int64_t)gb.size() / 2;
+    ws.agrp_ngrp = nga + ngb;
+    ws.agrp_host = ga;
+    ws.agrp_host.insert(ws.agrp_host.end(), gb.begin(), gb.end());
+    ws.agrp_host.insert(ws.agrp_host.end(), ia.begin(), ia.end());
+    ws.agrp_host.insert(ws.agrp_host.end(), ib.begin(), ib.end());
     int rc;
     if ((rc = buf_ensure(ws.A, ws.agrp, ws.agrp_host.size() * 4)))
         return rc;
@@ -833,13 +862,17 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     res.record_bytes = (uint32_t)rbytes;
     res.key_bits = key_bits;
     Small *ds = ws.dsmall();
-    // alpha-alpha doubles shared between references of one alpha string
-    // (direct generation with bitstring keys)
-    int64_t ngrp = 0;
-    const bool reuse = !P.compact && c->opt.alpha_reuse && !sys.kc.on && !sys.kc.hash && L.nDaa > 0 && alpha_ok(L, W);
-    if (reuse && (rc = alpha_groups(ws, refs, W, c->norb, J.n, st, ngrp)))
+    // same-spin doubles shared between references of one spin string (direct
+    // generation with bitstring keys)
+    int64_t nga = 0, ngb = 0;
+    const bool want = c->opt.string_reuse == 2 ? L.nDaa + L.nDbb > 0 : c->opt.string_reuse == 1 && L.nDaa > 0;
+    const bool reuse = !P.compact && want && !sys.kc.on && !sys.kc.hash && spin_reuse_ok(L, W);
+    if (reuse && (rc = spin_groups(ws, refs, W, c->norb, J.n, st, nga, ngb)))
         return rc;
-    res.n_alpha_groups = (uint64_t)ngrp;
+    if (c->opt.string_reuse < 2)
+        ngb = 0;  // beta strings: only on request
+    res.n_alpha_groups = (uint64_t)nga;
+    res.n_beta_groups = (uint64_t)ngb;
     std::vector<Partial> part_res(P.parts.size());
     for (size_t q = 0; q < P.parts.size(); q++) {
         const int64_t n = (int64_t)P.sizes[q];
@@ -850,9 +883,14 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = timed_begin(ws, tm, st, a)))
             return rc;
         if (!P.compact) {
-            HIPCHK(launch_gen_direct(sys, L, pm, refs, J.n, P.chunk, ngrp > 0 ? 1 : 0, A, st));
-            if (ngrp > 0)
-                HIPCHK(launch_gen_alpha(sys, L, pm, refs, (const uint32_t *)ws.agrp.p, ngrp, A, st));
+            const int kinds = nga > 0 ? (ngb > 0 ? 2 : 1) : 0;
+            HIPCHK(launch_gen_direct(sys, L, pm, refs, J.n, P.chunk, kinds, A, st));
+            if (kinds > 0) {
+                const uint32_t *G = (const uint32_t *)ws.agrp.p, *I = G + 2 * ws.agrp_ngrp;
+                HIPCHK(launch_gen_spin(sys, L, pm, refs, 0, G, I, nga, A, st));
+                if (kinds == 2)
+                    HIPCHK(launch_gen_spin(sys, L, pm, refs, 1, G + 2 * nga, I + J.n, ngb, A, st));
+            }
         }
         else if (P.target)
             HIPCHK(launch_gen_target(sys, L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
@@ -1430,7 +1468,7 @@ PT2_API void pt2_default_options(pt2_options *o)
     o->exclusion = PT2_EXCLUDE_SEARCH;
     o->device = 0;
     o->n_streams = 4;
-    o->alpha_reuse = 1;
+    o->string_reuse = 1;
 }
 
 PT2_API int pt2_key_words(int norb) { return (2 * norb + 63) / 64; }
@@ -1471,8 +1509,8 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         return fail(PT2_E_INVALID, "spin_flip must be 0 or 1");
     if (o.spin_flip && nalpha != nbeta)
         return fail(PT2_E_INVALID, "spin_flip needs nalpha == nbeta (S_z = 0)");
-    if (o.alpha_reuse != 0 && o.alpha_reuse != 1)
-        return fail(PT2_E_INVALID, "alpha_reuse must be 0 or 1");
+    if (o.string_reuse < 0 || o.string_reuse > 2)
+        return fail(PT2_E_INVALID, "string_reuse must be 0, 1 or 2");
     if (o.compress_keys < -1 || o.compress_keys > 2)
         return fail(PT2_E_INVALID, "compress_keys must be -1, 0, 1 or 2");
     if ((o.alloc == nullptr) != (o.free == nullptr))

@@ -459,11 +459,12 @@ __device__ inline void store_pay(const GenLds &g, const DevSys &s, const ExcLayo
 
 // ---------------------------------------------------------------------------
 // Every term of every reference determinant, at its place in the reference's
-// block of nper records.  With skip_aa the alpha-alpha doubles are left to
-// k_gen_alpha, which shares them between references of one alpha string.
+// block of nper records.  skip_kinds = 1 leaves the alpha-alpha doubles
+// [o2, o3), 2 all same-spin doubles [o2, o4), to k_gen_spin, which shares them
+// between references of one spin string.
 template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout L, const Planes refs, int64_t nref, int64_t chunk,
-                                                            int cpd, int skip_aa, Planes out)
+                                                            int cpd, int skip_kinds, Planes out)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
     const int64_t ch = blockIdx.x - det * cpd;
     det_setup<W>(g, s, L, refs, det);
     const DivConsts D = div_consts(L);
-    const int64_t skip = skip_aa ? L.nDaa : 0;
+    const int64_t skip = (skip_kinds >= 1 ? L.nDaa : 0) + (skip_kinds == 2 ? L.nDbb : 0);
     const int64_t lo = ch * chunk;
     const int64_t hi = lo + chunk < L.nper - skip ? lo + chunk : L.nper - skip;
     const int64_t base = det * L.nper;
@@ -486,50 +487,56 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
     }
 }
 
-// Alpha-alpha doubles shared by the references of one alpha string (Section
-// V, data reuse for unique alpha strings).  The excitation, its matrix element
-// and its phase depend on the alpha string alone, so a workgroup takes a group
-// of at most ALPHA_GROUP references that share it (consecutive in the sorted
-// reference) and a chunk of their alpha-alpha index space, computes each term
-// once and writes it for every reference of the group: the record keeps that
-// reference's beta string and is scaled by its coefficient.  Records land
-// where k_gen_direct puts them, with the same values (bitstring keys only).
-// grp holds (first reference, count) pairs.
-template <int W, int PM>
-__global__ __launch_bounds__(GEN_THREADS) void k_gen_alpha(DevSys s, ExcLayout L, const Planes refs,
-                                                           const uint32_t *grp, int64_t achunk, int cpa, Planes out)
+// Same-spin doubles shared by the references of one spin string (Section V,
+// data reuse for unique alpha and beta strings).  An alpha-alpha double, its
+// matrix element and its phase depend on the alpha string alone (beta-beta:
+// the beta string), so a workgroup takes a group of at most ALPHA_GROUP
+// references that share that string and a chunk of their index space of that
+// kind, computes each term once and writes it for every reference of the
+// group: the record keeps the reference's other string and is scaled by its
+// coefficient.  Records land where k_gen_direct puts them, with the same
+// values (bitstring keys only).  grp holds (start, count) pairs into gidx,
+// the reference indices of the groups one after another.
+template <int W, int PM, int SP>
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_spin(DevSys s, ExcLayout L, const Planes refs,
+                                                          const uint32_t *grp, const uint32_t *gidx, int64_t achunk,
+                                                          int cpa, Planes out)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
     uint64_t *s_key = (uint64_t *)(lds + gen_lds_bytes_dev(L));  // [ALPHA_GROUP][W]
     double *s_c = (double *)(s_key + ALPHA_GROUP * W);            // [ALPHA_GROUP]
+    int64_t *s_det = (int64_t *)(s_c + ALPHA_GROUP);              // [ALPHA_GROUP]
     const int64_t gi = blockIdx.x / cpa;
     const int64_t ch = blockIdx.x - gi * cpa;
-    const int64_t first = grp[2 * gi];
+    const uint32_t *members = gidx + grp[2 * gi];
     const int m = (int)grp[2 * gi + 1];
-    det_setup<W>(g, s, L, refs, first, false);
+    det_setup<W>(g, s, L, refs, members[0], false);
     for (int i = threadIdx.x; i < m; i += GEN_THREADS) {
+        const int64_t d = members[i];
 #pragma unroll
         for (int w = 0; w < W; w++)
-            s_key[i * W + w] = pl_get<W>(refs, w, first + i);
-        s_c[i] = ((const double *)refs.pay)[first + i];
+            s_key[i * W + w] = pl_get<W>(refs, w, d);
+        s_c[i] = ((const double *)refs.pay)[d];
+        s_det[i] = d;
     }
     __syncthreads();
     const DivConsts D = div_consts(L);
     const GenHead *H = g.head;
-    const int n = s.norb;
+    const int n = s.norb, off = SP == 0 ? n : 0;
+    const int64_t o0 = SP == 0 ? L.o2 : L.o3, nk = SP == 0 ? L.nDaa : L.nDbb;
     const int64_t lo = ch * achunk;
-    const int64_t hi = lo + achunk < L.nDaa ? lo + achunk : L.nDaa;
+    const int64_t hi = lo + achunk < nk ? lo + achunk : nk;
     for (int64_t x = lo + threadIdx.x; x < hi; x += GEN_THREADS) {
-        const Exc e = decode(g, L, D, L.o2 + x);
+        const Exc e = decode(g, L, D, o0 + x);
         uint64_t fm[W];
 #pragma unroll
         for (int w = 0; w < W; w++)
             fm[w] = 0;
-        flip<W>(fm, n + H->occ[0][e.oi]);
-        flip<W>(fm, n + H->occ[0][e.oj]);
-        flip<W>(fm, n + H->vir[0][e.vi]);
-        flip<W>(fm, n + H->vir[0][e.vj]);
+        flip<W>(fm, off + H->occ[SP][e.oi]);
+        flip<W>(fm, off + H->occ[SP][e.oj]);
+        flip<W>(fm, off + H->vir[SP][e.vi]);
+        flip<W>(fm, off + H->vir[SP][e.vj]);
         double vd = 0.0;
         float vf = 0.f;
         if (PM == PM_FP32_ARITH)
@@ -537,7 +544,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_alpha(DevSys s, ExcLayout L
         else
             vd = exc_value<double>(g, s, L, e, s.V, s.h);
         for (int r = 0; r < m; r++) {
-            const int64_t pos = (first + r) * L.nper + L.o2 + x;
+            const int64_t pos = s_det[r] * L.nper + o0 + x;
             uint64_t key[W];
 #pragma unroll
             for (int w = 0; w < W; w++)
@@ -1091,9 +1098,9 @@ __global__ void k_refs_rank(DevSys s, Planes bits, int64_t n, Planes out)
 
 template <int W, int PM>
 hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int64_t chunk,
-                        int skip_aa, Planes out, hipStream_t st)
+                        int skip_kinds, Planes out, hipStream_t st)
 {
-    const int64_t nred = L.nper - (skip_aa ? L.nDaa : 0);
+    const int64_t nred = L.nper - (skip_kinds >= 1 ? L.nDaa : 0) - (skip_kinds == 2 ? L.nDbb : 0);
     int cpd = (int)((nred + chunk - 1) / chunk);
     int64_t blocks = nref * cpd;
     if (blocks == 0 || nred == 0)
@@ -1102,24 +1109,29 @@ hipError_t gen_direct_t(const DevSys &s, const ExcLayout &L, const Planes &refs,
         return hipErrorInvalidValue;
     size_t lds = gen_lds_bytes(L);
     hipLaunchKernelGGL((k_gen_direct<W, PM>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
-                       chunk, cpd, skip_aa, out);
+                       chunk, cpd, skip_kinds, out);
     return hipGetLastError();
 }
 
 template <int W, int PM>
-hipError_t gen_alpha_t(const DevSys &s, const ExcLayout &L, const Planes &refs, const uint32_t *grp, int64_t ngrp,
-                       Planes out, hipStream_t st)
+hipError_t gen_spin_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int sp, const uint32_t *grp,
+                      const uint32_t *gidx, int64_t ngrp, Planes out, hipStream_t st)
 {
-    if (ngrp == 0 || L.nDaa == 0)
+    const int64_t nk = sp == 0 ? L.nDaa : L.nDbb;
+    if (ngrp == 0 || nk == 0)
         return hipSuccess;
     const int64_t achunk = ALPHA_CHUNK;
-    const int cpa = (int)((L.nDaa + achunk - 1) / achunk);
+    const int cpa = (int)((nk + achunk - 1) / achunk);
     const int64_t blocks = ngrp * cpa;
     if (blocks > 0x7FFFFFFFll)
         return hipErrorInvalidValue;
-    const size_t lds = gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 8);
-    hipLaunchKernelGGL((k_gen_alpha<W, PM>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs, grp,
-                       achunk, cpa, out);
+    const size_t lds = gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 16);
+    if (sp == 0)
+        hipLaunchKernelGGL((k_gen_spin<W, PM, 0>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs,
+                           grp, gidx, achunk, cpa, out);
+    else
+        hipLaunchKernelGGL((k_gen_spin<W, PM, 1>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs,
+                           grp, gidx, achunk, cpa, out);
     return hipGetLastError();
 }
 
@@ -1137,9 +1149,9 @@ size_t target_lds_bytes(const ExcLayout &L, int log2p)
     return gen_lds_bytes(L) + tgt_lds_layout(L, log2p, o);
 }
 
-bool alpha_ok(const ExcLayout &L, int W)
+bool spin_reuse_ok(const ExcLayout &L, int W)
 {
-    return gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 8) <= 65536;
+    return gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 16) <= 65536;
 }
 
 bool target_ok(const ExcLayout &L, int64_t nref, int log2p)
@@ -1166,17 +1178,17 @@ bool target_ok(const ExcLayout &L, int64_t nref, int log2p)
     }
 
 hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk,
-                             int skip_aa, Planes out, hipStream_t st)
+                             int skip_kinds, Planes out, hipStream_t st)
 {
-#define CALL(W, F) gen_direct_t<W, F>(s, L, refs, nref, chunk, skip_aa, out, st)
+#define CALL(W, F) gen_direct_t<W, F>(s, L, refs, nref, chunk, skip_kinds, out, st)
     PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }
 
-hipError_t launch_gen_alpha(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, const uint32_t *grp,
-                            int64_t ngrp, Planes out, hipStream_t st)
+hipError_t launch_gen_spin(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int sp, const uint32_t *grp,
+                           const uint32_t *gidx, int64_t ngrp, Planes out, hipStream_t st)
 {
-#define CALL(W, F) gen_alpha_t<W, F>(s, L, refs, grp, ngrp, out, st)
+#define CALL(W, F) gen_spin_t<W, F>(s, L, refs, sp, grp, gidx, ngrp, out, st)
     PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }

@@ -37,8 +37,8 @@ constexpr int RED_LDS_REFS = 64;                      // reference keys staged p
 constexpr size_t RED_LDS_TABLE_MAX = 36 * 1024;       // packed diagonal table kept in LDS up to this size
 constexpr size_t RED_LDS_MAX = 64 * 1024;             // dynamic LDS of one single-pass workgroup
 constexpr int GEN_THREADS = 256;
-constexpr int ALPHA_GROUP = 32;                      // references per workgroup of k_gen_alpha
-constexpr int64_t ALPHA_CHUNK = 4096;                // alpha-alpha doubles per workgroup of k_gen_alpha
+constexpr int ALPHA_GROUP = 32;                      // references per workgroup of k_gen_spin
+constexpr int64_t ALPHA_CHUNK = 4096;                // same-spin doubles per workgroup of k_gen_spin
 
 // Device-side error flags (bitmask in Flags::err).
 enum : uint32_t {
@@ -348,16 +348,18 @@ inline int64_t gen_nchunks(const ExcLayout &L, int64_t nref, int64_t chunk)
 // gen.hip
 size_t gen_lds_bytes(const ExcLayout &L);
 // Direct generation: every term of every reference, record index
-// det*nper + k.  Requires no cutoff and a single subset.  skip_aa leaves the
-// alpha-alpha doubles [o2, o3) to launch_gen_alpha.
+// det*nper + k.  Requires no cutoff and a single subset.  skip_kinds = 1
+// leaves the alpha-alpha doubles [o2, o3), 2 the same-spin doubles [o2, o4),
+// to launch_gen_spin.
 hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
-                             int64_t chunk, int skip_aa, Planes out, hipStream_t st);
-// The alpha-alpha doubles of direct generation, computed once per group of
-// references sharing an alpha string: grp = ngrp (first, count) pairs over the
-// sorted reference, count <= ALPHA_GROUP.  Bitstring keys only.
-bool alpha_ok(const ExcLayout &L, int W);  // its LDS fits
-hipError_t launch_gen_alpha(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, const uint32_t *grp,
-                            int64_t ngrp, Planes out, hipStream_t st);
+                             int64_t chunk, int skip_kinds, Planes out, hipStream_t st);
+// The same-spin doubles of spin sp (0: alpha-alpha, 1: beta-beta) of direct
+// generation, computed once per group of references sharing that spin
+// string: grp = ngrp (start, count) pairs into gidx, the member reference
+// indices, count <= ALPHA_GROUP.  Bitstring keys only.
+bool spin_reuse_ok(const ExcLayout &L, int W);  // its LDS fits
+hipError_t launch_gen_spin(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int sp, const uint32_t *grp,
+                           const uint32_t *gidx, int64_t ngrp, Planes out, hipStream_t st);
 // Count pass: cnt[p * nchunks + chunk] = kept terms of chunk in subset p.
 hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                         int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks, hipStream_t st);

@@ -117,13 +117,13 @@ def test_bad_options_rejected():
     assert rc == pt2.PT2_E_INVALID
     assert b"spin_flip" in pt2._lib.pt2_last_error()
     o = pt2.default_options()
-    assert o.alpha_reuse == 1
-    o.alpha_reuse = 3
+    assert o.string_reuse == 1
+    o.string_reuse = 3
     ctx = pt2._CTX()
     rc = pt2._lib.pt2_create(hh.ctypes.data_as(pt2._f64p), ee.ctypes.data_as(pt2._f64p), 4, 2, 2,
                              pt2.C.byref(o), pt2.C.byref(ctx))
     assert rc == pt2.PT2_E_INVALID
-    assert b"alpha_reuse" in pt2._lib.pt2_last_error()
+    assert b"string_reuse" in pt2._lib.pt2_last_error()
 
 
 def test_evaluate_null_context_rejected():

@@ -414,15 +414,26 @@ def test_invalid_references_rejected(pt2, c1):
     assert_matches(ctx.evaluate(c1["dets"], c1["c"], c1["e0"]), c1["ref"])
 
 
+def spin_groups(dets, norb, spin, size=32):
+    """Groups of at most `size` references sharing their alpha (spin 0) or beta
+    (spin 1) string: the sum over distinct strings of ceil(count / size)."""
+    counts = {}
+    for row in dets:
+        k = int.from_bytes(row.astype("<u8").tobytes(), "little")
+        s = k >> norb if spin == 0 else k & ((1 << norb) - 1)
+        counts[s] = counts.get(s, 0) + 1
+    return sum((m + size - 1) // size for m in counts.values())
+
+
 @pytest.mark.parametrize("norb,na,nb,n_alpha,per_alpha,prec", [
     (12, 4, 4, 3, 70, "fp64"), (40, 10, 10, 6, 45, "fp32"), (33, 5, 3, 4, 40, "fp32-arith"),
-    (70, 4, 4, 3, 33, "fp64")])
-def test_alpha_reuse_gives_identical_results(pt2, norb, na, nb, n_alpha, per_alpha, prec):
-    """References sharing alpha strings, in groups larger than the 32 a
-    workgroup takes: generating the alpha-alpha doubles once per group gives
-    every result bit for bit as generating them per reference, with the group
-    count that the sorted reference implies; the smallest case also matches
-    the oracle."""
+    (70, 4, 4, 3, 33, "fp64"), (8, 3, 2, 4, 28, "fp64")])
+def test_string_reuse_gives_identical_results(pt2, norb, na, nb, n_alpha, per_alpha, prec):
+    """References sharing alpha strings (in groups larger than the 32 a
+    workgroup takes) and, the last case, beta strings: generating the same-spin
+    doubles once per group of references sharing the spin string gives every
+    result bit for bit as generating them per reference, with the group counts
+    that the reference implies; the small cases also match the oracle."""
     rng = np.random.default_rng(norb * 100 + n_alpha)
     A, B, seen_a = [], [], set()
     while len(seen_a) < n_alpha:
@@ -446,19 +457,21 @@ def test_alpha_reuse_gives_identical_results(pt2, norb, na, nb, n_alpha, per_alp
     O = oracle.Oracle(h, eri, norb, na, nb)
     e0 = float(O.diag(dets).min()) - 5.0
     res = {}
-    for reuse in (True, False):
-        ctx = pt2.Context(h, eri, norb, na, nb, precision=prec, compress_keys=0, alpha_reuse=reuse)
-        res[reuse] = ctx.evaluate(dets, c, e0)
+    for mode in (0, 1, 2):
+        ctx = pt2.Context(h, eri, norb, na, nb, precision=prec, compress_keys=0, string_reuse=mode)
+        res[mode] = ctx.evaluate(dets, c, e0)
         ctx.close()
-    groups = n_alpha * ((per_alpha + 31) // 32)
-    print("alpha groups", res[True]["n_alpha_groups"], "expected", groups, flush=True)
-    assert res[True]["n_alpha_groups"] == groups
-    assert res[False]["n_alpha_groups"] == 0
-    for k in ALL_FIELDS:
-        assert res[True][k] == res[False][k], (k, res[True][k], res[False][k])
+    ga, gb = spin_groups(dets, norb, 0), spin_groups(dets, norb, 1)
+    print("groups", res[2]["n_alpha_groups"], res[2]["n_beta_groups"], "expected", ga, gb, flush=True)
+    assert (res[0]["n_alpha_groups"], res[0]["n_beta_groups"]) == (0, 0)
+    assert (res[1]["n_alpha_groups"], res[1]["n_beta_groups"]) == (ga, 0)
+    assert (res[2]["n_alpha_groups"], res[2]["n_beta_groups"]) == (ga, gb)
+    for mode in (1, 2):
+        for k in ALL_FIELDS:
+            assert res[mode][k] == res[0][k], (mode, k, res[mode][k], res[0][k])
     if norb <= 12:
         ref, _ = O.pt2(dets, c, e0)
-        assert_matches(res[True], ref)
+        assert_matches(res[2], ref)
 
 
 # ---------------------------------------------------------------------------
