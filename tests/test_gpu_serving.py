@@ -70,6 +70,36 @@ def test_served_results_equal_standalone(pt2, reqs):
         ctx.close()
 
 
+def test_served_string_reuse(pt2, reqs):
+    """Served requests with bitstring keys, their same-spin doubles shared by
+    the references of one alpha (and beta) string, running concurrently:
+    every result equals the request evaluated alone, and equals the result
+    without the sharing."""
+    ctxs, alone = [], []
+    for j, (r, h, eri, dets, c, e0) in enumerate(reqs[:4]):
+        mode = 1 + j % 2
+        ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, compress_keys=0, string_reuse=mode, n_streams=4)
+        ctxs.append(ctx)
+        alone.append(ctx.evaluate(dets, c, e0))
+        assert alone[-1]["n_alpha_groups"] > 0
+        assert (alone[-1]["n_beta_groups"] > 0) == (mode == 2)
+        off = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, compress_keys=0, string_reuse=0)
+        plain = off.evaluate(dets, c, e0)
+        off.close()
+        for k in KEYS:
+            assert alone[-1][k] == plain[k], (j, k, alone[-1][k], plain[k])
+    ids = []
+    for rep in range(2):
+        for j, (r, h, eri, dets, c, e0) in enumerate(reqs[:4]):
+            ids.append((j, ctxs[j].submit(dets, c, e0)))
+    for j, rid in ids:
+        got = ctxs[j].wait(rid)
+        for k in KEYS:
+            assert got[k] == alone[j][k], (j, k, got[k], alone[j][k])
+    for ctx in ctxs:
+        ctx.close()
+
+
 def test_served_results_match_oracle(pt2, reqs):
     for j in (0, 1):
         r, h, eri, dets, c, e0 = reqs[j]
