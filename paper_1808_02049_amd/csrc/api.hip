@@ -675,7 +675,7 @@ void fill_result(pt2_result *out, const Partial &p)
     out->key_sum = p.key_sum;
 }
 
-// Groups of at most ALPHA_GROUP references that share their alpha string
+// Groups of at most REUSE_GROUP references that share their alpha string
 // (bits [norb, 2 norb) of the key; consecutive in the sorted reference) and
 // groups that share their beta string (bits [0, norb); from a stable sort of
 // the reference by beta string), for k_gen_spin.  Uploaded to ws.agrp as u32:
@@ -718,7 +718,7 @@ int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, h
     auto cut = [&](const std::vector<uint32_t> &ord, const uint64_t *mask, std::vector<uint32_t> &grp) {
         int64_t first = 0;
         for (int64_t i = 1; i <= n; i++) {
-            if (i < n && i - first < ALPHA_GROUP && same(ord[(size_t)i], ord[(size_t)first], mask))
+            if (i < n && i - first < REUSE_GROUP && same(ord[(size_t)i], ord[(size_t)first], mask))
                 continue;
             grp.push_back((uint32_t)first);
             grp.push_back((uint32_t)(i - first));

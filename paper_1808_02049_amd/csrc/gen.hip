@@ -490,7 +490,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
 // Same-spin doubles shared by the references of one spin string (Section V,
 // data reuse for unique alpha and beta strings).  An alpha-alpha double, its
 // matrix element and its phase depend on the alpha string alone (beta-beta:
-// the beta string), so a workgroup takes a group of at most ALPHA_GROUP
+// the beta string), so a workgroup takes a group of at most REUSE_GROUP
 // references that share that string and a chunk of their index space of that
 // kind, computes each term once and writes it for every reference of the
 // group: the record keeps the reference's other string and is scaled by its
@@ -504,9 +504,9 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_spin(DevSys s, ExcLayout L,
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
-    uint64_t *s_key = (uint64_t *)(lds + gen_lds_bytes_dev(L));  // [ALPHA_GROUP][W]
-    double *s_c = (double *)(s_key + ALPHA_GROUP * W);            // [ALPHA_GROUP]
-    int64_t *s_det = (int64_t *)(s_c + ALPHA_GROUP);              // [ALPHA_GROUP]
+    uint64_t *s_key = (uint64_t *)(lds + gen_lds_bytes_dev(L));  // [REUSE_GROUP][W]
+    double *s_c = (double *)(s_key + REUSE_GROUP * W);            // [REUSE_GROUP]
+    int64_t *s_det = (int64_t *)(s_c + REUSE_GROUP);              // [REUSE_GROUP]
     const int64_t gi = blockIdx.x / cpa;
     const int64_t ch = blockIdx.x - gi * cpa;
     const uint32_t *members = gidx + grp[2 * gi];
@@ -1120,12 +1120,12 @@ hipError_t gen_spin_t(const DevSys &s, const ExcLayout &L, const Planes &refs, i
     const int64_t nk = sp == 0 ? L.nDaa : L.nDbb;
     if (ngrp == 0 || nk == 0)
         return hipSuccess;
-    const int64_t achunk = ALPHA_CHUNK;
+    const int64_t achunk = REUSE_CHUNK;
     const int cpa = (int)((nk + achunk - 1) / achunk);
     const int64_t blocks = ngrp * cpa;
     if (blocks > 0x7FFFFFFFll)
         return hipErrorInvalidValue;
-    const size_t lds = gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 16);
+    const size_t lds = gen_lds_bytes(L) + (size_t)REUSE_GROUP * (W * 8 + 16);
     if (sp == 0)
         hipLaunchKernelGGL((k_gen_spin<W, PM, 0>), dim3((unsigned)blocks), dim3(GEN_THREADS), lds, st, s, L, refs,
                            grp, gidx, achunk, cpa, out);
@@ -1151,7 +1151,7 @@ size_t target_lds_bytes(const ExcLayout &L, int log2p)
 
 bool spin_reuse_ok(const ExcLayout &L, int W)
 {
-    return gen_lds_bytes(L) + (size_t)ALPHA_GROUP * (W * 8 + 16) <= 65536;
+    return gen_lds_bytes(L) + (size_t)REUSE_GROUP * (W * 8 + 16) <= 65536;
 }
 
 bool target_ok(const ExcLayout &L, int64_t nref, int log2p)

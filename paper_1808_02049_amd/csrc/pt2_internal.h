@@ -37,8 +37,8 @@ constexpr int RED_LDS_REFS = 64;                      // reference keys staged p
 constexpr size_t RED_LDS_TABLE_MAX = 36 * 1024;       // packed diagonal table kept in LDS up to this size
 constexpr size_t RED_LDS_MAX = 64 * 1024;             // dynamic LDS of one single-pass workgroup
 constexpr int GEN_THREADS = 256;
-constexpr int ALPHA_GROUP = 32;                      // references per workgroup of k_gen_spin
-constexpr int64_t ALPHA_CHUNK = 4096;                // same-spin doubles per workgroup of k_gen_spin
+constexpr int REUSE_GROUP = 32;                      // references per workgroup of k_gen_spin
+constexpr int64_t REUSE_CHUNK = 4096;                // same-spin doubles per workgroup of k_gen_spin
 
 // Device-side error flags (bitmask in Flags::err).
 enum : uint32_t {
@@ -356,7 +356,7 @@ hipError_t launch_gen_direct(const DevSys &s, const ExcLayout &L, int pm, const 
 // The same-spin doubles of spin sp (0: alpha-alpha, 1: beta-beta) of direct
 // generation, computed once per group of references sharing that spin
 // string: grp = ngrp (start, count) pairs into gidx, the member reference
-// indices, count <= ALPHA_GROUP.  Bitstring keys only.
+// indices, count <= REUSE_GROUP.  Bitstring keys only.
 bool spin_reuse_ok(const ExcLayout &L, int W);  // its LDS fits
 hipError_t launch_gen_spin(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int sp, const uint32_t *grp,
                            const uint32_t *gidx, int64_t ngrp, Planes out, hipStream_t st);
