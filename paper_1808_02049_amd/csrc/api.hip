@@ -677,12 +677,12 @@ void fill_result(pt2_result *out, const Partial &p)
 
 // Groups of at most REUSE_GROUP references that share their alpha string
 // (bits [norb, 2 norb) of the key; consecutive in the sorted reference) and
-// groups that share their beta string (bits [0, norb); from a stable sort of
-// the reference by beta string), for k_gen_spin.  Uploaded to ws.agrp as u32:
-// the nga alpha (start, count) pairs, the ngb beta pairs, then the alpha and
-// the beta member lists (n indices each) that the starts point into.
-int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, hipStream_t st, int64_t &nga,
-                int64_t &ngb)
+// if beta, groups that share their beta string (bits [0, norb); from a stable
+// sort of the reference by beta string), for k_gen_spin.  Uploaded to ws.agrp
+// as u32: the nga alpha (start, count) pairs, the ngb beta pairs, then the
+// alpha and the beta member lists (n indices each) that the starts point into.
+int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, bool beta, hipStream_t st,
+                int64_t &nga, int64_t &ngb)
 {
     nga = ngb = 0;
     if (n <= 0 || n > 0x7FFFFFFFll)
@@ -703,9 +703,11 @@ int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, h
                 return false;
         return true;
     };
-    std::vector<uint32_t> ia((size_t)n), ib((size_t)n);
+    std::vector<uint32_t> ia((size_t)n), ib;
     for (int64_t i = 0; i < n; i++)
-        ia[(size_t)i] = ib[(size_t)i] = (uint32_t)i;
+        ia[(size_t)i] = (uint32_t)i;
+    if (beta)
+        ib = ia;
     std::stable_sort(ib.begin(), ib.end(), [&](uint32_t x, uint32_t y) {
         for (int w = W - 1; w >= 0; w--) {
             const uint64_t a = word(x, w) & bm[w], b = word(y, w) & bm[w];
@@ -726,7 +728,8 @@ int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, h
         }
     };
     cut(ia, am, ga);
-    cut(ib, bm, gb);
+    if (beta)
+        cut(ib, bm, gb);
     nga = (int64_t)ga.size() / 2, ngb = (int64_t)gb.size() / 2;
     ws.agrp_ngrp = nga + ngb;
     ws.agrp_host = ga;
@@ -867,10 +870,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     int64_t nga = 0, ngb = 0;
     const bool want = c->opt.string_reuse == 2 ? L.nDaa + L.nDbb > 0 : c->opt.string_reuse == 1 && L.nDaa > 0;
     const bool reuse = !P.compact && want && !sys.kc.on && !sys.kc.hash && spin_reuse_ok(L, W);
-    if (reuse && (rc = spin_groups(ws, refs, W, c->norb, J.n, st, nga, ngb)))
+    if (reuse && (rc = spin_groups(ws, refs, W, c->norb, J.n, c->opt.string_reuse == 2, st, nga, ngb)))
         return rc;
-    if (c->opt.string_reuse < 2)
-        ngb = 0;  // beta strings: only on request
     res.n_alpha_groups = (uint64_t)nga;
     res.n_beta_groups = (uint64_t)ngb;
     std::vector<Partial> part_res(P.parts.size());
