@@ -33,6 +33,34 @@ def test_struct_sizes_match_header_layout():
     assert o.log2_partitions == -1 and o.precision == pt2.PT2_FP64 and o.cutoff == 0.0
 
 
+def test_field_offsets_match_header(tmp_path):
+    """Every field of the ctypes mirrors of pt2_options and pt2_result sits at
+    the offset the C compiler gives it from include/pt2.h, and the sizes agree
+    (a field missing on either side moves an offset or the size)."""
+    import shutil
+    import subprocess
+    import paper_1808_02049_amd as pt2
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = (("pt2_options", pt2.Options), ("pt2_result", pt2.Result))
+    lines = ["#include <stdio.h>", '#include "pt2.h"', "int main(void) {"]
+    for name, cls in structs:
+        lines.append(f'printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {(a, b): int(c) for a, b, c in (line.split() for line in out.splitlines())}
+    for name, cls in structs:
+        assert got[(name, "sizeof")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+
+
 def test_key_words():
     import paper_1808_02049_amd as pt2
     assert [pt2.key_words(n) for n in (1, 12, 32, 33, 40, 64, 76, 100, 128)] == [1, 1, 1, 2, 2, 2, 3, 4, 4]
