@@ -462,3 +462,45 @@ def test_spin_flip_identity(norb, n_el, nref, sign):
             half += (1.0 if ka == kb else 2.0) * nums[i] ** 2 / (e0 - diag[i])
     full, _ = O.pt2(dets, c, e0)
     assert half == pytest.approx(full["e_pt2"], rel=1e-12, abs=1e-14)
+
+
+def _terms_by_flip(O, det, norb):
+    """The oracle's terms H_ai of one determinant (c = 1), keyed by the bits
+    flipped in the alpha half and in the beta half."""
+    keys, vals = O.emit(det[None], np.ones(1))
+    k0 = int.from_bytes(det.astype("<u8").tobytes(), "little")
+    lo = (1 << norb) - 1
+    out = {}
+    for k, v in zip(keys, vals):
+        d = int.from_bytes(k.astype("<u8").tobytes(), "little") ^ k0
+        out[(d >> norb, d & lo)] = v
+    return out
+
+
+def test_same_spin_doubles_depend_on_their_own_string_only():
+    """The premise of sharing same-spin doubles between references (Section
+    V, data reuse for unique alpha and beta strings): an alpha-alpha double's
+    H_ai, phase included, is the same for two determinants with one alpha
+    string and different beta strings (beta-beta likewise); an alpha single's
+    is not, as it sums over the occupied orbitals of both spins."""
+    norb, na, nb = 8, 3, 3
+    h, eri, _ = synth.make_integrals(norb, 6, 4242)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    occ = lambda idx: np.isin(np.arange(norb), idx)
+    a1, a2 = occ([0, 2, 5]), occ([1, 2, 6])
+    b1, b2 = occ([0, 1, 4]), occ([2, 3, 7])
+    dets = synth.pack_keys(np.array([a1, a1, a1, a2]), np.array([b1, b2, b1, b1]), norb)
+    t = [_terms_by_flip(O, d, norb) for d in dets]
+
+    def kind(t, pred):
+        return {f: v for f, v in t.items() if pred(bin(f[0]).count("1"), bin(f[1]).count("1"))}
+
+    aa = lambda x, y: x == 4 and y == 0
+    bb = lambda x, y: x == 0 and y == 4
+    a_single = lambda x, y: x == 2 and y == 0
+    # dets 0 and 1 share the alpha string; dets 2 and 3 share the beta string
+    assert kind(t[0], aa) and kind(t[0], aa) == kind(t[1], aa)
+    assert kind(t[2], bb) and kind(t[2], bb) == kind(t[3], bb)
+    s0, s1 = kind(t[0], a_single), kind(t[1], a_single)
+    assert s0.keys() == s1.keys() and any(s0[f] != s1[f] for f in s0)
+
