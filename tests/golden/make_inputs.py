@@ -30,7 +30,7 @@ import synth  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def make(name: str) -> dict:
+def make(name: str, outdir: str = HERE) -> dict:
     w = synth.WORKLOADS[name]
     t0 = time.time()
     h, eri, rng = synth.make_integrals(w.norb, w.n_chol, w.seed)
@@ -51,7 +51,7 @@ def make(name: str) -> dict:
         c = synth.decaying_coefficients(w.n_ref, w.decay, signs)
         e0 = float(O.expectation(dets, c))
     out["e0"] = np.float64(e0)
-    np.savez_compressed(os.path.join(HERE, f"inputs_{name}.npz"), **out)
+    np.savez_compressed(os.path.join(outdir, f"inputs_{name}.npz"), **out)
     meta = {"workload": name, "pool": int(len(pool)), "n_ref": int(w.n_ref), "e0": e0,
             "e0_hex": float(e0).hex(), "seconds": round(time.time() - t0, 1)}
     print(json.dumps(meta), flush=True)
