@@ -61,6 +61,20 @@ def test_field_offsets_match_header(tmp_path):
             assert got[(name, f)] == getattr(cls, f).offset, (name, f)
 
 
+def test_import_fails_without_the_library(tmp_path):
+    """No CPU fallback: the binding refuses to import when libpt2.so is absent."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1808_02049_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1808_02049_amd", "__init__.py"), pkg)
+    r = subprocess.run([sys.executable, "-c", "import paper_1808_02049_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is missing" in r.stderr
+
+
 def test_key_words():
     import paper_1808_02049_amd as pt2
     assert [pt2.key_words(n) for n in (1, 12, 32, 33, 40, 64, 76, 100, 128)] == [1, 1, 1, 2, 2, 2, 3, 4, 4]
