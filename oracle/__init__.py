@@ -73,6 +73,8 @@ def _libs():
         _pt2.orc_numerators.restype = C.c_int64
         _pt2.orc_diag_many.argtypes = [S, _u64p, C.c_int64, _f64p, C.c_int]
         _pt2.orc_diag_many.restype = None
+        _pt2.orc_denominator_many.argtypes = [S, _u64p, C.c_int64, C.c_double, _f64p]
+        _pt2.orc_denominator_many.restype = None
         _pt2.orc_hrr.argtypes = [S, _u64p, C.c_int64, _f64p]
         _pt2.orc_hrr.restype = None
         _pt2.orc_expectation.argtypes = [S, _u64p, _f64p, C.c_int64, C.c_int]
@@ -189,6 +191,17 @@ class Oracle(_Base):
         if len(k):
             lib.orc_diag_many(C.byref(self._sys), _ptr(k, _u64p), len(k), _ptr(out, _f64p),
                               int(nthreads or default_threads()))
+        return out
+
+    def denominators(self, keys, e0):
+        """E0 - H_aa of each key as one compensated sum (exact to a few ulps
+        of the difference itself)."""
+        lib, _ = _libs()
+        k = self._keys(keys)
+        out = np.zeros(len(k), dtype=np.float64)
+        if len(k):
+            lib.orc_denominator_many(C.byref(self._sys), _ptr(k, _u64p), len(k), float(e0),
+                                     _ptr(out, _f64p))
         return out
 
     def hij(self, ki, kj):

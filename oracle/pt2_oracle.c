@@ -18,8 +18,10 @@
  * double excitations; each emits the pair (bitstring, H_ai * c_i); the pairs
  * are grouped by bitstring with the C library's qsort (a library primitive);
  * a single pass over the groups forms N_a, skips bitstrings present in the
- * reference (found by bsearch), evaluates the diagonal element from scratch
- * and accumulates the energy with Neumaier compensated summation.
+ * reference (found by bsearch), forms the denominator E0 - H_aa from scratch
+ * as one compensated sum (orc_denominator: exact to a few units in the last
+ * place of the difference, which near-singular denominators need) and
+ * accumulates the energy with Neumaier compensated summation.
  *
  * Constraints: the external space is split into 2^k non-overlapping, complete
  * subsets by the top k bits of a Zobrist hash of the bitstring (XOR of one
@@ -139,6 +141,19 @@ static uint64_t key_mix(const uint64_t *key, int W)
 /* ------------------------------------------------------------------------ */
 /* Matrix elements                                                          */
 
+/* Neumaier's compensated summation: sum + comp carries the running total,
+ * comp the exact rounding errors of the additions (each recovered by the
+ * two-sum error-free transformation). */
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x))
+        *comp += (*sum - t) + x;
+    else
+        *comp += (x - t) + *sum;
+    *sum = t;
+}
+
 /* <D|H|D> from scratch:  sum_p h_pp + sum_{p<q} [(pp|qq) - delta_spin (pq|qp)] */
 double orc_diag(const orc_system *s, const uint64_t *key)
 {
@@ -160,6 +175,40 @@ double orc_diag(const orc_system *s, const uint64_t *key)
         }
     }
     return e;
+}
+
+/* The Epstein-Nesbet denominator E0 - <D|H|D> (Section II), as ONE
+ * compensated sum of E0 and the negated diagonal summands.
+ *
+ * E0 and <D|H|D> are each of order 10^2 Eh while their difference can be
+ * 10^-6 Eh or less for some external determinants, and such a determinant's
+ * term N^2 / (E0 - H_DD) moves by its own size for every relative change of
+ * the difference.  Rounding <D|H|D> to FP64 first (orc_diag) leaves an error
+ * of about 1e-13 Eh in the difference, which is amplified there by
+ * (N / (E0 - H_DD))^2, up to 1e6 on the synthetic systems.  Every summand here
+ * (E0, -h_pp, -(pp|qq), +(pq|qp)) is an exact FP64 number, and the
+ * compensated sum returns their exact total to within a few units in the last
+ * place of the total itself, whatever its size. */
+double orc_denominator(const orc_system *s, const uint64_t *key, double e0)
+{
+    int orb[2 * ORC_MAXORB], spn[2 * ORC_MAXORB], n = 0;
+    for (int spin = 0; spin < 2; spin++)
+        for (int p = 0; p < s->norb; p++)
+            if (get_bit(key, spin_bit(s, spin, p))) {
+                orb[n] = p;
+                spn[n] = spin;
+                n++;
+            }
+    double sum = e0, comp = 0.0;
+    for (int i = 0; i < n; i++) {
+        neumaier_add(&sum, &comp, -H1(s, orb[i], orb[i]));
+        for (int j = i + 1; j < n; j++) {
+            neumaier_add(&sum, &comp, -ERI(s, orb[i], orb[i], orb[j], orb[j]));
+            if (spn[i] == spn[j])
+                neumaier_add(&sum, &comp, ERI(s, orb[i], orb[j], orb[j], orb[i]));
+        }
+    }
+    return sum + comp;
 }
 
 /* <D'|H|D> for D' = D with r -> a in one spin (phase excluded):
@@ -439,16 +488,6 @@ static int64_t ref_find(const orc_refset *R, const uint64_t *key)
     return -1;
 }
 
-static void neumaier_add(double *sum, double *comp, double x)
-{
-    double t = *sum + x;
-    if (fabs(*sum) >= fabs(x))
-        *comp += (*sum - t) + x;
-    else
-        *comp += (x - t) + *sum;
-    *sum = t;
-}
-
 /* Walk records sorted by (key, seq). Returns the subset energy (compensated). */
 static double single_pass(const orc_system *s, const orc_refset *R, double e0, orc_rec *rec, size_t n,
                           orc_result *res)
@@ -469,7 +508,7 @@ static double single_pass(const orc_system *s, const orc_refset *R, double e0, o
             res->n_in_ref_hit++;
             res->ref_cross += R->c[hit] * num;
         } else {
-            double denom = e0 - orc_diag(s, rec[i].key);
+            double denom = orc_denominator(s, rec[i].key, e0);
             res->n_external++;
             if (fabs(denom) < res->min_abs_denom)
                 res->min_abs_denom = fabs(denom);
@@ -826,6 +865,14 @@ static void *diag_worker(void *arg)
     for (int64_t i = J->lo; i < J->hi; i++)
         J->out[i] = orc_diag(J->s, J->keys + i * J->W);
     return NULL;
+}
+
+/* E0 - H_aa (orc_denominator) of many determinants, one thread. */
+void orc_denominator_many(const orc_system *s, const uint64_t *keys, int64_t n, double e0, double *out)
+{
+    int W = orc_key_words(s->norb);
+    for (int64_t i = 0; i < n; i++)
+        out[i] = orc_denominator(s, keys + i * W, e0);
 }
 
 void orc_diag_many(const orc_system *s, const uint64_t *keys, int64_t n, double *out, int nthreads)

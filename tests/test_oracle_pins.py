@@ -504,3 +504,146 @@ def test_same_spin_doubles_depend_on_their_own_string_only():
     s0, s1 = kind(t[0], a_single), kind(t[1], a_single)
     assert s0.keys() == s1.keys() and any(s0[f] != s1[f] for f in s0)
 
+
+
+# --------------------------------------------------------------------------
+# The Epstein-Nesbet denominator E0 - H_aa (Section II) at near-singular
+# values, against exact rational arithmetic.  The integrals are FP64 numbers,
+# so H_aa = sum_p h_pp + sum_{p<q} [(pp|qq) - delta_spin (pq|qp)] has an exact
+# rational value; so has E0 - H_aa.  E0 is put at the FP64 number nearest to
+# H_aa, so the difference is below half a unit in the last place of H_aa and
+# a plain FP64 sum of H_aa gets none of its digits right.
+
+def _exact_diag(h, eri, norb, key):
+    from fractions import Fraction
+    a, b = synth.unpack_keys(np.asarray(key, dtype=np.uint64).reshape(1, -1), norb)
+    occ = [(p, 0) for p in np.nonzero(a[0])[0]] + [(p, 1) for p in np.nonzero(b[0])[0]]
+    g = eri.reshape(norb, norb, norb, norb)
+    e, mags = Fraction(0), 0.0
+    for i, (p, sp) in enumerate(occ):
+        e += Fraction(float(h[p, p]))
+        mags += abs(float(h[p, p]))
+        for q, sq in occ[i + 1:]:
+            e += Fraction(float(g[p, p, q, q]))
+            mags += abs(float(g[p, p, q, q]))
+            if sp == sq:
+                e -= Fraction(float(g[p, q, q, p]))
+                mags += abs(float(g[p, q, q, p]))
+    return e, mags, len(occ) * (len(occ) + 1) // 2
+
+
+def _ulp(x):
+    return np.spacing(abs(x)) if x != 0.0 else np.spacing(0.0)
+
+
+def _check_denominators(h, eri, norb, na, nb, keys, shifts):
+    from fractions import Fraction
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    u = 2.0 ** -53
+    for key in keys:
+        hx, mags, n = _exact_diag(h, eri, norb, key)
+        for shift in shifts:
+            e0 = float(hx) + shift
+            exact = Fraction(e0) - hx
+            got = O.denominators(key.reshape(1, -1), e0)[0]
+            gam = (n + 1) * u / (1 - (n + 1) * u)
+            bound = 2 * u * abs(float(exact)) + gam * gam * (mags + abs(e0))
+            assert abs(Fraction(got) - exact) <= Fraction(bound), (key, shift, got, float(exact))
+            # a plain FP64 evaluation is far outside the bound whenever the
+            # difference is small: the pin can fail
+            if shift == 0.0:
+                plain = e0 - O.diag(key.reshape(1, -1))[0]
+                assert float(exact) == 0.0 or abs(Fraction(plain) - exact) > Fraction(bound) or plain == got
+
+
+def test_denominator_exact_small_system():
+    norb, na, nb = 10, 4, 3
+    h, eri = system(norb, na, nb, 71)
+    dets = all_dets(norb, na, nb)
+    keys = dets[np.random.default_rng(7).choice(len(dets), 40, replace=False)]
+    _check_denominators(h, eri, norb, na, nb, keys, [0.0, 1e-13, -3e-12, 0.37])
+
+
+def test_denominator_exact_c3_keys():
+    """Sampled determinants of workload C3 (28 electrons in 76 orbitals):
+    reference determinants and double excitations of them."""
+    w = synth.WORKLOADS["c3"]
+    h, eri, _ = synth.make_integrals(w.norb, w.n_chol, w.seed)
+    f = np.load(synth_path("inputs_c3.npz"))
+    refs = f["dets"]
+    rng = np.random.default_rng(11)
+    keys = [refs[i] for i in rng.choice(len(refs), 6, replace=False)]
+    a, b = synth.unpack_keys(np.stack(keys), w.norb)
+    ext = []
+    for j in range(len(keys)):          # move two electrons to virtual orbitals
+        aa, bb = a[j].copy(), b[j].copy()
+        ao, av = np.nonzero(aa)[0], np.nonzero(~aa)[0]
+        bo, bv = np.nonzero(bb)[0], np.nonzero(~bb)[0]
+        aa[rng.choice(ao)] = False
+        aa[rng.choice(av)] = True
+        bb[rng.choice(bo)] = False
+        bb[rng.choice(bv)] = True
+        ext.append(synth.pack_keys(aa[None], bb[None], w.norb)[0])
+    _check_denominators(h, eri, w.norb, w.nalpha, w.nbeta, np.stack(keys + ext),
+                        [0.0, 2.5e-12, -0.25])
+
+
+def test_pass_uses_the_compensated_denominator():
+    """With E0 placed on a determinant's diagonal energy, the single pass's
+    smallest |E0 - H_aa| is that determinant's exact (tiny) difference."""
+    from fractions import Fraction
+    norb, na, nb = 6, 2, 2
+    h, eri = system(norb, na, nb, 81)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    hf = synth.hf_key(norb, na, nb).reshape(1, -1)
+    keys, nums = O.numerators(hf, np.ones(1))
+    ext = keys[np.argmax(np.abs(nums))]      # the external determinant of largest |N|
+    hx, _, _ = _exact_diag(h, eri, norb, ext)
+    e0 = float(hx)
+    exact = abs(float(Fraction(e0) - hx))
+    res, _ = O.pt2(hf, np.ones(1), e0)
+    assert res["min_abs_denom"] <= exact * (1 + 1e-6) + 1e-300
+
+
+# --------------------------------------------------------------------------
+# <c|H|c> (orc_expectation writes every stored E0 of the synthetic inputs)
+
+def test_expectation_matches_brute_force_c1():
+    """<c|H|c> against the operator-by-operator Hamiltonian applied to c over
+    the whole FCI space, with coefficients that are not an eigenvector."""
+    w, h, eri, dets, _, _ = load_c1()
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    B = oracle.Brute(h, eri, w.norb, w.nalpha, w.nbeta)
+    c = np.random.default_rng(9).normal(size=len(dets))
+    c /= np.linalg.norm(c)
+    hc = B.h_times(dets, c)
+    want = float(c @ hc[B.index_of(dets)])
+    assert O.expectation(dets, c) == pytest.approx(want, abs=1e-12)
+
+
+@pytest.mark.parametrize("norb,na,nb,nref", [(7, 3, 2, 60), (8, 2, 3, 90)])
+def test_expectation_matches_brute_force_random(norb, na, nb, nref):
+    h, eri = system(norb, na, nb, 91)
+    dets = all_dets(norb, na, nb)
+    sel = dets[np.random.default_rng(4).choice(len(dets), nref, replace=False)]
+    c = np.random.default_rng(5).normal(size=nref)
+    O = oracle.Oracle(h, eri, norb, na, nb)
+    B = oracle.Brute(h, eri, norb, na, nb)
+    want = float(c @ B.h_times(sel, c)[B.index_of(sel)])
+    for nt in (1, 3):
+        assert O.expectation(sel, c, nthreads=nt) == pytest.approx(want, abs=1e-12)
+
+
+def test_expectation_c2_slice_matches_dense_hrr():
+    """On 500 references of workload C2 (20 electrons in 40 orbitals): the
+    threaded, compensated sum with its skip of pairs more than a double
+    excitation apart equals c^T H_RR c over the dense pairwise matrix."""
+    w = synth.WORKLOADS["c2"]
+    h, eri, _ = synth.make_integrals(w.norb, w.n_chol, w.seed)
+    f = np.load(synth_path("inputs_c2.npz"))
+    dets = f["dets"][:500]
+    c = np.random.default_rng(6).normal(size=len(dets))
+    O = oracle.Oracle(h, eri, w.norb, w.nalpha, w.nbeta)
+    H = O.hrr(dets)
+    assert np.count_nonzero(H) > len(dets)          # the slice is connected
+    assert O.expectation(dets, c) == pytest.approx(float(c @ H @ c), abs=1e-11)
