@@ -154,7 +154,7 @@ struct Small {  // one device block for small control data
     uint64_t hist[MAX_DIG * 256];
     uint64_t bucket[MAX_DIG * 256];
     Partial partials[RED_GRID];
-    uint32_t coll[RED_GRID];  // hash records: workgroups with collided segments
+    CollList coll[RED_GRID];  // hash records: collided segments per single-pass workgroup
     Partial result;
     unsigned long long n_out;
 };
@@ -166,7 +166,7 @@ struct Workspace {
     Buf refK;                // the references' rank keys (same order) when records carry them
     Buf tref;                // reference range of every single-pass tile
     Buf refH0, refH1;        // hash records: reference hashes with indices (sort ping-pong)
-    Buf hp, gv;              // hash records: energy and g vector of every reference
+    Buf hp, gv;              // hash records: E0 - energy and g vector of every reference (double-double)
     Buf refX;                // hash records: reference bitstrings record by record
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
@@ -258,7 +258,7 @@ struct pt2_ctx {
     int norb, na, nb, W;
     int topb;  // bytes of the last key plane of a record
     Alloc A;
-    Buf h, V, h32, V32, T, R, binom;
+    Buf h, V, h32, V32, T, Tlo, R, binom;
     DevSys sys;
     ExcLayout L;
     hipStream_t stream = nullptr;
@@ -809,12 +809,12 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         const int nso = 2 * c->norb;
         if ((rc = buf_ensure(ws.A, ws.refH0, planes_bytes(1, J.n, 8, 8))) ||
             (rc = buf_ensure(ws.A, ws.refH1, planes_bytes(1, J.n, 8, 8))) ||
-            (rc = buf_ensure(ws.A, ws.hp, (size_t)J.n * 8)) ||
-            (rc = buf_ensure(ws.A, ws.gv, (size_t)J.n * nso * 8)) ||
+            (rc = buf_ensure(ws.A, ws.hp, (size_t)J.n * 16)) ||
+            (rc = buf_ensure(ws.A, ws.gv, (size_t)J.n * nso * 16)) ||
             (rc = buf_ensure(ws.A, ws.refX, (size_t)J.n * (c->W == 3 ? 4 : c->W) * 8)))
             return rc;
         HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
-        HIPCHK(launch_parent_g(sys, refs, J.n, (double *)ws.hp.p, (double *)ws.gv.p, st));
+        HIPCHK(launch_parent_g(sys, refs, J.n, J.e0, (double *)ws.hp.p, (double *)ws.gv.p, st));
     }
     // subtraction form: sum_i c_i^2 (E0 - H_ii), removed from the total below
     double ref_terms = 0.0;
@@ -837,15 +837,30 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         mx = std::max(mx, s);
     uint32_t key_bits = (uint32_t)RL.bits;
     if (RL.hash) {
-        // sort on as few hash bits as keep the expected number of colliding
-        // pairs in the largest subset, N^2 / 2^(b+1), at 256 or fewer: each
-        // byte less is a digit pass less, and collided runs are resolved
-        // exactly (a few workgroups revisited)
+        // sort on the hash bits that take the fewest digit passes while the
+        // expected number of colliding pairs in the largest subset,
+        // N^2 / 2^(b+1), stays at 256 or fewer; among choices with equal
+        // passes, the most bits (collided runs are resolved exactly, but each
+        // costs a revisit of its workgroup's records).  The subset fixes the
+        // top log2p bits of the hash, so a top byte inside them is a digit
+        // with one value, which the sort skips: with 512 subsets, 64 bits take
+        // the passes of 56.
         int b = 64;
         if (c->opt.hash_bits == 0) {
-            b = 32;
-            while (b < 64 && (double)mx * (double)mx / std::ldexp(1.0, b + 1) > 256.0)
-                b += 8;
+            auto passes = [&](int bits) {
+                int np = 0;
+                for (int d = 0; d < bits / 8; d++)
+                    np += 8 * d >= 64 - P.log2p ? 0 : 1;
+                return np;
+            };
+            int best = 64;
+            for (int bits = 64; bits >= 32; bits -= 8) {
+                if ((double)mx * (double)mx / std::ldexp(1.0, bits + 1) > 256.0)
+                    break;
+                if (passes(bits) < passes(best))
+                    best = bits;
+            }
+            b = best;
             sys.kc.hash_mask = b >= 64 ? ~0ull : ((1ull << b) - 1);
         } else {
             b = c->opt.hash_bits >= 64 ? 64 : c->opt.hash_bits;
@@ -921,7 +936,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
         if (RL.hash)
-            HIPCHK(launch_reduce_hash(sys, fp32, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n, (const double *)ws.hp.p,
+            HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n, (const double *)ws.hp.p,
                                       (const double *)ws.gv.p, J.e0, subtract ? 0 : 1, ds->partials, ds->coll,
                                       &ds->flags, st));
         else
@@ -1572,14 +1587,22 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     const size_t n2 = n * n, n4 = n2 * n2, nso = 2 * n, ntri = nso * (nso + 1) / 2;
     // packed upper triangle over spin-orbitals b1 <= b2 (row b1 starts at
     // b1*nso - b1*(b1-1)/2, entry b2 - b1 within it)
-    std::vector<double> T(ntri, 0.0);
+    // Each entry is kept exactly as the pair (rounded difference, its exact
+    // rounding error): the denominators E0 - H_aa are formed in double-double
+    // arithmetic and must not inherit the rounding of (pp|qq) - (pq|qp).
+    std::vector<double> T(ntri, 0.0), Tlo(ntri, 0.0);
     for (size_t b1 = 0, o = 0; b1 < nso; b1++) {
         const size_t p = b1 < n ? b1 : b1 - n;
         T[o++] = h[p * n + p];
-        for (size_t b2 = b1 + 1; b2 < nso; b2++) {
+        for (size_t b2 = b1 + 1; b2 < nso; b2++, o++) {
             const size_t q = b2 < n ? b2 : b2 - n;
             const bool same = (b1 < n) == (b2 < n);
-            T[o++] = E(p, p, q, q) - (same ? E(p, q, q, p) : 0.0);
+            const double a = E(p, p, q, q), b = same ? -E(p, q, q, p) : 0.0;
+            // two-sum: T + Tlo == a + b exactly
+            const double sum = a + b;
+            const double bb = sum - a;
+            T[o] = sum;
+            Tlo[o] = (a - (sum - bb)) + (b - bb);
         }
     }
     std::vector<uint64_t> R(nso);
@@ -1588,11 +1611,13 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         R[b] = splitmix_next(st);
     int rc;
     if ((rc = buf_alloc(c->A, c->h, n2 * 8)) || (rc = buf_alloc(c->A, c->V, n4 * 8)) ||
-        (rc = buf_alloc(c->A, c->T, ntri * 8)) || (rc = buf_alloc(c->A, c->R, nso * 8)))
+        (rc = buf_alloc(c->A, c->T, ntri * 8)) || (rc = buf_alloc(c->A, c->Tlo, ntri * 8)) ||
+        (rc = buf_alloc(c->A, c->R, nso * 8)))
         return rc;
     HIPCHK(hipMemcpy(c->h.p, h, n2 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->V.p, eri, n4 * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->T.p, T.data(), ntri * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->Tlo.p, Tlo.data(), ntri * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->R.p, R.data(), nso * 8, hipMemcpyHostToDevice));
     if (o.precision == PT2_FP32_ARITH) {
         std::vector<float> h32(n2), V32(n4);
@@ -1611,6 +1636,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.h32 = (const float *)c->h32.p;
     c->sys.V32 = (const float *)c->V32.p;
     c->sys.T = (const double *)c->T.p;
+    c->sys.Tlo = (const double *)c->Tlo.p;
     c->sys.R = (const uint64_t *)c->R.p;
     c->sys.z2 = o.spin_flip;
 
@@ -1840,7 +1866,7 @@ PT2_API int pt2_destroy(pt2_ctx *c)
             (void)hipStreamSynchronize(c->stream);
         c->ws.release();
         buf_free(c->A, c->h), buf_free(c->A, c->V), buf_free(c->A, c->h32), buf_free(c->A, c->V32);
-        buf_free(c->A, c->T), buf_free(c->A, c->R), buf_free(c->A, c->binom);
+        buf_free(c->A, c->T), buf_free(c->A, c->Tlo), buf_free(c->A, c->R), buf_free(c->A, c->binom);
         if (c->own_stream && c->stream)
             (void)hipStreamDestroy(c->stream);
     }

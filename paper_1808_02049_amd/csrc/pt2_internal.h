@@ -95,6 +95,7 @@ struct DevSys {
     const double *T;    // packed upper-triangular spin-orbital pair table for the
                         // diagonal, row b1 at b1*nso - b1*(b1-1)/2 - b1, column b2 >= b1:
                         // T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin](pq|qp)
+    const double *Tlo;  // the exact rounding error of each T entry (T + Tlo is exact)
     const uint64_t *R;  // Zobrist words, one per bit (2 norb)
     int z2;             // spin flip: generate alpha >= beta only, weight alpha != beta by 2
 };
@@ -202,6 +203,16 @@ __device__ inline void pl_put(const Planes &p, int w, int64_t i, uint64_t v)
     else
         ((uint16_t *)b)[i] = (uint16_t)v;
 }
+
+// Hash records: the collided segments (runs of one hash holding more than one
+// determinant) a single-pass workgroup found, by the index of their last
+// record, ascending; n > COLL_LIST means the list overflowed and the
+// workgroup's whole record range is revisited.
+constexpr int COLL_LIST = 8;
+struct CollList {
+    uint32_t n, pad;
+    int64_t tail[COLL_LIST];
+};
 
 // Per-block partial of the single pass; summed in block order.
 struct Partial {
@@ -424,15 +435,19 @@ hipError_t launch_check_swap(const DevSys &s, const Planes &refs, int64_t n, Fla
 // Rank keys of sorted bitstring references (planes of kw words + coefficients).
 hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
 // Hash records: the references' hashes with their indices (planes: 1 key word
-// with 8-byte top, u64 payload), sorted afterwards by hash; per-reference
-// energies Hp and g vectors G (nref x 2 norb); the single pass.
+// with 8-byte top, u64 payload), sorted afterwards by hash; per reference
+// E0 minus its energy (D0) and its g vector G (nref x 2 norb), double-double;
+// the single pass.
 hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
-hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st);
+// D0[p] = E0 - H_pp and G[p][x] as double-double pairs (hi, lo).
+hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double e0, double *D0, double *G,
+                           hipStream_t st);
 // The references' bitstrings record by record, 2^ceil(log2 W) words each.
 hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ra, hipStream_t st);
-hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
-                              int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st);
+// pm: the payload mode (PM_*), which sets the FP32 rounding bound.
+hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
+                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
+                              int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
 // Inspection: unique keys and numerators (n_out on device).

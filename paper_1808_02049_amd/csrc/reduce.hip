@@ -8,9 +8,18 @@
 // duplicate-removal subsection of Section V), but per distinct bitstring and
 // against only the few reference bitstrings that fall inside the tile's key
 // range, staged in LDS: the sorted records and the sorted reference list are
-// merged tile by tile.  H_aa is evaluated from scratch from a spin-orbital pair
-// table (packed upper triangle, in LDS when it fits), sum over occupied pairs
-// b1 <= b2 of T[b1][b2].
+// merged tile by tile.  H_aa comes from a spin-orbital pair table (packed
+// upper triangle, in LDS when it fits), sum over occupied pairs b1 <= b2 of
+// T[b1][b2], taken relative to an anchor determinant.
+//
+// The denominator E0 - H_aa is formed in double-double arithmetic: E0 and
+// H_aa are of order 10^2 Eh while their difference can be 10^-6 Eh or less,
+// and such a determinant's term moves by its own size for every relative
+// change of the difference.  Every summand is an exact FP64 number (the pair
+// table carries each entry's rounding error beside it), the anchor's g vector
+// and E0 - E(anchor) are double-double, and the per-key combination adds the
+// pairs with the two-sum error-free transformation, so the difference is
+// exact to a few units in its own last place.
 //
 // A fixed grid of RED_GRID workgroups takes contiguous ranges of tiles; a
 // workgroup owns the segments whose first record lies in its tiles, follows a
@@ -101,50 +110,33 @@ __device__ inline uint64_t key_mix(const uint64_t (&k)[W])
 // of b1 starts at tri_row(b1) and is indexed by b2.
 __host__ __device__ inline int tri_row(int b1, int nso) { return b1 * nso - (b1 * (b1 - 1)) / 2 - b1; }
 
-// H_aa = sum over occupied spin-orbital pairs b1 <= b2 of T[b1][b2]
-// (T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin] (pq|qp)); two
-// independent accumulators per row keep two table reads in flight.
-template <int W>
-__device__ inline double diag_packed(const double *Tp, int nso, const uint64_t (&k)[W])
+// Double-double accumulator: the exact value is hi + lo.  Knuth's two-sum
+// gives the exact rounding error of each addition.
+struct DD {
+    double hi, lo;
+};
+
+__device__ inline double two_sum(double a, double b, double &err)
 {
-    double e = 0.0;
-#pragma unroll
-    for (int w1 = 0; w1 < W; w1++) {
-        uint64_t m1 = k[w1];
-        while (m1) {
-            const int b1 = w1 * 64 + __builtin_ctzll(m1);
-            m1 &= m1 - 1;
-            const double *row = Tp + tri_row(b1, nso);
-            double a0 = row[b1], a1 = 0.0;
-            uint64_t m2 = m1;
-            while (m2) {
-                const int q0 = w1 * 64 + __builtin_ctzll(m2);
-                m2 &= m2 - 1;
-                a0 += row[q0];
-                if (m2) {
-                    const int q1 = w1 * 64 + __builtin_ctzll(m2);
-                    m2 &= m2 - 1;
-                    a1 += row[q1];
-                }
-            }
-#pragma unroll
-            for (int w2 = w1 + 1; w2 < W; w2++) {
-                uint64_t m3 = k[w2];
-                while (m3) {
-                    const int q0 = w2 * 64 + __builtin_ctzll(m3);
-                    m3 &= m3 - 1;
-                    a0 += row[q0];
-                    if (m3) {
-                        const int q1 = w2 * 64 + __builtin_ctzll(m3);
-                        m3 &= m3 - 1;
-                        a1 += row[q1];
-                    }
-                }
-            }
-            e += a0 + a1;
-        }
-    }
-    return e;
+    const double s = a + b;
+    const double bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+// x += (vh + vl)
+__device__ inline void dd_add(DD &x, double vh, double vl)
+{
+    double e;
+    x.hi = two_sum(x.hi, vh, e);
+    x.lo += e + vl;
+}
+
+__device__ inline DD dd_sum(const DD &x, const DD &y)
+{
+    DD r = x;
+    dd_add(r, y.hi, y.lo);
+    return r;
 }
 
 __device__ inline double tri_at(const double *Tp, int nso, int b1, int b2)
@@ -153,15 +145,57 @@ __device__ inline double tri_at(const double *Tp, int nso, int b1, int b2)
     return Tp[tri_row(lo, nso) + hi];
 }
 
-// H_aa relative to an anchor determinant S0 with known energy E0 and
-// g_x = h_x + sum_{c in S0, c != x} T[x][c]: with R the spin-orbitals removed
-// from S0 and A those added,
-//   H = E0 - sum_R g_r + sum_A g_a + sum_{r<r' in R} T + sum_{a<a' in A} T
-//       - sum_{a in A, r in R} T[a][r].
+// x += sign * T[b1][b2] (both parts; the low part is zero for pairs of
+// opposite spin and for the diagonal, so it is read only for same-spin pairs)
+__device__ inline void dd_add_pair(DD &x, const double *Tp, const double *Tl, int nso, int b1, int b2, double sign)
+{
+    const int lo = b1 < b2 ? b1 : b2, hi = b1 < b2 ? b2 : b1;
+    const int at = tri_row(lo, nso) + hi;
+    const bool same = (lo < nso / 2) == (hi < nso / 2) && lo != hi;
+    dd_add(x, sign * Tp[at], same ? sign * Tl[at] : 0.0);
+}
+
+// E0 - H_aa from scratch: E0 minus every occupied pair b1 <= b2 of T, in
+// double-double.
+template <int W>
+__device__ inline double den_scratch(const double *Tp, const double *Tl, int nso, const uint64_t (&k)[W], double e0)
+{
+    DD d = {e0, 0.0};
+#pragma unroll
+    for (int w1 = 0; w1 < W; w1++) {
+        uint64_t m1 = k[w1];
+        while (m1) {
+            const int b1 = w1 * 64 + __builtin_ctzll(m1);
+            m1 &= m1 - 1;
+            dd_add(d, -Tp[tri_row(b1, nso) + b1], 0.0);
+            uint64_t m2 = m1;
+            while (m2) {
+                dd_add_pair(d, Tp, Tl, nso, b1, w1 * 64 + __builtin_ctzll(m2), -1.0);
+                m2 &= m2 - 1;
+            }
+#pragma unroll
+            for (int w2 = w1 + 1; w2 < W; w2++) {
+                uint64_t m3 = k[w2];
+                while (m3) {
+                    dd_add_pair(d, Tp, Tl, nso, b1, w2 * 64 + __builtin_ctzll(m3), -1.0);
+                    m3 &= m3 - 1;
+                }
+            }
+        }
+    }
+    return d.hi + d.lo;
+}
+
+// E0 - H_aa relative to an anchor determinant S0, given d0 = E0 - E(S0) and
+// g_x = h_x + sum_{c in S0, c != x} T[x][c] (both double-double; g as gh + gl):
+// with R the spin-orbitals removed from S0 and A those added,
+//   H = E(S0) - sum_R g_r + sum_A g_a + sum_{r<r' in R} T + sum_{a<a' in A} T
+//       - sum_{a in A, r in R} T[a][r],
+// so E0 - H = d0 + sum_R g_r - sum_A g_a - sum_RR T - sum_AA T + sum_AR T.
 // Falls back to the from-scratch sum when the difference is large.
 template <int W>
-__device__ inline double diag_anchor(const double *Tp, int nso, int nel, const uint64_t (&k)[W],
-                                     const uint64_t *anc, const double *g, double e_anc)
+__device__ inline double den_anchor(const double *Tp, const double *Tl, int nso, int nel, const uint64_t (&k)[W],
+                                    const uint64_t *anc, const double *gh, const double *gl, DD d0, double e0)
 {
     uint64_t rm[W], ad[W];
     int m = 0;
@@ -173,25 +207,25 @@ __device__ inline double diag_anchor(const double *Tp, int nso, int nel, const u
         m += __popcll(ad[w]);
     }
     if (2 * m * m + m >= (nel * nel) / 2)
-        return diag_packed<W>(Tp, nso, k);
-    double e = e_anc, pr = 0.0;
+        return den_scratch<W>(Tp, Tl, nso, k, e0);
+    DD d = d0;
 #pragma unroll
     for (int w1 = 0; w1 < W; w1++) {
         uint64_t x = rm[w1];
         while (x) {
             const int r = w1 * 64 + __builtin_ctzll(x);
             x &= x - 1;
-            e -= g[r];
+            dd_add(d, gh[r], gl[r]);
             uint64_t y = x;  // r < r' within R
             while (y) {
-                pr += tri_at(Tp, nso, r, w1 * 64 + __builtin_ctzll(y));
+                dd_add_pair(d, Tp, Tl, nso, r, w1 * 64 + __builtin_ctzll(y), -1.0);
                 y &= y - 1;
             }
 #pragma unroll
             for (int w2 = w1 + 1; w2 < W; w2++) {
                 uint64_t z = rm[w2];
                 while (z) {
-                    pr += tri_at(Tp, nso, r, w2 * 64 + __builtin_ctzll(z));
+                    dd_add_pair(d, Tp, Tl, nso, r, w2 * 64 + __builtin_ctzll(z), -1.0);
                     z &= z - 1;
                 }
             }
@@ -199,7 +233,7 @@ __device__ inline double diag_anchor(const double *Tp, int nso, int nel, const u
             for (int w2 = 0; w2 < W; w2++) {
                 uint64_t z = ad[w2];  // cross pairs with A
                 while (z) {
-                    pr -= tri_at(Tp, nso, r, w2 * 64 + __builtin_ctzll(z));
+                    dd_add_pair(d, Tp, Tl, nso, r, w2 * 64 + __builtin_ctzll(z), 1.0);
                     z &= z - 1;
                 }
             }
@@ -211,23 +245,23 @@ __device__ inline double diag_anchor(const double *Tp, int nso, int nel, const u
         while (x) {
             const int a = w1 * 64 + __builtin_ctzll(x);
             x &= x - 1;
-            e += g[a];
+            dd_add(d, -gh[a], -gl[a]);
             uint64_t y = x;
             while (y) {
-                pr += tri_at(Tp, nso, a, w1 * 64 + __builtin_ctzll(y));
+                dd_add_pair(d, Tp, Tl, nso, a, w1 * 64 + __builtin_ctzll(y), -1.0);
                 y &= y - 1;
             }
 #pragma unroll
             for (int w2 = w1 + 1; w2 < W; w2++) {
                 uint64_t z = ad[w2];
                 while (z) {
-                    pr += tri_at(Tp, nso, a, w2 * 64 + __builtin_ctzll(z));
+                    dd_add_pair(d, Tp, Tl, nso, a, w2 * 64 + __builtin_ctzll(z), -1.0);
                     z &= z - 1;
                 }
             }
         }
     }
-    return e + pr;
+    return d.hi + d.lo;
 }
 
 __device__ inline void neumaier(double &sum, double &comp, double x)
@@ -261,15 +295,16 @@ struct RefSlice {
 
 // One distinct bitstring with its numerator: exclusion test, then the term.
 struct Anchor {
-    const uint64_t *key;  // LDS, W words
-    const double *g;      // LDS, nso entries
-    double e;
+    const uint64_t *key;    // LDS, W words
+    const double *gh, *gl;  // LDS, nso entries each: the g vector, double-double
+    DD d0;                  // E0 - E(anchor)
 };
 
 // k is the record key (W words); the diagonal and the checksum use the
 // bitstring (WB words), which is k itself or, for rank keys, unranked from it.
 template <int W, int WB, bool RK>
-__device__ inline void process_segment(const DevSys &s, const double *Tp, const Anchor &an, const Planes &refs,
+__device__ inline void process_segment(const DevSys &s, const double *Tp, const double *Tl, const Anchor &an,
+                                       const Planes &refs,
                                        const RefSlice &rs, const uint64_t *s_rk, const double *s_rc, double e0,
                                        const uint64_t (&k)[W], double num, Acc &a, const uint64_t *binom,
                                        bool search)
@@ -331,8 +366,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
         for (int w = 0; w < WB; w++)
             kb[w] = k[w < W ? w : 0];
     }
-    const double haa = diag_anchor<WB>(Tp, 2 * s.norb, s.na + s.nb, kb, an.key, an.g, an.e);
-    const double den = e0 - haa;
+    const double den = den_anchor<WB>(Tp, Tl, 2 * s.norb, s.na + s.nb, kb, an.key, an.gh, an.gl, an.d0, e0);
     a.n_ext++;
     const double ad = fabs(den);
     a.min_abs = ad < a.min_abs ? ad : a.min_abs;
@@ -415,7 +449,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
     __shared__ uint64_t s_anc[WB];
-    __shared__ double s_er[RED_THREADS / 64];
+    __shared__ double s_er[RED_THREADS / 64], s_erl[RED_THREADS / 64];
     __shared__ Partial s_wp[RED_THREADS / 64];
 
     const int nso = 2 * s.norb;
@@ -424,12 +458,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     // its tile (the key is read back from the tile, which is in the caches)
     double *q_num = (double *)dyn;                            // [RED_Q]
     uint32_t *q_idx = (uint32_t *)(dyn + (size_t)RED_Q * 8);  // [RED_Q]
-    // g vector of the tile's anchor (nso entries) after the queue region
+    // g vector of the tile's anchor (nso entries, high then low parts) after
+    // the queue region
     double *s_g = (double *)(dyn + q_bytes);
+    double *s_gl = s_g + nso;
     const double *Tp = s.T;
+    const double *Tl = s.Tlo;
     const int ntri = nso * (nso + 1) / 2;
     if (lds_table) {
-        double *t = (double *)(dyn + q_bytes + (size_t)nso * 8);
+        double *t = (double *)(dyn + q_bytes + (size_t)nso * 16);
         for (int i = tid; i < ntri; i += RED_THREADS)
             t[i] = s.T[i];
         Tp = t;
@@ -437,7 +474,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     // binomial table for unranking rank keys, after the pair table
     uint64_t *binom = nullptr;
     if constexpr (RK) {
-        binom = (uint64_t *)(dyn + q_bytes + (size_t)nso * 8 + (lds_table ? (size_t)ntri * 8 : 0));
+        binom = (uint64_t *)(dyn + q_bytes + (size_t)nso * 16 + (lds_table ? (size_t)ntri * 8 : 0));
         const int nb = (s.norb + 1) * s.kc.stride;
         for (int i = tid; i < nb; i += RED_THREADS)
             binom[i] = s.kc.binom[i];
@@ -499,36 +536,41 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         }
         __syncthreads();
         // anchor of this tile = its first record: g_x for every spin-orbital x
-        // and the anchor's own energy as a sum of per-row partials
+        // and twice the anchor's energy, sum over its occupied x of h_x + g_x
+        // (each pair counted from both ends), all double-double
         {
-            double gx = 0.0, rowx = 0.0;
+            DD ex = {0.0, 0.0};
             if (tid < nso) {
                 const int bx = tid;
                 const bool occ = (s_anc[bx >> 6] >> (bx & 63)) & 1ull;
                 const double hx = Tp[tri_row(bx, nso) + bx];
-                gx = hx;
-                rowx = occ ? hx : 0.0;
+                DD gx = {hx, 0.0};
 #pragma unroll
                 for (int w = 0; w < WB; w++) {
                     uint64_t m = s_anc[w];
                     while (m) {
                         const int c = w * 64 + __builtin_ctzll(m);
                         m &= m - 1;
-                        if (c == bx)
-                            continue;
-                        const double t = tri_at(Tp, nso, bx, c);
-                        gx += t;
-                        if (occ && c > bx)
-                            rowx += t;
+                        if (c != bx)
+                            dd_add_pair(gx, Tp, Tl, nso, bx, c, 1.0);
                     }
                 }
-                s_g[bx] = gx;
+                s_g[bx] = gx.hi;
+                s_gl[bx] = gx.lo;
+                if (occ) {
+                    ex = gx;
+                    dd_add(ex, hx, 0.0);
+                }
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1)
-                rowx += __shfl_down(rowx, o);
-            if (lane == 0)
-                s_er[wave] = rowx;
+            for (int o = 32; o >= 1; o >>= 1) {
+                const DD y = {__shfl_down(ex.hi, o), __shfl_down(ex.lo, o)};
+                ex = dd_sum(ex, y);
+            }
+            if (lane == 0) {
+                s_er[wave] = ex.hi;
+                s_erl[wave] = ex.lo;
+            }
         }
         RefSlice rs;
         rs.lo = s_lo, rs.hi = s_hi;
@@ -689,15 +731,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         const int qn = (int)qtot + cflag;
         Anchor an;
         an.key = s_anc;
-        an.g = s_g;
-        an.e = 0.0;
+        an.gh = s_g;
+        an.gl = s_gl;
+        {
+            DD e2 = {0.0, 0.0};  // 2 E(anchor)
 #pragma unroll
-        for (int w = 0; w < RED_THREADS / 64; w++)
-            an.e += s_er[w];
+            for (int w = 0; w < RED_THREADS / 64; w++)
+                dd_add(e2, s_er[w], s_erl[w]);
+            an.d0.hi = e0, an.d0.lo = 0.0;
+            dd_add(an.d0, -0.5 * e2.hi, -0.5 * e2.lo);
+        }
         for (int e = tid; e < qn; e += RED_THREADS) {
             uint64_t kk[W];
             load_key<W>(in, base + q_idx[e], kk);
-            process_segment<W, WB, RK>(s, Tp, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom, search != 0);
+            process_segment<W, WB, RK>(s, Tp, Tl, an, refs, rs, s_rk, s_rc, e0, kk, q_num[e], a, binom,
+                                       search != 0);
         }
         __syncthreads();
     }
@@ -763,7 +811,7 @@ __global__ __launch_bounds__(256) void k_ref_terms(DevSys s, Planes refs, int64_
         uint64_t k[W];
         load_key<W>(refs, i, k);
         const double ci = ((const double *)refs.pay)[i];
-        neumaier(sum, comp, ci * ci * (e0 - diag_packed<W>(s.T, 2 * s.norb, k)));
+        neumaier(sum, comp, ci * ci * den_scratch<W>(s.T, s.Tlo, 2 * s.norb, k, e0));
     }
     s_s[threadIdx.x] = sum;
     s_c[threadIdx.x] = comp;
@@ -812,52 +860,62 @@ __global__ void k_refs_hash(DevSys s, Planes bits, int64_t n, Planes out)
     }
 }
 
-// Per reference p: its energy Hp[p] and g[p][x] = h_x + sum_{c in p, c != x} T[x][c]
-// for every spin-orbital x (one workgroup per reference, one thread per x).
+// Per reference p, double-double: D0[p] = E0 - H_pp (at 2p, 2p+1) and
+// g[p][x] = h_x + sum_{c in p, c != x} T[x][c] for every spin-orbital x (at
+// 2(p nso + x), +1), one workgroup per reference, one thread per x.  The
+// energy is half the sum over occupied x of h_x + g_x (every pair is counted
+// from both ends).
 template <int WB>
-__global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t n, double *Hp, double *G)
+__global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t n, double e0, double *D0, double *G)
 {
     __shared__ uint64_t s_k[WB];
-    __shared__ double s_row[256 / 64];
+    __shared__ double s_row[256 / 64], s_rowl[256 / 64];
     const int nso = 2 * s.norb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
         if (tid < WB)
             s_k[tid] = pl_get<WB>(bits, tid, p);
         __syncthreads();
-        double rowx = 0.0;
+        DD ex = {0.0, 0.0};
         if (tid < nso) {
             const int bx = tid;
             const bool occ = (s_k[bx >> 6] >> (bx & 63)) & 1ull;
             const double hx = s.T[tri_row(bx, nso) + bx];
-            double gx = hx;
-            rowx = occ ? hx : 0.0;
+            DD gx = {hx, 0.0};
 #pragma unroll
             for (int w = 0; w < WB; w++) {
                 uint64_t m = s_k[w];
                 while (m) {
                     const int c = w * 64 + __builtin_ctzll(m);
                     m &= m - 1;
-                    if (c == bx)
-                        continue;
-                    const double t = tri_at(s.T, nso, bx, c);
-                    gx += t;
-                    if (occ && c > bx)
-                        rowx += t;
+                    if (c != bx)
+                        dd_add_pair(gx, s.T, s.Tlo, nso, bx, c, 1.0);
                 }
             }
-            G[p * nso + bx] = gx;
+            G[2 * (p * nso + bx)] = gx.hi;
+            G[2 * (p * nso + bx) + 1] = gx.lo;
+            if (occ) {
+                ex = gx;
+                dd_add(ex, hx, 0.0);
+            }
         }
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1)
-            rowx += __shfl_down(rowx, o);
-        if (lane == 0)
-            s_row[wave] = rowx;
+        for (int o = 32; o >= 1; o >>= 1) {
+            const DD y = {__shfl_down(ex.hi, o), __shfl_down(ex.lo, o)};
+            ex = dd_sum(ex, y);
+        }
+        if (lane == 0) {
+            s_row[wave] = ex.hi;
+            s_rowl[wave] = ex.lo;
+        }
         __syncthreads();
         if (tid == 0) {
-            double e = 0.0;
+            DD e2 = {0.0, 0.0};
             for (int w = 0; w < 256 / 64; w++)
-                e += s_row[w];
-            Hp[p] = e;
+                dd_add(e2, s_row[w], s_rowl[w]);
+            DD d = {e0, 0.0};
+            dd_add(d, -0.5 * e2.hi, -0.5 * e2.lo);
+            D0[2 * p] = d.hi;
+            D0[2 * p + 1] = d.lo;
         }
         __syncthreads();
     }
@@ -916,11 +974,12 @@ __device__ inline void hash_key(const uint64_t *ra, uint64_t aux, uint64_t (&k)[
     }
 }
 
-// H_aa relative to the parent p (at most two spin-orbitals removed and two
-// added): Hp - sum_R g_r + sum_A g_a + sum_{r<r'} T + sum_{a<a'} T - sum_{a,r} T.
+// E0 - H_aa relative to the parent p (at most two spin-orbitals removed and
+// two added), double-double:
+//   D0[p] + sum_R g_r - sum_A g_a - sum_{r<r'} T - sum_{a<a'} T + sum_{a,r} T.
 template <int WB>
-__device__ inline double diag_parent(const double *Tp, int nso, const uint64_t (&k)[WB], const uint64_t *ra,
-                                     int64_t p, const double *G, double hp)
+__device__ inline double den_parent(const double *Tp, const double *Tl, int nso, const uint64_t (&k)[WB],
+                                    const uint64_t *ra, int64_t p, const double *G, const double *D0)
 {
     int rm[2], ad[2], nr = 0, na = 0;
     uint64_t pk[WB];
@@ -943,31 +1002,150 @@ __device__ inline double diag_parent(const double *Tp, int nso, const uint64_t (
             }
         }
     }
-    const double *g = G + p * nso;
-    double e = hp;
-    for (int i = 0; i < nr && i < 2; i++)
-        e -= g[rm[i]];
-    for (int i = 0; i < na && i < 2; i++)
-        e += g[ad[i]];
+    const double2 *g = (const double2 *)G + p * nso;
+    const double2 d0 = ((const double2 *)D0)[p];
+    DD d = {d0.x, d0.y};
+    for (int i = 0; i < nr && i < 2; i++) {
+        const double2 v = g[rm[i]];
+        dd_add(d, v.x, v.y);
+    }
+    for (int i = 0; i < na && i < 2; i++) {
+        const double2 v = g[ad[i]];
+        dd_add(d, -v.x, -v.y);
+    }
     if (nr == 2)
-        e += tri_at(Tp, nso, rm[0], rm[1]);
+        dd_add_pair(d, Tp, Tl, nso, rm[0], rm[1], -1.0);
     if (na == 2)
-        e += tri_at(Tp, nso, ad[0], ad[1]);
+        dd_add_pair(d, Tp, Tl, nso, ad[0], ad[1], -1.0);
     for (int i = 0; i < nr && i < 2; i++)
         for (int j = 0; j < na && j < 2; j++)
-            e -= tri_at(Tp, nso, ad[j], rm[i]);
-    return e;
+            dd_add_pair(d, Tp, Tl, nso, ad[j], rm[i], 1.0);
+    return d.hi + d.lo;
 }
 
 constexpr int HR_REFS = 256;  // reference hashes staged per workgroup
 
-// One distinct determinant of a hash segment: exclusion, then the term.
+__device__ inline int64_t eri_at(int n, int p, int q, int r, int t)
+{
+    return (((int64_t)p * n + q) * n + r) * n + t;
+}
+
 template <int WB>
-__device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const uint64_t *ra, const Planes &rh,
-                                     int64_t lo, int64_t hi,
-                                     const uint64_t *s_rh, const int64_t *s_ri, bool staged, uint64_t h,
-                                     const uint64_t (&k)[WB], int64_t parent, double num, const double *Hp,
-                                     const double *G, double e0, Acc &a, bool search)
+__device__ inline bool bit_set(const uint64_t (&k)[WB], int b)
+{
+    uint64_t w = k[0];
+#pragma unroll
+    for (int i = 1; i < WB; i++)
+        w = (b >> 6) == i ? k[i] : w;
+    return (w >> (b & 63)) & 1ull;
+}
+
+// (-1)^(occupied orbitals of spin sp strictly between orbitals x and y)
+template <int WB>
+__device__ inline int spin_phase(const uint64_t (&k)[WB], int norb, int sp, int x, int y)
+{
+    const int off = sp == 0 ? norb : 0, lo = (x < y ? x : y) + off + 1, hi = (x < y ? y : x) + off;
+    int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < WB; w++) {
+        const int s0 = w * 64;
+        uint64_t m = ~0ull;
+        if (lo > s0)
+            m = lo - s0 >= 64 ? 0ull : m & (~0ull << (lo - s0));
+        if (hi < s0 + 64)
+            m = hi <= s0 ? 0ull : m & ((1ull << (hi - s0)) - 1ull);
+        cnt += __popcll(k[w] & m);
+    }
+    return (cnt & 1) ? -1 : 1;
+}
+
+// H_ai c_i of one hash record in FP64, from its parent's bitstring and the
+// flipped spin-orbitals, by the Slater-Condon rules with the operations in
+// the order FP64 generation uses (so the value is that record's FP64
+// payload bit for bit):
+//   single r->a:        ph * [h_ra + sum_{j occ} (ra|jj) - sum_{j occ, same spin} (rj|ja)]
+//   same-spin r<q->a<b: ph(r->a) ph(q->b after r->a) [(ra|qb) - (rb|qa)]
+//   alpha r->a, beta q->b: ph_alpha ph_beta (ra|qb)
+template <int WB>
+__device__ inline double rec_value64(const DevSys &s, const uint64_t *ra, const double *coef, uint64_t aux)
+{
+    const int64_t p = (int64_t)(aux >> 32);
+    uint64_t pk[WB];
+    ref_bits<WB>(ra, p, pk);
+    const int n = s.norb;
+    const int f0 = (int)(aux & 0xFFu), f1 = (int)((aux >> 8) & 0xFFu);
+    const int f2 = (int)((aux >> 16) & 0xFFu), f3 = (int)((aux >> 24) & 0xFFu);
+    double v;
+    if (f2 == (int)FLIP_NONE) {
+        const int sp = f0 >= n ? 0 : 1, off = sp == 0 ? n : 0;
+        const int r = f0 - off, a = f1 - off;
+        double f = s.h[r * n + a];
+        const double *Vra = s.V + eri_at(n, r, a, 0, 0);
+        for (int t = 0; t < 2; t++) {
+            const int o2 = t == 0 ? n : 0;
+            for (int j = 0; j < n; j++) {
+                if (!bit_set<WB>(pk, o2 + j))
+                    continue;
+                f += Vra[j * n + j];
+                if (t == sp)
+                    f -= s.V[eri_at(n, r, j, j, a)];
+            }
+        }
+        v = (double)spin_phase<WB>(pk, n, sp, r, a) * f;
+    } else if (bit_set<WB>(pk, f1)) {
+        const int sp = f0 >= n ? 0 : 1, off = sp == 0 ? n : 0;
+        const int r = f0 - off, q = f1 - off, a = f2 - off, b = f3 - off;
+        const int ph1 = spin_phase<WB>(pk, n, sp, r, a);
+        int ph2 = spin_phase<WB>(pk, n, sp, q, b);
+        const int lo = q < b ? q : b, hi = q < b ? b : q;
+        if (r > lo && r < hi)
+            ph2 = -ph2;
+        if (a > lo && a < hi)
+            ph2 = -ph2;
+        const double d = s.V[eri_at(n, r, a, q, b)] - s.V[eri_at(n, r, b, q, a)];
+        v = (double)(ph1 * ph2) * d;
+    } else {
+        const int r = f0 - n, a = f1 - n, q = f2, b = f3;
+        const int ph = spin_phase<WB>(pk, n, 0, r, a) * spin_phase<WB>(pk, n, 1, q, b);
+        v = (double)ph * s.V[eri_at(n, r, a, q, b)];
+    }
+    return v * coef[p];
+}
+
+// FP32 payloads: a term whose numerator's storage rounding could move it by
+// more than REFINE_TOL gets its numerator again as the FP64 sum of its
+// records' FP64 payloads.  The rounding moves N by at most eps * sum |p_i|,
+// so the term by about 2 |N/d| eps sum |p_i|; the sum of |p_i| is read only
+// when |N/d| exceeds REFINE_RATIO.
+constexpr double REFINE_RATIO = 1e-3;
+constexpr double REFINE_TOL = 1e-11;
+
+template <int WB>
+__device__ inline double refine_num(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+                                    uint64_t h, int64_t tail, double num, double den, double eps)
+{
+    int64_t head = tail;
+    double absum = fabs((double)((const float *)in.pay)[tail]);
+    while (head > 0 && in.key[0][head - 1] == h) {
+        head--;
+        absum += fabs((double)((const float *)in.pay)[head]);
+    }
+    if (2.0 * fabs(num / den) * absum * eps <= REFINE_TOL)
+        return num;
+    double n64 = 0.0;
+    for (int64_t x = head; x <= tail; x++)
+        n64 += rec_value64<WB>(s, ra, (const double *)bits.pay, in.key[1][x]);
+    return n64;
+}
+
+// One distinct determinant of a hash segment: exclusion, then the term.
+// tail: index of the segment's last record (FP32 refinement); refine < 0: the
+// numerator is already FP64.
+template <int WB, int PB>
+__device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+                                     const Planes &rh, int64_t lo, int64_t hi, const uint64_t *s_rh, const int64_t *s_ri,
+                                     bool staged, uint64_t h, const uint64_t (&k)[WB], int64_t parent, int64_t tail,
+                                     double num, const double *D0, const double *G, Acc &a, bool search, double eps)
 {
     a.n_unique++;
     if (!search)
@@ -1004,8 +1182,11 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &bits, const 
             return;
         }
     }
-    const double haa = diag_parent<WB>(s.T, 2 * s.norb, k, ra, parent, G, Hp[parent]);
-    const double den = e0 - haa;
+    const double den = den_parent<WB>(s.T, s.Tlo, 2 * s.norb, k, ra, parent, G, D0);
+    if constexpr (PB == 4) {
+        if (tail >= 0 && den != 0.0 && fabs(num / den) > REFINE_RATIO)
+            num = refine_num<WB>(s, in, bits, ra, h, tail, num, den, eps);
+    }
     a.n_ext++;
     const double ad = fabs(den);
     a.min_abs = ad < a.min_abs ? ad : a.min_abs;
@@ -1098,19 +1279,21 @@ __device__ inline bool bits_eq(const uint64_t (&x)[WB], const uint64_t (&y)[WB])
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits,
                                                              const uint64_t *ra, Planes rh,
-                                                             int64_t nref, const double *Hp, const double *G,
-                                                             double e0, int64_t tiles_per_block, int search,
-                                                             Partial *partials, uint32_t *coll, Flags *flags)
+                                                             int64_t nref, const double *D0, const double *G,
+                                                             int64_t tiles_per_block, int search, double eps,
+                                                             Partial *partials, CollList *coll, Flags *flags)
 {
-    // queue of owned segment ends (hash, parent word, sum, collided); the
-    // block's partials reuse it at the end
-    constexpr size_t QB = (size_t)RED_Q * (8 + 8 + 8 + 4);
+    // queue of owned segment ends (hash, parent word, sum, collided, index of
+    // the last record relative to the tile); the block's partials reuse it at
+    // the end
+    constexpr size_t QB = (size_t)RED_Q * (8 + 8 + 8 + 4 + 4);
     constexpr size_t LB = QB > sizeof(Partial) * RED_THREADS ? QB : sizeof(Partial) * RED_THREADS;
     __shared__ __align__(16) char s_q[LB];
     uint64_t *q_h = (uint64_t *)s_q;
     uint64_t *q_a = q_h + RED_Q;
     double *q_v = (double *)(q_a + RED_Q);
     int *q_c = (int *)(q_v + RED_Q);
+    uint32_t *q_t = (uint32_t *)(q_c + RED_Q);
     __shared__ uint64_t s_rh[HR_REFS];
     __shared__ int64_t s_ri[HR_REFS];
     __shared__ int64_t s_lo, s_hi;
@@ -1119,7 +1302,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     __shared__ HashScan s_cont;
     __shared__ uint64_t s_ch;
     __shared__ int s_cflag;
-    __shared__ uint32_t s_coll;
+    __shared__ uint32_t s_ncoll;
+    __shared__ int64_t s_coll_t[COLL_LIST];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
@@ -1127,7 +1311,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     Acc a;
     acc_init(a);
     if (tid == 0)
-        s_coll = 0;
+        s_ncoll = 0;
     // references whose hash lies in the workgroup's hash range, staged in LDS
     // when few
     int64_t lo = 0, hi = 0;
@@ -1313,6 +1497,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 q_v[slot] = hh[j] ? run[j] : carry.v + run[j];
                 q_a[slot] = hh[j] ? rha[j] : carry.a;
                 q_c[slot] = hh[j] ? rc[j] : (carry.c | rc[j]);
+                q_t[slot] = (uint32_t)(idx - base);
                 slot++;
             }
         }
@@ -1343,8 +1528,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                     col |= __shfl_down(col, o);
                 }
                 total += v;  // lane 0 holds the sum of this step
-                if (m != ~0ull)
+                if (m != ~0ull) {
+                    pos += __builtin_ctzll(~m);  // equal records are a prefix of the lanes
                     break;
+                }
                 pos += 64;
             }
             if (lane == 0) {
@@ -1354,20 +1541,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 // the tile part compared neighbours, the continuation compares
                 // with the segment's first record
                 q_c[qtot] = s_cont.c | col;
+                q_t[qtot] = (uint32_t)(pos - 1 - base);
             }
         }
         __syncthreads();
         const int qn = (int)qtot + cflag;
         for (int e = tid; e < qn; e += RED_THREADS) {
             if (q_c[e]) {
-                s_coll = 1;
+                const uint32_t i = atomicAdd(&s_ncoll, 1u);
+                if (i < COLL_LIST)
+                    s_coll_t[i] = base + (int64_t)q_t[e];
                 continue;
             }
             uint64_t k0[WB];
             const uint64_t aux = q_a[e];
             hash_key<WB>(ra, aux, k0);
-            hash_key_term<WB>(s, bits, ra, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32), q_v[e], Hp,
-                              G, e0, a, search != 0);
+            hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32),
+                                  base + (int64_t)q_t[e], q_v[e], D0, G, a, search != 0, eps);
         }
         __syncthreads();
     }
@@ -1378,83 +1568,112 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     block_partial(s_p);
     if (tid == 0) {
         partials[blockIdx.x] = s_p[0];
-        coll[blockIdx.x] = s_coll;
+        // the collided segments in ascending order, so that the revisit sums
+        // them in an order independent of the threads' timing
+        const uint32_t nc = s_ncoll, m = nc < COLL_LIST ? nc : COLL_LIST;
+        for (uint32_t i = 1; i < m; i++)
+            for (uint32_t j = i; j > 0 && s_coll_t[j - 1] > s_coll_t[j]; j--) {
+                const int64_t t = s_coll_t[j];
+                s_coll_t[j] = s_coll_t[j - 1];
+                s_coll_t[j - 1] = t;
+            }
+        coll[blockIdx.x].n = nc;
+        for (uint32_t i = 0; i < m; i++)
+            coll[blockIdx.x].tail[i] = s_coll_t[i];
     }
 }
 
-// The collided segments of the workgroups k_reduce_hash marked (same record
-// ranges): each distinct determinant of such a segment, taken at its first
-// record, gets the sum of its records' payloads; the workgroup's partial is
-// merged into the one k_reduce_hash wrote.  Unmarked workgroups return at once.
+// Records [i, e) are one collided segment (one hash, several determinants):
+// each distinct determinant, taken at its first record, gets the sum of its
+// records' payloads (with FP32 payloads, of their FP64 values) and its term.
+template <int WB, int PB>
+__device__ inline void coll_segment(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+                                    const Planes &rh, int64_t nref, const double *D0, const double *G, int64_t i,
+                                    int64_t e, Acc &a, bool search)
+{
+    const uint64_t h = in.key[0][i];
+    for (int64_t x = i; x < e; x++) {
+        uint64_t kx[WB];
+        const uint64_t ax = in.key[1][x];
+        hash_key<WB>(ra, ax, kx);
+        bool seen = false;
+        for (int64_t y = i; y < x && !seen; y++) {
+            uint64_t ky[WB];
+            hash_key<WB>(ra, in.key[1][y], ky);
+            seen = bits_eq<WB>(ky, kx);
+        }
+        if (seen)
+            continue;
+        double nx = 0.0;
+        for (int64_t y = x; y < e; y++) {
+            uint64_t ky[WB];
+            const uint64_t ay = in.key[1][y];
+            hash_key<WB>(ra, ay, ky);
+            if (bits_eq<WB>(ky, kx))
+                nx += PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ay) : load_pay<PB>(in, y);
+        }
+        // references searched in global memory over the whole list
+        hash_key_term<WB, PB>(s, in, bits, ra, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), -1,
+                              nx, D0, G, a, search, 0.0);
+    }
+}
+
+// The collided segments k_reduce_hash listed, per workgroup: one thread per
+// listed segment (in ascending order), or, when a workgroup's list
+// overflowed, its whole record range again.  The workgroup's partial is
+// merged into the one k_reduce_hash wrote.  Workgroups with none return at
+// once.
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
-                                                                  const uint64_t *ra, Planes rh, int64_t nref, const double *Hp,
-                                                                  const double *G, double e0,
+                                                                  const uint64_t *ra, Planes rh, int64_t nref, const double *D0,
+                                                                  const double *G,
                                                                   int64_t tiles_per_block, int search, Partial *partials,
-                                                                  const uint32_t *coll, Flags *flags)
+                                                                  const CollList *coll, Flags *flags)
 {
     __shared__ Partial s_p[RED_THREADS];
-    if (coll[blockIdx.x] == 0)
+    const uint32_t ncoll = coll[blockIdx.x].n;
+    if (ncoll == 0)
         return;
     const int tid = threadIdx.x;
-    const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
-    const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
-    const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
-    const int64_t b0 = t_begin * RED_TILE;
-    const int64_t b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
     Acc a;
     acc_init(a);
-    for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
-        const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
-        for (int j = 0; j < RED_ITEMS; j++) {
-            const int64_t i = i0 + j;
-            if (i >= b1)
-                break;
-            const uint64_t h = in.key[0][i];
-            if (i > 0 && in.key[0][i - 1] == h)
-                continue;  // not a segment head
-            int64_t e = i;
-            while (e < n && in.key[0][e] == h)
-                e++;
-            uint64_t k0[WB];
-            hash_key<WB>(ra, in.key[1][i], k0);
-            bool collided = false;
-            for (int64_t y = i + 1; y < e && !collided; y++) {
-                uint64_t ky[WB];
-                hash_key<WB>(ra, in.key[1][y], ky);
-                for (int w = 0; w < WB; w++)
-                    collided = collided || ky[w] != k0[w];
-            }
-            if (!collided)
-                continue;  // k_reduce_hash took it
-            for (int64_t x = i; x < e; x++) {
-                uint64_t kx[WB];
-                const uint64_t ax = in.key[1][x];
-                hash_key<WB>(ra, ax, kx);
-                bool seen = false;
-                for (int64_t y = i; y < x && !seen; y++) {
+    if (ncoll <= COLL_LIST) {
+        if (tid < (int)ncoll) {
+            const int64_t t = coll[blockIdx.x].tail[tid];
+            const uint64_t h = in.key[0][t];
+            int64_t b = t;
+            while (b > 0 && in.key[0][b - 1] == h)
+                b--;
+            coll_segment<WB, PB>(s, in, bits, ra, rh, nref, D0, G, b, t + 1, a, search != 0);
+        }
+    } else {
+        const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
+        const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
+        const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
+        const int64_t b0 = t_begin * RED_TILE;
+        const int64_t b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
+        for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
+            const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
+            for (int j = 0; j < RED_ITEMS; j++) {
+                const int64_t i = i0 + j;
+                if (i >= b1)
+                    break;
+                const uint64_t h = in.key[0][i];
+                if (i > 0 && in.key[0][i - 1] == h)
+                    continue;  // not a segment head
+                int64_t e = i;
+                while (e < n && in.key[0][e] == h)
+                    e++;
+                uint64_t k0[WB];
+                hash_key<WB>(ra, in.key[1][i], k0);
+                bool collided = false;
+                for (int64_t y = i + 1; y < e && !collided; y++) {
                     uint64_t ky[WB];
                     hash_key<WB>(ra, in.key[1][y], ky);
-                    bool same = true;
-                    for (int w = 0; w < WB; w++)
-                        same = same && ky[w] == kx[w];
-                    seen = same;
+                    collided = !bits_eq<WB>(ky, k0);
                 }
-                if (seen)
-                    continue;
-                double nx = 0.0;
-                for (int64_t y = x; y < e; y++) {
-                    uint64_t ky[WB];
-                    hash_key<WB>(ra, in.key[1][y], ky);
-                    bool same = true;
-                    for (int w = 0; w < WB; w++)
-                        same = same && ky[w] == kx[w];
-                    if (same)
-                        nx += load_pay<PB>(in, y);
-                }
-                // references searched in global memory over the whole list
-                hash_key_term<WB>(s, bits, ra, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), nx,
-                                  Hp, G, e0, a, search != 0);
+                if (collided)  // otherwise k_reduce_hash took it
+                    coll_segment<WB, PB>(s, in, bits, ra, rh, nref, D0, G, i, e, a, search != 0);
             }
         }
     }
@@ -1581,7 +1800,7 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     size_t q_bytes = (size_t)RED_Q * (8 + 4);
     q_bytes = (q_bytes + 15) & ~(size_t)15;
     const size_t binom_bytes = rk ? (size_t)(s.norb + 1) * s.kc.stride * 8 : 0;
-    const size_t fixed = q_bytes + (size_t)nso * 8 + binom_bytes;
+    const size_t fixed = q_bytes + (size_t)nso * 16 + binom_bytes;
     if (fixed + (lds_table ? tri_bytes : 0) > RED_LDS_MAX)
         lds_table = 0;  // the pair table is then read through the caches
     const size_t dyn = fixed + (lds_table ? tri_bytes : 0);
@@ -1751,7 +1970,8 @@ hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint6
     return hipGetLastError();
 }
 
-hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double *Hp, double *G, hipStream_t st)
+hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double e0, double *D0, double *G,
+                           hipStream_t st)
 {
     if (n <= 0)
         return hipSuccess;
@@ -1759,28 +1979,33 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
         return hipErrorInvalidValue;
     dim3 g((unsigned)(n < 65536 ? n : 65536)), b(256);
     switch (s.W) {
-    case 1: hipLaunchKernelGGL((k_parent_g<1>), g, b, 0, st, s, bits, n, Hp, G); break;
-    case 2: hipLaunchKernelGGL((k_parent_g<2>), g, b, 0, st, s, bits, n, Hp, G); break;
-    case 3: hipLaunchKernelGGL((k_parent_g<3>), g, b, 0, st, s, bits, n, Hp, G); break;
-    case 4: hipLaunchKernelGGL((k_parent_g<4>), g, b, 0, st, s, bits, n, Hp, G); break;
+    case 1: hipLaunchKernelGGL((k_parent_g<1>), g, b, 0, st, s, bits, n, e0, D0, G); break;
+    case 2: hipLaunchKernelGGL((k_parent_g<2>), g, b, 0, st, s, bits, n, e0, D0, G); break;
+    case 3: hipLaunchKernelGGL((k_parent_g<3>), g, b, 0, st, s, bits, n, e0, D0, G); break;
+    case 4: hipLaunchKernelGGL((k_parent_g<4>), g, b, 0, st, s, bits, n, e0, D0, G); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_hash(const DevSys &s, int fp32, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *Hp, const double *G, double e0,
-                              int search, Partial *partials, uint32_t *coll, Flags *flags, hipStream_t st)
+hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
+                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
+                              int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st)
 {
+    (void)e0;  // carried by D0
+    // relative rounding of a stored FP32 payload: once (FP64 arithmetic), or
+    // FP32 integrals and arithmetic (a looser bound)
+    const double eps = pm == PM_FP32_ARITH ? std::ldexp(1.0, -20) : std::ldexp(1.0, -24);
+    const bool fp32 = pm != PM_FP64;
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     dim3 g(RED_GRID), b(RED_THREADS);
 #define RH(WB, PB)                                                                                                 \
     do {                                                                                                           \
         const int64_t ge = red_workers((const void *)&k_reduce_hash<WB, PB>, 0);                                    \
         const int64_t per = (ntiles + ge - 1) / ge;                                                                \
-        hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per,     \
-                           search, partials, coll, flags);                                                         \
-        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, Hp, G, e0, per, \
+        hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, D0, G, per,         \
+                           search, eps, partials, coll, flags);                                                    \
+        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, D0, G, per,     \
                            search, partials, coll, flags);                                                         \
     } while (0)
     switch (s.W * 2 + (fp32 ? 0 : 1)) {

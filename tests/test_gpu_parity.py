@@ -345,9 +345,18 @@ def test_hash_records_match(pt2, norb, na, nb, nref, log2p, prec, hash_bits):
     for k in ("n_contrib", "n_after_cutoff", "n_unique", "n_external", "n_in_ref_hit", "n_nonneg_denom",
               "key_xor", "key_sum"):
         assert res[0][k] == res[2][k], (k, res[0][k], res[2][k])
-    assert res[2]["e_pt2"] == pytest.approx(res[0]["e_pt2"], rel=1e-12, abs=1e-12)
+    if prec == "fp64":
+        assert res[2]["e_pt2"] == pytest.approx(res[0]["e_pt2"], rel=1e-12, abs=1e-12)
+    # (FP32 payloads: hash records recompute the numerators of the terms their
+    # rounding could move most from FP64 matrix elements, bitstring records
+    # keep the rounded sum, so the two differ within the FP32 bar, checked
+    # against the oracle below for both)
     assert res[2]["ref_cross"] == pytest.approx(res[0]["ref_cross"], rel=1e-12, abs=1e-14)
     ref, _ = O.pt2(dets, c, e0)
+    if prec != "fp64":
+        assert_matches(res[0], ref, tol=1e-6, cross_tol=1e-7)
+        print("fp32 |dE| vs FP64 oracle: bitstring", abs(res[0]["e_pt2"] - ref["e_pt2"]), "hash",
+              abs(res[2]["e_pt2"] - ref["e_pt2"]), flush=True)
     if prec == "fp64":
         assert_matches(res[2], ref)
     else:
