@@ -257,6 +257,17 @@ int pt2_evaluate_parts(pt2_ctx *ctx, const uint64_t *dets, const double *coeffs,
                        pt2_result *out);
 
 /*
+ * As pt2_evaluate_parts, but d_dets and d_coeffs are device pointers already
+ * resident in HBM (layout as pt2_evaluate); parts and e_parts stay host
+ * arrays.  Evaluating the 2^log2p subsets in several calls of contiguous
+ * groups, and summing e_parts in subset order, gives the full energy with
+ * each call's work bounded (Algorithm 2: the subsets are independent).
+ */
+int pt2_evaluate_parts_device(pt2_ctx *ctx, const uint64_t *d_dets, const double *d_coeffs,
+                              int64_t ndets, double e0, int log2p, const uint32_t *parts, int nparts,
+                              double *e_parts, pt2_result *out);
+
+/*
  * Serving form.  pt2_submit copies dets and coeffs (host arrays) and queues
  * the request; it returns at once with a request id.  Requests of every
  * context share one device scheduler: a request starts when a stream is free

@@ -79,6 +79,8 @@ _SIGS = {
     "pt2_evaluate_device": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.POINTER(Result)]),
     "pt2_evaluate_parts": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.c_int, _u32p,
                                      C.c_int, _f64p, C.POINTER(Result)]),
+    "pt2_evaluate_parts_device": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.c_int, _u32p,
+                                            C.c_int, _f64p, C.POINTER(Result)]),
     "pt2_submit": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, _i64p]),
     "pt2_poll": (C.c_int, [_CTX, C.c_int64, C.POINTER(Result)]),
     "pt2_wait": (C.c_int, [_CTX, C.c_int64, C.POINTER(Result)]),
@@ -233,15 +235,18 @@ class Context:
         return r.as_dict()
 
     def evaluate_parts(self, dets, coeffs, e0, log2p, parts):
-        """Energies of the listed subsets of a 2^log2p hash split (host arrays)."""
-        _dev, dp, cp, n, _keep = self._args(np.asarray(dets), np.asarray(coeffs))
+        """Energies of the listed subsets of a 2^log2p hash split (host arrays,
+        or CUDA tensors resident on the device)."""
+        if not (_is_torch_cuda(dets) or _is_torch_cuda(coeffs)):
+            dets, coeffs = np.asarray(dets), np.asarray(coeffs)
+        dev, dp, cp, n, _keep = self._args(dets, coeffs)
         pp = np.ascontiguousarray(np.asarray(parts, dtype=np.uint32))
         ep = np.zeros(len(pp), dtype=np.float64)
         r = Result()
         r.struct_size = C.sizeof(Result)
-        _check(_lib.pt2_evaluate_parts(self._ctx, dp, cp, n, float(e0), int(log2p),
-                                       pp.ctypes.data_as(_u32p), len(pp), ep.ctypes.data_as(_f64p),
-                                       C.byref(r)))
+        fn = _lib.pt2_evaluate_parts_device if dev else _lib.pt2_evaluate_parts
+        _check(fn(self._ctx, dp, cp, n, float(e0), int(log2p), pp.ctypes.data_as(_u32p), len(pp),
+                  ep.ctypes.data_as(_f64p), C.byref(r)))
         return r.as_dict(), ep
 
     # -- serving -------------------------------------------------------------

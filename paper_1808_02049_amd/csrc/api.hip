@@ -1764,8 +1764,8 @@ PT2_API int pt2_evaluate_device(pt2_ctx *c, const uint64_t *d_dets, const double
     return eval_common(c, J, out);
 }
 
-PT2_API int pt2_evaluate_parts(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0,
-                               int log2p, const uint32_t *parts, int nparts, double *e_parts, pt2_result *out)
+static int eval_parts(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0, int log2p,
+                      const uint32_t *parts, int nparts, double *e_parts, pt2_result *out, bool host)
 {
     int rc = check_eval_args(c, dets, coeffs, n, out);
     if (rc)
@@ -1778,7 +1778,7 @@ PT2_API int pt2_evaluate_parts(pt2_ctx *c, const uint64_t *dets, const double *c
         if (parts[i] >= (1u << log2p))
             return fail(PT2_E_INVALID, "subset index out of range");
     Job J{};
-    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = true, J.e0 = e0, J.forced_log2p = log2p;
+    J.dets = dets, J.coeffs = coeffs, J.n = n, J.host = host, J.e0 = e0, J.forced_log2p = log2p;
     J.parts = parts, J.nparts = nparts, J.e_parts = e_parts;
     if (nparts == 0) {
         memset(out, 0, sizeof *out);
@@ -1786,6 +1786,19 @@ PT2_API int pt2_evaluate_parts(pt2_ctx *c, const uint64_t *dets, const double *c
         return PT2_OK;
     }
     return eval_common(c, J, out);
+}
+
+PT2_API int pt2_evaluate_parts(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0,
+                               int log2p, const uint32_t *parts, int nparts, double *e_parts, pt2_result *out)
+{
+    return eval_parts(c, dets, coeffs, n, e0, log2p, parts, nparts, e_parts, out, true);
+}
+
+PT2_API int pt2_evaluate_parts_device(pt2_ctx *c, const uint64_t *d_dets, const double *d_coeffs, int64_t n,
+                                      double e0, int log2p, const uint32_t *parts, int nparts, double *e_parts,
+                                      pt2_result *out)
+{
+    return eval_parts(c, d_dets, d_coeffs, n, e0, log2p, parts, nparts, e_parts, out, false);
 }
 
 PT2_API int pt2_dump_records(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, int sorted,

@@ -47,7 +47,7 @@ CASES = {
     "c5_sample300": ("c5", 300, 5, None, 8),
     # the eight subsets 40..47 of the 4096-way split of the whole of C5, which
     # together are subset 5 of its 512-way split
-    "c5_parts12": ("c5", None, 12, list(range(40, 48)), 1),
+    "c5_parts12": ("c5", None, 12, list(range(40, 48)), 2),
 }
 
 

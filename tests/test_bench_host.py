@@ -21,7 +21,7 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_committed_counters():
-    text = open(bench.COUNTERS_MD).read()
+    text = open(bench.counters_md("c2", "fp64")).read()
     m = re.search(r"scatter_traffic_bytes_per_launch=(\S+) .*source_sha256_16=([0-9a-f]+)", text)
     rb = int(re.search(r"record_bytes=(\d+)", text).group(1))
     cur = hashlib.sha256(open(bench.SORT_SRC, "rb").read()).hexdigest()[:16]
@@ -30,16 +30,22 @@ def test_traffic_follows_the_committed_counters():
         assert got == float(m.group(1))
     else:
         assert got is None
-    # other workloads, precisions or record formats have no counters
-    assert bench.measured_traffic("c3", "fp64", rb) is None
+    # precisions or record formats without counters have none
     assert bench.measured_traffic("c2", "fp32", rb) is None
     assert bench.measured_traffic("c2", "fp64", rb + 2) is None
+    assert bench.measured_traffic("c4", "fp64", rb) is None
 
 
 def test_traffic_is_dropped_when_the_sort_source_changes(tmp_path, monkeypatch):
     changed = tmp_path / "sort.hip"
     changed.write_bytes(open(bench.SORT_SRC, "rb").read() + b"\n// edited\n")
     monkeypatch.setattr(bench, "SORT_SRC", str(changed))
-    text = open(bench.COUNTERS_MD).read()
+    text = open(bench.counters_md("c2", "fp64")).read()
     rb = int(re.search(r"record_bytes=(\d+)", text).group(1))
     assert bench.measured_traffic("c2", "fp64", rb) is None
+
+
+def test_host_threads_and_neumaier():
+    assert 1 <= bench.host_threads() <= len(__import__("os").sched_getaffinity(0))
+    vals = [1e16, 1.0, -1e16, 1.0]
+    assert bench.neumaier(vals) == 2.0

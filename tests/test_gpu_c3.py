@@ -4,9 +4,11 @@ device budget forces a hash split into many subsets.
 
 The full evaluation is checked by properties that hold at any size (the
 closed-form count, the <c|H|c> identity from the in-reference numerators, the
-FP32-payload form within 1e-6 Eh); four subsets of a 4096-way split are
-compared with the FP64 oracle term for term (the oracle expands all 1e5
-references once for the four subsets).
+FP32-payload form within 1e-6 Eh of the FP64 path); four subsets of a
+4096-way split are compared with the FP64 oracle run live (the oracle expands
+all 1e5 references once for the four subsets).  The stored oracle results of
+tests/test_gpu_goldens.py cover the first 2000 references and eight more
+subsets.
 """
 import os
 
@@ -71,11 +73,12 @@ def test_c3_full_fp64_and_fp32_forms(c3):
     ctx32.close()
     print("fp32 payload form", got32["e_pt2"], got32["e_pt2"] - got["e_pt2"], got32["ms_total"],
           got32["n_partitions"], flush=True)
-    # Rounding each stored term to FP32 leaves a random error of about 2^-24
-    # times sqrt(sum over keys of (2 N_a^2 / d_a)^2 k_a); it is dominated by a
-    # few large terms and comes to a few 1e-9 of E_PT2 here, so the 1e-6 Eh
-    # bar, met at C1 and C2, is exceeded at this system's E_PT2 of -1268 Eh
-    # (measured 5.1e-6).  The check is the relative bound.
-    assert abs(got32["e_pt2"] - got["e_pt2"]) <= 1e-8 * abs(got["e_pt2"])
+    # The FP32-payload form within its 1e-6 Eh bar of the FP64 path (itself
+    # within 1e-9 Eh of the oracle wherever the stored oracle results reach:
+    # the first 2000 references and eight split subsets of this workload).
+    # Terms whose numerator rounding could move them by more than 1e-11 Eh are
+    # recomputed from FP64 matrix elements; without that the near-singular
+    # denominators of this system left 5.1e-6 Eh.
+    assert abs(got32["e_pt2"] - got["e_pt2"]) <= 1e-6
     for k in ("n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum"):
         assert got32[k] == got[k]
