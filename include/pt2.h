@@ -245,6 +245,26 @@ int pt2_evaluate_device(pt2_ctx *ctx, const uint64_t *d_dets, const double *d_co
                         int64_t ndets, double e0, pt2_result *out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * pt2_evaluate_device, but the call allocates nothing.  Every device buffer
+ * of the evaluation (reference planes, record and sort buffers, counts,
+ * partial sums, control data) is carved from one static device array of
+ * 256 MiB that the library holds on each device it runs on until the
+ * process ends; no hipMalloc, hipFree, pinned host allocation, stream or
+ * event is created, and per-kernel timings are not recorded.  The record
+ * buffers of one subset are planned to fit 60% of it (the planner splits
+ * the work into more subsets as needed); an evaluation that does not fit
+ * returns PT2_E_NOMEM with a message naming the scratch size.  The call
+ * clears what must start at zero and returns after its work is done.  All
+ * calls on one device share the array: calls that overlap on one device
+ * (different contexts or threads) race.  Inputs, errors and results as
+ * pt2_evaluate_device.
+ */
+int pt2_evaluate_device_noalloc(pt2_ctx *ctx, const uint64_t *d_dets, const double *d_coeffs,
+                                int64_t ndets, double e0, pt2_result *out);
+
+/*
  * Evaluate only the listed subsets of a 2^log2p split (0 <= log2p <= 12) of the external space
  * (Algorithm 2; each subset on its own), from host arrays.
  *   parts   host, nparts subset indices in [0, 2^log2p)

@@ -79,6 +79,7 @@ _SIGS = {
     "pt2_evaluate_device": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.POINTER(Result)]),
     "pt2_evaluate_parts": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.c_int, _u32p,
                                      C.c_int, _f64p, C.POINTER(Result)]),
+    "pt2_evaluate_device_noalloc": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.POINTER(Result)]),
     "pt2_evaluate_parts_device": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.c_int, _u32p,
                                             C.c_int, _f64p, C.POINTER(Result)]),
     "pt2_submit": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, _i64p]),
@@ -232,6 +233,17 @@ class Context:
         r.struct_size = C.sizeof(Result)
         fn = _lib.pt2_evaluate_device if dev else _lib.pt2_evaluate
         _check(fn(self._ctx, dp, cp, n, float(e0), C.byref(r)))
+        return r.as_dict()
+
+    def evaluate_noalloc(self, dets, coeffs, e0):
+        """As evaluate on device tensors, through the allocation-free entry
+        point (the library's static device scratch)."""
+        dev, dp, cp, n, _keep = self._args(dets, coeffs)
+        if not dev:
+            raise ValueError("evaluate_noalloc takes device tensors")
+        r = Result()
+        r.struct_size = C.sizeof(Result)
+        _check(_lib.pt2_evaluate_device_noalloc(self._ctx, dp, cp, n, float(e0), C.byref(r)))
         return r.as_dict()
 
     def evaluate_parts(self, dets, coeffs, e0, log2p, parts):

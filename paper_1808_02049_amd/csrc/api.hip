@@ -75,12 +75,20 @@ uint64_t splitmix_next(uint64_t &st)
 // ---------------------------------------------------------------------------
 // device memory through the optional hook
 
+// A bump arena over a fixed device region: buffers are carved in order and
+// never freed one by one (the whole arena is dropped after the call).
+struct BumpArena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+
 struct Alloc {
     void *(*fa)(size_t, void *) = nullptr;
     void (*ff)(void *, size_t, void *) = nullptr;
     void *user = nullptr;
     int device = 0;
     hipStream_t stream = nullptr;  // non-null: stream-ordered allocation on this stream
+    BumpArena *arena = nullptr;    // non-null: carve from this region, allocate nothing
     bool same_source(const Alloc &o) const { return fa == o.fa && ff == o.ff && user == o.user; }
 };
 
@@ -98,6 +106,16 @@ int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
         return PT2_OK;
     bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
+    if (A.arena) {
+        if (bytes > A.arena->cap - A.arena->used)
+            return fail(PT2_E_NOMEM, "the evaluation needs more than the %zu MiB static scratch (%zu MiB in use, "
+                                     "%zu more requested)",
+                        A.arena->cap >> 20, A.arena->used >> 20, bytes >> 20);
+        b.p = A.arena->base + A.arena->used;
+        b.bytes = bytes;
+        A.arena->used += bytes;
+        return PT2_OK;
+    }
     if (A.fa) {
         p = A.fa(bytes, A.user);
         if (!p)
@@ -116,7 +134,7 @@ int buf_alloc(const Alloc &A, Buf &b, size_t bytes)
 
 void buf_free(const Alloc &A, Buf &b)
 {
-    if (b.p && !b.borrowed) {
+    if (b.p && !b.borrowed && !A.arena) {
         if (A.ff) {
             // an external allocator may hand the block out at once: let every
             // queued kernel that might still use it finish first
@@ -180,8 +198,10 @@ struct Workspace {
     std::vector<uint32_t> agrp_host;       // source of the last upload of agrp
     int64_t agrp_ngrp = 0;                 // alpha plus beta groups in agrp
     Small *host_small = nullptr;  // pinned mirror
+    bool own_host_small = true;   // false: static host storage (allocation-free evaluation)
     std::vector<hipEvent_t> evpool;
     size_t ev_used = 0;
+    hipStream_t zero_stream = nullptr;  // allocation-free evaluation: the stream that clears `small`
 
     ~Workspace() { release(); }
 
@@ -193,10 +213,9 @@ struct Workspace {
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev), buf_free(A, agrp);
         rec_cap = scan_tiles = 0;
-        if (host_small) {
+        if (host_small && own_host_small)
             (void)hipHostFree(host_small);
-            host_small = nullptr;
-        }
+        host_small = nullptr;
         for (auto e : evpool)
             (void)hipEventDestroy(e);
         evpool.clear();
@@ -316,6 +335,8 @@ int ensure_small(Workspace &ws)
         static_assert(sizeof(Small) % 8 == 0, "Small is cleared in 8-byte words");
         if (ws.A.stream)
             HIPCHK(launch_zero_u64((uint64_t *)ws.small.p, (int64_t)(sizeof(Small) / 8), ws.A.stream));
+        else if (ws.A.arena)  // cleared on the evaluation's stream (ensure_small's caller passes it)
+            HIPCHK(launch_zero_u64((uint64_t *)ws.small.p, (int64_t)(sizeof(Small) / 8), ws.zero_stream));
         else
             HIPCHK(hipMemset(ws.small.p, 0, sizeof(Small)));
     }
@@ -760,7 +781,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     const int pb = fp32 ? 4 : 8;
     int rc;
     Timing tm;
-    tm.on = c->opt.timing != 0;
+    tm.on = c->opt.timing != 0 && !ws.A.arena;  // no events are created without allocation
     ws.ev_used = 0;
     pt2_result res;
     memset(&res, 0, sizeof res);
@@ -1762,6 +1783,71 @@ PT2_API int pt2_evaluate_device(pt2_ctx *c, const uint64_t *d_dets, const double
     J.dets = d_dets, J.coeffs = d_coeffs, J.n = n, J.host = false, J.e0 = e0, J.forced_log2p = -1;
     J.live_budget = true;
     return eval_common(c, J, out);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation: every device buffer of the call is carved from
+// one file-scope device array.  In host code `scratch` names a host-side
+// stand-in, not device memory: the array's device address is taken once per
+// device with hipGetSymbolAddress (that device current) and only that
+// address is used.  Calls on one device share the array and overlap-race.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64];  // device address of `scratch` per device (null until taken)
+Small g_scratch_host[64]; // host mirror of the control block per device
+
+int scratch_base(int dev, char **out)
+{
+    if (dev < 0 || dev >= 64)
+        return fail(PT2_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(PT2_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PT2_OK;
+}
+}  // namespace
+
+PT2_API int pt2_evaluate_device_noalloc(pt2_ctx *c, const uint64_t *d_dets, const double *d_coeffs, int64_t n,
+                                        double e0, pt2_result *out)
+{
+    int rc = check_eval_args(c, d_dets, d_coeffs, n, out);
+    if (rc)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    const int dev = c->opt.device;
+    if (hipSetDevice(dev) != hipSuccess)
+        return fail(PT2_E_DEVICE, "hipSetDevice failed");
+    char *base = nullptr;
+    if ((rc = scratch_base(dev, &base)))
+        return rc;
+    BumpArena ar;
+    ar.base = base, ar.cap = NOALLOC_SCRATCH_BYTES, ar.used = 0;
+    Workspace ws;
+    ws.A.device = dev;
+    ws.A.arena = &ar;
+    ws.zero_stream = c->stream;
+    ws.host_small = &g_scratch_host[dev];
+    ws.own_host_small = false;
+    Job J{};
+    J.dets = d_dets, J.coeffs = d_coeffs, J.n = n, J.host = false, J.e0 = e0, J.forced_log2p = -1;
+    // the record buffers of a subset take at most 60% of the scratch; the
+    // rest holds the reference planes, counts and control data
+    J.plan_budget = 0.6 * (double)NOALLOC_SCRATCH_BYTES;
+    rc = run_job(c, ws, c->stream, J, out);
+    if (rc == PT2_OK)
+        HIPCHK(hipStreamSynchronize(c->stream));
+    return rc;
 }
 
 static int eval_parts(pt2_ctx *c, const uint64_t *dets, const double *coeffs, int64_t n, double e0, int log2p,
