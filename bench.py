@@ -287,8 +287,11 @@ def split_bench(args):
     d_dets = torch.from_numpy(np.ascontiguousarray(dets).view(np.int64)).cuda()
     d_c = torch.from_numpy(np.ascontiguousarray(c)).cuda()
     torch.cuda.synchronize()
-    steps = max(1, min(args.steps, P))
-    groups = np.array_split(np.arange(P), steps)
+    # --subsets K (profiling runs): only the first K subsets; the line then
+    # covers that part of the workload and says so
+    nsub = P if args.subsets <= 0 else min(args.subsets, P)
+    steps = max(1, min(args.steps, nsub))
+    groups = np.array_split(np.arange(nsub), steps)
     print(f"bench: {args.workload} {args.precision}, {P} subsets in {steps} steps, warmup {args.warmup}",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -331,7 +334,9 @@ def split_bench(args):
         "data": "synthetic (seeded integrals and reference, stand-in for molecular inputs)",
         "config": {"workload": f"{args.workload}: ({w.nalpha}a,{w.nbeta}b) electrons in {w.norb} orbitals, "
                                f"{len(dets)} reference determinants, {tot['n_contrib']} contributions, "
-                               f"all {P} subsets of a hash split once, in {steps} steps",
+                               (f"all {P} subsets of a hash split once, in {steps} steps" if nsub == P else
+                                f"PARTIAL: the first {nsub} of the {P} subsets of a hash split "
+                                f"(a profiling run, not the whole workload), in {steps} steps"),
                    "precision": args.precision, "key_bits": res[0]["key_bits"], "record_bytes": rec,
                    "subsets": P},
         "e_pt2": e_total,
@@ -351,14 +356,14 @@ def split_bench(args):
         sh = 12 - log2p
         top = {p >> sh for p in g["parts"]}
         whole = len(top) == 1 and sorted(g["parts"]) == list(range(min(top) << sh, (min(top) + 1) << sh))
-        if whole:
+        if whole and min(top) < nsub:
             p = min(top)
             line["parity_vs_oracle"] = {"subset": int(p), "of": P, "engine": float(eparts[p]),
                                         "oracle": g["e"], "abs_dE": abs(float(eparts[p]) - g["e"])}
     ctx.close()
     torch.cuda.synchronize()
     extra = {}
-    if args.fp32_subsets > 0 and args.precision == "fp64":
+    if args.fp32_subsets > 0 and args.precision == "fp64" and nsub == P:
         sel = sorted({5 % P} | set(np.linspace(0, P - 1, args.fp32_subsets).astype(int).tolist()))
         ctx32 = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision="fp32", timing=True, stream=stream,
                             compress_keys=args.compress_keys)
@@ -497,6 +502,8 @@ def main():
     ap.add_argument("--no-c2-line", dest="c2_line", action="store_false",
                     help="skip the workload C2 line")
     ap.add_argument("--c2-steps", type=int, default=5)
+    ap.add_argument("--subsets", type=int, default=0,
+                    help="profiling: evaluate only the first K subsets of the split (0: all)")
     ap.add_argument("--compress-keys", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="record keys: -1 library default, 0 bitstrings, 1 combinatorial ranks, 2 hash records")
     ap.add_argument("--serving", action="store_true",

@@ -595,19 +595,26 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
     return PT2_OK;
 }
 
+double serving_device_budget(int dev);
+
 int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout &RL, Workspace &ws,
              const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
 {
     const int W = RL.W;
     const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
     const double total = (double)nref * (double)L.nper;
-    // without an explicit budget: 80% of what is free now plus the record
-    // buffers this workspace already holds (they are reused)
     uint64_t budget = J.plan_budget > 0.0 ? (uint64_t)J.plan_budget : c->budget;
     if (!c->opt.device_budget_bytes && J.live_budget) {
+        // without an explicit budget: the budget the scheduler plans served
+        // requests against (80% of what was free when the device was first
+        // used), so that a request evaluated alone takes the plan, and with it
+        // the summation order, it takes when served; unless less is free now
+        // (80% of the free memory plus the record buffers this workspace
+        // already holds, which are reused)
+        budget = (uint64_t)serving_device_budget(c->opt.device);
         size_t freeb = 0, totalb = 0;
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess)
-            budget = (uint64_t)(0.8 * ((double)freeb + (double)ws.record_bytes()));
+            budget = std::min<uint64_t>(budget, (uint64_t)(0.8 * ((double)freeb + (double)ws.record_bytes())));
     }
     const double cap_bytes =
         (double)(c->opt.max_partition_bytes && c->opt.max_partition_bytes < budget ? c->opt.max_partition_bytes
@@ -1233,6 +1240,12 @@ class Scheduler {
         return rc;
     }
 
+    double device_budget(int dev)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return device_budget_locked(dev);
+    }
+
     // bytes the scheduler may hand to the record buffers of running requests
     // on a device: 80% of what was free when it first served the device.
     // Freed request buffers stay in the device's stream-ordered pool for the
@@ -1486,6 +1499,12 @@ class Scheduler {
         }
     }
 };
+
+// The scheduler's planning budget of a device (taken once per device).
+double serving_device_budget(int dev)
+{
+    return Scheduler::get().device_budget(dev);
+}
 
 }  // namespace
 

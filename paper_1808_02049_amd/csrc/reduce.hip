@@ -479,6 +479,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         for (int i = tid; i < nb; i += RED_THREADS)
             binom[i] = s.kc.binom[i];
     }
+    // the staged tables are read by other threads from here on: thread 0
+    // unranks each tile's anchor with the binomial table before the tile's
+    // first barrier
+    __syncthreads();
     Acc a;
     acc_init(a);
 

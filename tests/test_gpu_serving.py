@@ -19,6 +19,9 @@ import synth
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 KEYS = ("e_pt2", "n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum")
+# the plan: a served request and the same request alone must take the same
+# split, key form and digit passes (the summation order follows from them)
+PLAN = ("n_partitions", "key_bits", "n_sort_passes", "record_bytes")
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +66,7 @@ def test_served_results_equal_standalone(pt2, reqs):
     t0 = time.time()
     for j, rid in ids:
         got = ctxs[j].wait(rid)
-        for k in KEYS:
+        for k in KEYS + PLAN:
             assert got[k] == alone[j][k], (j, k, got[k], alone[j][k])
     print(f"served {len(ids)} requests in {time.time() - t0:.2f} s", flush=True)
     for ctx in ctxs:
@@ -94,7 +97,7 @@ def test_served_string_reuse(pt2, reqs):
             ids.append((j, ctxs[j].submit(dets, c, e0)))
     for j, rid in ids:
         got = ctxs[j].wait(rid)
-        for k in KEYS:
+        for k in KEYS + PLAN:
             assert got[k] == alone[j][k], (j, k, got[k], alone[j][k])
     for ctx in ctxs:
         ctx.close()
@@ -146,8 +149,8 @@ def test_tight_budget_splits_the_plan(pt2, reqs):
     ids = [ctx.submit(dets, c, e0) for _ in range(4)]
     for rid in ids:
         got = ctx.wait(rid)
-        for k in KEYS + ("n_partitions",):
-            assert got[k] == alone[k]
+        for k in KEYS + PLAN:
+            assert got[k] == alone[k], (k, got[k], alone[k])
     ctx.close()
 
 
@@ -179,7 +182,7 @@ def test_workers_reused_across_key_widths(pt2):
         ids.append((j % 2, ctx.submit(dets, c, e0)))
     for s, rid in ids:
         got = systems[s][0].wait(rid)
-        for k in KEYS:
-            assert got[k] == systems[s][4][k], (s, k)
+        for k in KEYS + PLAN:
+            assert got[k] == systems[s][4][k], (s, k, got[k], systems[s][4][k])
     for ctx, *_ in systems:
         ctx.close()
