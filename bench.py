@@ -270,6 +270,14 @@ def serving_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def split_scope(P, nsub, steps):
+    """How much of a split workload a line covers."""
+    if nsub == P:
+        return f"all {P} subsets of a hash split once, in {steps} steps"
+    return (f"PARTIAL: the first {nsub} of the {P} subsets of a hash split "
+            f"(a profiling run, not the whole workload), in {steps} steps")
+
+
 def split_bench(args):
     """A workload evaluated as the 2^log2p subsets of its hash split, every
     subset once in the timed region, as args.steps contiguous groups."""
@@ -283,7 +291,7 @@ def split_bench(args):
     P = 1 << log2p
     stream = torch.cuda.current_stream()
     ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision=args.precision, timing=True,
-                      stream=stream, compress_keys=args.compress_keys)
+                      stream=stream, compress_keys=args.compress_keys, cutoff=args.cutoff)
     d_dets = torch.from_numpy(np.ascontiguousarray(dets).view(np.int64)).cuda()
     d_c = torch.from_numpy(np.ascontiguousarray(c)).cuda()
     torch.cuda.synchronize()
@@ -334,9 +342,7 @@ def split_bench(args):
         "data": "synthetic (seeded integrals and reference, stand-in for molecular inputs)",
         "config": {"workload": f"{args.workload}: ({w.nalpha}a,{w.nbeta}b) electrons in {w.norb} orbitals, "
                                f"{len(dets)} reference determinants, {tot['n_contrib']} contributions, "
-                               (f"all {P} subsets of a hash split once, in {steps} steps" if nsub == P else
-                                f"PARTIAL: the first {nsub} of the {P} subsets of a hash split "
-                                f"(a profiling run, not the whole workload), in {steps} steps"),
+                               + split_scope(P, nsub, steps),
                    "precision": args.precision, "key_bits": res[0]["key_bits"], "record_bytes": rec,
                    "subsets": P},
         "e_pt2": e_total,
@@ -350,7 +356,14 @@ def split_bench(args):
                      "bytes_per_launch": scatter_bytes / launches, "avg_launch_ms": scatter_ms,
                      "whole_digit_pass": {"avg_ms": tot["ms_sort"] / launches, "achieved_GBs": pass_gbs}},
     }
+    if args.cutoff > 0:
+        # the paper's screening (Section V): terms with |H_ai c_i| below the
+        # cutoff are dropped; the contribution count stays the structural one
+        line["cutoff"] = {"value": args.cutoff, "n_after_cutoff": int(tot["n_after_cutoff"]),
+                          "kept_fraction": tot["n_after_cutoff"] / tot["n_contrib"]}
     # one benchmarked subset against the stored oracle result of its records
+    # (with a cutoff: the cutoff's effect on that subset, against the exact
+    # cutoff-0 oracle value)
     g = golden(f"{args.workload}_parts12")
     if g and log2p <= 12 and args.precision == "fp64":
         sh = 12 - log2p
@@ -358,12 +371,13 @@ def split_bench(args):
         whole = len(top) == 1 and sorted(g["parts"]) == list(range(min(top) << sh, (min(top) + 1) << sh))
         if whole and min(top) < nsub:
             p = min(top)
-            line["parity_vs_oracle"] = {"subset": int(p), "of": P, "engine": float(eparts[p]),
-                                        "oracle": g["e"], "abs_dE": abs(float(eparts[p]) - g["e"])}
+            key = "parity_vs_oracle" if args.cutoff <= 0 else "cutoff_dE_vs_cutoff0_oracle"
+            line[key] = {"subset": int(p), "of": P, "engine": float(eparts[p]),
+                         "oracle": g["e"], "abs_dE": abs(float(eparts[p]) - g["e"])}
     ctx.close()
     torch.cuda.synchronize()
     extra = {}
-    if args.fp32_subsets > 0 and args.precision == "fp64" and nsub == P:
+    if args.fp32_subsets > 0 and args.precision == "fp64" and nsub == P and args.cutoff <= 0:
         sel = sorted({5 % P} | set(np.linspace(0, P - 1, args.fp32_subsets).astype(int).tolist()))
         ctx32 = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision="fp32", timing=True, stream=stream,
                             compress_keys=args.compress_keys)
@@ -494,6 +508,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5", choices=["c2", "c3", "c5"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--cutoff", type=float, default=0.0,
+                    help="drop terms with |H_ai c_i| below this (the paper's production setting is 1e-8)")
     ap.add_argument("--log2p", type=int, default=-1, help="hash split (default: 9 for c5, 5 for c3)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="reference determinants in the oracle's timed sample (0: skip; default per workload)")
@@ -514,7 +530,18 @@ def main():
                     help="time each request's phases with HIP events (serving diagnostics)")
     ap.add_argument("--serving-closed-only", action="store_true",
                     help="measure the closed loop only (diagnostics)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="counter runs: first copy 1 GiB device to device (the reference that scales "
+                         "FETCH_SIZE and WRITE_SIZE to bytes)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "

@@ -133,13 +133,16 @@ typedef struct {
                                       subtraction the counts and checksums cover
                                       every distinct determinant                      */
     int hash_bits;                 /* hash records: bits of the hash kept as the sort
-                                      key.  0 (default): per evaluation, the fewest
-                                      of 32, 40, 48, 56, 64 for which the expected
-                                      number of colliding pairs in the largest
-                                      subset, N^2 / 2^(bits+1), is 256 or fewer
-                                      (collided runs are resolved exactly).  1-64:
-                                      exactly that many (few bits make collisions
-                                      common, to test their handling)               */
+                                      key.  0 (default): per evaluation, the top 32,
+                                      40, 48, 56 or 64 bits, the choice with the
+                                      fewest digit passes (then the most bits) for
+                                      which the expected number of colliding pairs
+                                      among the largest subset's N records,
+                                      N^2 / 2^(bits - log2p + 1) with 2^log2p
+                                      subsets, is 16384 or fewer (collided runs are
+                                      resolved exactly).  1-64: exactly that many
+                                      low bits (few bits make collisions common, to
+                                      test their handling)                          */
     int spin_flip;                 /* 1: use the alpha/beta swap symmetry of an S_z = 0
                                       reference (Section V, spin symmetry): only
                                       determinants whose alpha string is not below
@@ -267,7 +270,8 @@ int pt2_evaluate_device_noalloc(pt2_ctx *ctx, const uint64_t *d_dets, const doub
 /*
  * Evaluate only the listed subsets of a 2^log2p split (0 <= log2p <= 12) of the external space
  * (Algorithm 2; each subset on its own), from host arrays.
- *   parts   host, nparts subset indices in [0, 2^log2p)
+ *   parts   host, nparts distinct subset indices in [0, 2^log2p) (an index
+ *           out of range or listed twice: PT2_E_INVALID)
  *   e_parts host, nparts FP64 outputs, the energy of each listed subset
  * out holds the totals over the listed subsets.  Used to check sampled
  * subsets of large workloads, and to shard a workload over devices.

@@ -175,6 +175,7 @@ struct Small {  // one device block for small control data
     CollList coll[RED_GRID];  // hash records: collided segments per single-pass workgroup
     Partial result;
     unsigned long long n_out;
+    AnchorBlk anc;            // the anchor of the diagonals (one evaluation)
 };
 
 struct Workspace {
@@ -576,18 +577,23 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
     int rc;
     const int Pn = 1 << P.log2p;
     const int pm = c->opt.precision;
-    if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * Pn * 4)))
+    // the bucketed count takes only the listed subsets; the enumerating count
+    // (a cutoff, the spin flip) takes every subset
+    const bool listed = P.target && cutoff <= 0.0 && !sys.z2;
+    const size_t ncols = listed ? P.parts.size() : (size_t)Pn;
+    if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * ncols * 4)))
         return rc;
     if ((rc = buf_ensure(ws.A, ws.off, (size_t)P.nchunks * P.parts.size() * 8)) ||
         (rc = buf_ensure(ws.A, ws.tot, P.parts.size() * 8)) ||
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    if (P.target && cutoff <= 0.0 && !sys.z2)
-        HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (uint32_t *)ws.cnt.p, st));
+    if (listed)
+        HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (const uint32_t *)ws.parts_dev.p,
+                                   (int)P.parts.size(), (uint32_t *)ws.cnt.p, st));
     else
         HIPCHK(launch_count(sys, L, pm, refs, nref, P.chunk, P.log2p, cutoff, (uint32_t *)ws.cnt.p, P.nchunks, st));
-    HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, (const uint32_t *)ws.parts_dev.p,
+    HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, listed ? nullptr : (const uint32_t *)ws.parts_dev.p,
                              (int)P.parts.size(), (uint64_t *)ws.off.p, (uint64_t *)ws.tot.p, st));
     tot_out.assign(P.parts.size(), 0);
     HIPCHK(hipMemcpyAsync(tot_out.data(), ws.tot.p, P.parts.size() * 8, hipMemcpyDeviceToHost, st));
@@ -644,6 +650,10 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
                     return fail(PT2_E_INVALID, "subset index %u out of range", J.parts[i]);
                 P.parts.push_back(J.parts[i]);
             }
+            std::vector<uint32_t> u(P.parts);
+            std::sort(u.begin(), u.end());
+            if (std::adjacent_find(u.begin(), u.end()) != u.end())
+                return fail(PT2_E_INVALID, "subset %u is listed twice", *std::adjacent_find(u.begin(), u.end()));
         } else {
             for (uint32_t p = 0; p < (1u << k); p++)
                 P.parts.push_back(p);
@@ -844,6 +854,18 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
         HIPCHK(launch_parent_g(sys, refs, J.n, J.e0, (double *)ws.hp.p, (double *)ws.gv.p, st));
     }
+    // the anchor of the diagonals of bitstring and rank-key records: the first
+    // sorted reference, its energy and g vector, and its hot pair rows (their
+    // count sizes the single pass's LDS); hash records take each diagonal
+    // relative to the record's parent instead
+    int anc_nh = 0;
+    if (!RL.hash) {
+        Small *d0 = ws.dsmall();
+        HIPCHK(launch_anchor(sys, refs, J.n, J.e0, &d0->anc, st));
+        HIPCHK(hipMemcpyAsync(&ws.host_small->anc.nh, &d0->anc.nh, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        anc_nh = ws.host_small->anc.nh;
+    }
     // subtraction form: sum_i c_i^2 (E0 - H_ii), removed from the total below
     double ref_terms = 0.0;
     if (subtract) {
@@ -865,31 +887,32 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         mx = std::max(mx, s);
     uint32_t key_bits = (uint32_t)RL.bits;
     if (RL.hash) {
-        // sort on the hash bits that take the fewest digit passes while the
-        // expected number of colliding pairs in the largest subset,
-        // N^2 / 2^(b+1), stays at 256 or fewer; among choices with equal
-        // passes, the most bits (collided runs are resolved exactly, but each
-        // costs a revisit of its workgroup's records).  The subset fixes the
-        // top log2p bits of the hash, so a top byte inside them is a digit
-        // with one value, which the sort skips: with 512 subsets, 64 bits take
-        // the passes of 56.
+        // sort on the top b bits of the hash, the fewest digit passes for
+        // which the expected number of colliding pairs among the largest
+        // subset's N records, N^2 / 2^(b - log2p + 1), stays at 16384 or fewer
+        // (the subset fixes the top log2p bits; collided runs are resolved
+        // exactly, each by a revisit of its own records, about 4 per
+        // single-pass workgroup at that bound); among choices with equal
+        // passes, the most bits.  A byte of the hash with no kept, varying
+        // bit is a digit with one value, which the sort skips: with 512
+        // subsets, 56 bits take 6 passes.
         int b = 64;
         if (c->opt.hash_bits == 0) {
             auto passes = [&](int bits) {
                 int np = 0;
-                for (int d = 0; d < bits / 8; d++)
-                    np += 8 * d >= 64 - P.log2p ? 0 : 1;
+                for (int d = 0; d < 8; d++)
+                    np += (8 * d + 8 > 64 - bits && 8 * d < 64 - P.log2p) ? 1 : 0;
                 return np;
             };
             int best = 64;
             for (int bits = 64; bits >= 32; bits -= 8) {
-                if ((double)mx * (double)mx / std::ldexp(1.0, bits + 1) > 256.0)
+                if ((double)mx * (double)mx / std::ldexp(1.0, bits - P.log2p + 1) > 16384.0)
                     break;
                 if (passes(bits) < passes(best))
                     best = bits;
             }
             b = best;
-            sys.kc.hash_mask = b >= 64 ? ~0ull : ((1ull << b) - 1);
+            sys.kc.hash_mask = b >= 64 ? ~0ull : ~((1ull << (64 - b)) - 1);
         } else {
             b = c->opt.hash_bits >= 64 ? 64 : c->opt.hash_bits;
         }
@@ -964,12 +987,12 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
         if (RL.hash)
-            HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n, (const double *)ws.hp.p,
-                                      (const double *)ws.gv.p, J.e0, subtract ? 0 : 1, ds->partials, ds->coll,
-                                      &ds->flags, st));
+            HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n,
+                                      (const double *)ws.hp.p, (const double *)ws.gv.p, J.e0, subtract ? 0 : 1,
+                                      ds->partials, ds->coll, &ds->flags, st));
         else
-            HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, (int64_t *)ws.tref.p, subtract ? 0 : 1,
-                                 ds->partials, &ds->flags, st));
+            HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, &ds->anc, anc_nh, (int64_t *)ws.tref.p,
+                                 subtract ? 0 : 1, ds->partials, &ds->flags, st));
         HIPCHK(launch_final(ds->partials, &ds->result, st));
         if ((rc = timed_end(ws, tm, st, a, 2)))
             return rc;

@@ -670,7 +670,7 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
                                                      uint64_t *off, uint64_t *tot)
 {
     __shared__ uint64_t sh[1024];
-    const uint32_t p = parts[blockIdx.x];
+    const uint32_t p = parts ? parts[blockIdx.x] : blockIdx.x;
     const uint32_t *src = cnt + (int64_t)p * nchunks;
     uint64_t *dst = off + (int64_t)blockIdx.x * nchunks;
     uint64_t carry = 0;
@@ -712,7 +712,9 @@ __global__ __launch_bounds__(1024) void k_chunk_scan(const uint32_t *cnt, int64_
 
 struct Tgt {
     uint32_t *bstart;  // [B + 1] bucket counts; after filling, bstart[b] = end of bucket b
-    uint32_t *hist;    // [B] subset counts (count pass only; aliases blist..pre)
+    uint32_t *hist;    // [B] counts of the listed subsets (count pass only; aliases blist..pre)
+    uint16_t *pmap;    // [B] position of a subset in the list, 0xFFFF if unlisted (count pass)
+    uint16_t *plist;   // [B] the listed subsets (count pass)
     uint16_t *blist;   // [max inner] inner indices grouped by bucket
     uint16_t *tgt;     // [max outer] matching bucket of each outer part
     uint32_t *pre;     // [max outer + 1] prefix of matching inner counts
@@ -739,17 +741,22 @@ __host__ __device__ inline size_t tgt_lds_layout(const ExcLayout &L, int log2p, 
     o[2] = x, x = align16(x + 2 * (size_t)(mi > 0 ? mi : 1));
     o[3] = x, x = align16(x + 2 * (size_t)(mo > 0 ? mo : 1));
     o[4] = x, x = align16(x + 4 * ((size_t)mo + 1));
-    // the count pass keeps its subset counts where generation keeps its lists
+    // the count pass keeps its subset counts, the subset list and its
+    // inverse where generation keeps its lists
     o[1] = rest;
-    const size_t xc = align16(rest + 4 * B);
+    o[6] = align16(rest + 4 * B);
+    o[7] = align16(o[6] + 2 * B);
+    const size_t xc = align16(o[7] + 2 * B);
     return x > xc ? x : xc;
 }
 
 __device__ inline Tgt carve_tgt(char *base, const ExcLayout &L, int log2p)
 {
-    size_t o[6];
+    size_t o[8];
     tgt_lds_layout(L, log2p, o);
     Tgt t;
+    t.pmap = (uint16_t *)(base + o[6]);
+    t.plist = (uint16_t *)(base + o[7]);
     t.bstart = (uint32_t *)(base + o[0]);
     t.hist = (uint32_t *)(base + o[1]);
     t.blist = (uint16_t *)(base + o[2]);
@@ -1009,42 +1016,56 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
         atomicOr(&flags->err, ERR_OVERFLOW);
 }
 
-// Subset counts of every reference determinant (cutoff 0): cnt[p * nref + det].
+// Counts of the listed subsets parts[0..nparts) of every reference
+// determinant (cutoff 0): cnt[j * nref + det] for the j-th listed subset.
 template <int W>
 __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
-                                                              int log2p, uint32_t *cnt)
+                                                              int log2p, const uint32_t *parts, int nparts,
+                                                              uint32_t *cnt)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
     Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x, B = 1 << log2p;
-    uint32_t *hist = t.hist;  // [B]
+    uint32_t *hist = t.hist;  // [nparts]
     det_setup<W>(g, s, L, refs, det, false);
     const DivConsts D = div_consts(L);
     const uint64_t zp = g.head->z;
-    for (int b = tid; b < B; b += GEN_THREADS)
+    for (int b = tid; b < B; b += GEN_THREADS) {
         hist[b] = 0;
+        t.pmap[b] = 0xFFFFu;
+    }
+    __syncthreads();
+    for (int j = tid; j < nparts; j += GEN_THREADS) {
+        t.plist[j] = (uint16_t)parts[j];
+        t.pmap[parts[j]] = (uint16_t)j;
+    }
     __syncthreads();
     for (int64_t k = tid; k < L.o2; k += GEN_THREADS) {
         const Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        atomicAdd(&hist[top_bits(z, log2p)], 1u);
+        const uint32_t j = t.pmap[top_bits(z, log2p)];
+        if (j != 0xFFFFu)
+            atomicAdd(&hist[j], 1u);
     }
     for (int kind = 2; kind <= 4; kind++) {
         const int no = n_outer(L, kind), ni = n_inner(L, kind);
         if (no == 0 || ni == 0)
             continue;
         if (B <= ni) {
-            // bucket counts, then every (outer part, bucket) pair
+            // bucket counts, then every (outer part, listed subset) pair: the
+            // inner parts completing o into subset p are the bucket
+            // p ^ top(z(D) ^ h_o)
             build_buckets(g, t, L, s.norb, kind, log2p, false);
-            const int64_t np = (int64_t)no * B;
-            for (int64_t x = tid; x < np; x += GEN_THREADS) {
-                const int o = (int)(x >> log2p), b = (int)(x & (B - 1));
-                const uint32_t c = t.bstart[b];
+            const uint32_t np = (uint32_t)no * (uint32_t)nparts;
+            for (uint32_t x = tid; x < np; x += GEN_THREADS) {
+                const uint32_t o = x / (uint32_t)nparts, j = x - o * (uint32_t)nparts;
+                const uint32_t c =
+                    t.bstart[t.plist[j] ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, (int)o), log2p)];
                 if (c)
-                    atomicAdd(&hist[b ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p)], c);
+                    atomicAdd(&hist[j], c);
             }
         } else {
             // fewer inner parts than subsets: every pair
@@ -1052,14 +1073,16 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
             for (int64_t x = tid; x < np; x += GEN_THREADS) {
                 const int o = (int)(x / ni), q = (int)(x - (int64_t)o * ni);
                 const uint64_t z = zp ^ outer_hash(g, L, s.norb, kind, o) ^ inner_hash(g, L, s.norb, kind, q);
-                atomicAdd(&hist[top_bits(z, log2p)], 1u);
+                const uint32_t j = t.pmap[top_bits(z, log2p)];
+                if (j != 0xFFFFu)
+                    atomicAdd(&hist[j], 1u);
             }
         }
         __syncthreads();
     }
     __syncthreads();
-    for (int b = tid; b < B; b += GEN_THREADS)
-        cnt[(int64_t)b * nref + det] = hist[b];
+    for (int j = tid; j < nparts; j += GEN_THREADS)
+        cnt[(int64_t)j * nref + det] = hist[j];
 }
 
 // Rank keys of the sorted bitstring references, same order, with their
@@ -1145,7 +1168,7 @@ size_t gen_lds_bytes(const ExcLayout &L)
 
 size_t target_lds_bytes(const ExcLayout &L, int log2p)
 {
-    size_t o[6];
+    size_t o[8];
     return gen_lds_bytes(L) + tgt_lds_layout(L, log2p, o);
 }
 
@@ -1224,13 +1247,13 @@ hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs
 }
 template <int W>
 hipError_t count_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                          uint32_t *cnt, hipStream_t st)
+                          const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st)
 {
-    if (nref == 0)
+    if (nref == 0 || nparts == 0)
         return hipSuccess;
     const size_t lds = target_lds_bytes(L, log2p);
     hipLaunchKernelGGL((k_count_target<W>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
-                       log2p, cnt);
+                       log2p, parts, nparts, cnt);
     return hipGetLastError();
 }
 
@@ -1267,15 +1290,15 @@ hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int pm, const
 }
 
 hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                               uint32_t *cnt, hipStream_t st)
+                               const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st)
 {
     if (!target_ok(L, nref, log2p))
         return hipErrorInvalidValue;
     switch (s.W) {
-    case 1: return count_target_t<1>(s, L, refs, nref, log2p, cnt, st);
-    case 2: return count_target_t<2>(s, L, refs, nref, log2p, cnt, st);
-    case 3: return count_target_t<3>(s, L, refs, nref, log2p, cnt, st);
-    case 4: return count_target_t<4>(s, L, refs, nref, log2p, cnt, st);
+    case 1: return count_target_t<1>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
+    case 2: return count_target_t<2>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
+    case 3: return count_target_t<3>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
+    case 4: return count_target_t<4>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
     default: return hipErrorInvalidValue;
     }
 }

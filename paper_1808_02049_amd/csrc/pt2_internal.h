@@ -34,7 +34,6 @@ constexpr int RED_ITEMS = 4;
 constexpr int RED_TILE = RED_THREADS * RED_ITEMS;     // records per reduce tile
 constexpr int RED_GRID = 4096;                        // fixed -> bit-reproducible sums
 constexpr int RED_LDS_REFS = 64;                      // reference keys staged per tile
-constexpr size_t RED_LDS_TABLE_MAX = 36 * 1024;       // packed diagonal table kept in LDS up to this size
 constexpr size_t RED_LDS_MAX = 64 * 1024;             // dynamic LDS of one single-pass workgroup
 constexpr int GEN_THREADS = 256;
 constexpr int REUSE_GROUP = 32;                      // references per workgroup of k_gen_spin
@@ -67,7 +66,8 @@ struct Flags {
 // fewer bits: 60 instead of 80 for (10a,10b) in 40 orbitals.
 struct KeyCodec {
     int hash;               // 1: records carry (Zobrist hash, parent and flips) instead (see below)
-    uint64_t hash_mask;     // bits of the hash stored (all 64, fewer only to test collisions)
+    uint64_t hash_mask;     // bits of the hash stored: all 64, its top bits (fewer digit
+                            // passes), or its low bits (tests that force collisions)
     int on;                 // 1: records carry rank keys
     int kw;                 // key words of a record (1 or 2)
     int ktop;               // bytes of the records' top key plane
@@ -98,6 +98,24 @@ struct DevSys {
     const double *Tlo;  // the exact rounding error of each T entry (T + Tlo is exact)
     const uint64_t *R;  // Zobrist words, one per bit (2 norb)
     int z2;             // spin flip: generate alpha >= beta only, weight alpha != beta by 2
+};
+
+// The anchor of the diagonals (Appendix, fast diagonal): one determinant A of
+// the reference (the first in sorted order) whose energy and g vector
+// g_x = h_x + sum_{c in A, c != x} T[x][c] are computed once per evaluation;
+// every E0 - H_aa is then taken relative to A.  Pair energies T[x][y] with x
+// or y in a spatial orbital occupied in A (the "hot" rows) are kept as the
+// two integrals J = (pp|qq) and K = (pq|qp) so that the single pass holds
+// them in LDS; other pairs come from the packed table DevSys::T.
+constexpr int ANC_HOT_MAX = 2048;  // entries of the hot J (and K) rows
+struct AnchorBlk {
+    uint64_t bits[MAXW];
+    double d0h, d0l;                     // E0 - E(A), double-double
+    int nh;                              // hot spatial orbitals (0: no hot rows)
+    int pad;
+    int16_t hr[MAXORB];                  // hot row of a spatial orbital, -1 if none
+    double gh[2 * MAXORB], gl[2 * MAXORB];  // g_x(A), double-double
+    double Jh[ANC_HOT_MAX], Kh[ANC_HOT_MAX];  // row r (the r-th hot orbital p), column q: (pp|qq), (pq|qp)
 };
 
 // The alpha string (bits norb..2norb-1) and the beta string (bits 0..norb-1)
@@ -208,7 +226,7 @@ __device__ inline void pl_put(const Planes &p, int w, int64_t i, uint64_t v)
 // determinant) a single-pass workgroup found, by the index of their last
 // record, ascending; n > COLL_LIST means the list overflowed and the
 // workgroup's whole record range is revisited.
-constexpr int COLL_LIST = 8;
+constexpr int COLL_LIST = 32;
 struct CollList {
     uint32_t n, pad;
     int64_t tail[COLL_LIST];
@@ -379,12 +397,15 @@ hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Plane
 // needs cutoff 0; generation walks only the terms of the subset.
 bool target_ok(const ExcLayout &L, int64_t nref, int log2p);
 size_t target_lds_bytes(const ExcLayout &L, int log2p);
+// Counts of the listed subsets only: cnt[j * nref + det] for parts[j] (device
+// list of nparts distinct subsets).
 hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                               uint32_t *cnt, hipStream_t st);
+                               const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st);
 hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                              int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
                              Planes out, Flags *flags, hipStream_t st);
-// Exclusive scan of cnt[p][*] into off[p][*] for each listed subset; tot[k] = N of parts[k].
+// Exclusive scan of cnt[p][*] into off[k][*] for each listed subset p = parts[k]
+// (parts == nullptr: p = k); tot[k] = N of that subset.
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
                              uint64_t *off, uint64_t *tot, hipStream_t st);
 // Compacting generation of subset `part` (offsets from launch_chunk_scan).
@@ -422,8 +443,13 @@ hipError_t launch_planes_to_aos(int W, int pay_bytes, const Planes &in, int64_t 
 // range: scratch of 2 int64 per tile of RED_TILE records.
 // search == 0: no reference search (subtraction form of the exclusion).
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n,
-                         const Planes &refs, int64_t nref, double e0, int64_t *range, int search,
-                         Partial *partials, Flags *flags, hipStream_t st);
+                         const Planes &refs, int64_t nref, double e0, const AnchorBlk *anc, int nh,
+                         int64_t *range, int search, Partial *partials, Flags *flags, hipStream_t st);
+// The anchor block of an evaluation from the sorted bitstring references
+// (bits: W planes, nref of them) and E0; nh: the anchor's hot rows (read back
+// by the host, it sizes the single pass's LDS).
+hipError_t launch_anchor(const DevSys &s, const Planes &bits, int64_t nref, double e0, AnchorBlk *anc,
+                         hipStream_t st);
 // out->e_sum + e_comp = sum over the bitstring references of c_i^2 (E0 - H_ii)
 // (partials: 256 entries of scratch).
 hipError_t launch_ref_terms(const DevSys &s, const Planes &refs, int64_t n, double e0, Partial *partials,

@@ -186,54 +186,118 @@ __device__ inline double den_scratch(const double *Tp, const double *Tl, int nso
     return d.hi + d.lo;
 }
 
-// E0 - H_aa relative to an anchor determinant S0, given d0 = E0 - E(S0) and
-// g_x = h_x + sum_{c in S0, c != x} T[x][c] (both double-double; g as gh + gl):
-// with R the spin-orbitals removed from S0 and A those added,
-//   H = E(S0) - sum_R g_r + sum_A g_a + sum_{r<r' in R} T + sum_{a<a' in A} T
-//       - sum_{a in A, r in R} T[a][r],
-// so E0 - H = d0 + sum_R g_r - sum_A g_a - sum_RR T - sum_AA T + sum_AR T.
+// The anchor block staged in LDS (the parts an evaluation uses).
+struct AncView {
+    const uint64_t *bits;       // MAXW words
+    DD d0;                      // E0 - E(A)
+    const int16_t *hr;          // norb entries
+    const double *gh, *gl;      // nso entries each
+    const double *Jh, *Kh;      // nh x norb each
+};
+
+__host__ __device__ inline size_t anc_lds_bytes(int norb, int nh)
+{
+    return (size_t)MAXW * 8 + (((size_t)norb * 2 + 15) & ~(size_t)15) + (size_t)norb * 32 +
+           (size_t)nh * norb * 16;
+}
+
+// Copy the anchor block into dyn (anc_lds_bytes bytes, 16-byte aligned) with
+// all threads; the caller synchronises before use.
+__device__ inline AncView stage_anchor(const AnchorBlk *g, char *dyn, int norb, int nh, int nthreads)
+{
+    const int tid = threadIdx.x, nso = 2 * norb;
+    AncView v;
+    uint64_t *bits = (uint64_t *)dyn;
+    int16_t *hr = (int16_t *)(dyn + MAXW * 8);
+    double *gh = (double *)(dyn + MAXW * 8 + (((size_t)norb * 2 + 15) & ~(size_t)15));
+    double *gl = gh + nso;
+    double *Jh = gl + nso;
+    double *Kh = Jh + (size_t)nh * norb;
+    if (tid < MAXW)
+        bits[tid] = g->bits[tid];
+    for (int i = tid; i < norb; i += nthreads)
+        hr[i] = g->hr[i];
+    for (int i = tid; i < nso; i += nthreads) {
+        gh[i] = g->gh[i];
+        gl[i] = g->gl[i];
+    }
+    for (int i = tid; i < nh * norb; i += nthreads) {
+        Jh[i] = g->Jh[i];
+        Kh[i] = g->Kh[i];
+    }
+    v.bits = bits, v.hr = hr, v.gh = gh, v.gl = gl, v.Jh = Jh, v.Kh = Kh;
+    v.d0.hi = g->d0h, v.d0.lo = g->d0l;
+    return v;
+}
+
+// x += sign * T[x1][x2] (x1 != x2): from the hot J and K rows when either
+// spatial orbital is occupied in the anchor (a same-spin pair adds J and -K,
+// each exact), else from the packed table.
+__device__ inline void dd_add_t(DD &x, const AncView &a, const double *Tp, const double *Tl, int norb, int x1, int x2,
+                                double sign)
+{
+    const int p = x1 < norb ? x1 : x1 - norb, q = x2 < norb ? x2 : x2 - norb;
+    int r = a.hr[p], c = q;
+    if (r < 0)
+        r = a.hr[q], c = p;
+    if (r >= 0) {
+        const int at = r * norb + c;
+        dd_add(x, sign * a.Jh[at], 0.0);
+        if ((x1 < norb) == (x2 < norb))
+            dd_add(x, -sign * a.Kh[at], 0.0);
+    } else {
+        dd_add_pair(x, Tp, Tl, 2 * norb, x1, x2, sign);
+    }
+}
+
+// E0 - H_aa relative to the anchor A, given d0 = E0 - E(A) and
+// g_x = h_x + sum_{c in A, c != x} T[x][c] (both double-double): with R the
+// spin-orbitals removed from A and P those added,
+//   H = E(A) - sum_R g_r + sum_P g_a + sum_{r<r' in R} T + sum_{a<a' in P} T
+//       - sum_{a in P, r in R} T[a][r],
+// so E0 - H = d0 + sum_R g_r - sum_P g_a - sum_RR T - sum_PP T + sum_PR T.
 // Falls back to the from-scratch sum when the difference is large.
 template <int W>
-__device__ inline double den_anchor(const double *Tp, const double *Tl, int nso, int nel, const uint64_t (&k)[W],
-                                    const uint64_t *anc, const double *gh, const double *gl, DD d0, double e0)
+__device__ inline double den_anchor(const AncView &an, const double *Tp, const double *Tl, int norb, int nel,
+                                    const uint64_t (&k)[W], double e0)
 {
     uint64_t rm[W], ad[W];
     int m = 0;
 #pragma unroll
     for (int w = 0; w < W; w++) {
-        const uint64_t d = k[w] ^ anc[w];
-        rm[w] = d & anc[w];
+        const uint64_t d = k[w] ^ an.bits[w];
+        rm[w] = d & an.bits[w];
         ad[w] = d & k[w];
         m += __popcll(ad[w]);
     }
     if (2 * m * m + m >= (nel * nel) / 2)
-        return den_scratch<W>(Tp, Tl, nso, k, e0);
-    DD d = d0;
+        return den_scratch<W>(Tp, Tl, 2 * norb, k, e0);
+    DD d = an.d0;
 #pragma unroll
     for (int w1 = 0; w1 < W; w1++) {
         uint64_t x = rm[w1];
         while (x) {
             const int r = w1 * 64 + __builtin_ctzll(x);
             x &= x - 1;
-            dd_add(d, gh[r], gl[r]);
+            dd_add(d, an.gh[r], an.gl[r]);
             uint64_t y = x;  // r < r' within R
             while (y) {
-                dd_add_pair(d, Tp, Tl, nso, r, w1 * 64 + __builtin_ctzll(y), -1.0);
+                dd_add_t(d, an, Tp, Tl, norb, r, w1 * 64 + __builtin_ctzll(y), -1.0);
                 y &= y - 1;
             }
 #pragma unroll
             for (int w2 = w1 + 1; w2 < W; w2++) {
                 uint64_t z = rm[w2];
                 while (z) {
-                    dd_add_pair(d, Tp, Tl, nso, r, w2 * 64 + __builtin_ctzll(z), -1.0);
+                    dd_add_t(d, an, Tp, Tl, norb, r, w2 * 64 + __builtin_ctzll(z), -1.0);
                     z &= z - 1;
                 }
             }
 #pragma unroll
             for (int w2 = 0; w2 < W; w2++) {
-                uint64_t z = ad[w2];  // cross pairs with A
+                uint64_t z = ad[w2];  // cross pairs with P
                 while (z) {
-                    dd_add_pair(d, Tp, Tl, nso, r, w2 * 64 + __builtin_ctzll(z), 1.0);
+                    dd_add_t(d, an, Tp, Tl, norb, r, w2 * 64 + __builtin_ctzll(z), 1.0);
                     z &= z - 1;
                 }
             }
@@ -245,17 +309,17 @@ __device__ inline double den_anchor(const double *Tp, const double *Tl, int nso,
         while (x) {
             const int a = w1 * 64 + __builtin_ctzll(x);
             x &= x - 1;
-            dd_add(d, -gh[a], -gl[a]);
+            dd_add(d, -an.gh[a], -an.gl[a]);
             uint64_t y = x;
             while (y) {
-                dd_add_pair(d, Tp, Tl, nso, a, w1 * 64 + __builtin_ctzll(y), -1.0);
+                dd_add_t(d, an, Tp, Tl, norb, a, w1 * 64 + __builtin_ctzll(y), -1.0);
                 y &= y - 1;
             }
 #pragma unroll
             for (int w2 = w1 + 1; w2 < W; w2++) {
                 uint64_t z = ad[w2];
                 while (z) {
-                    dd_add_pair(d, Tp, Tl, nso, a, w2 * 64 + __builtin_ctzll(z), -1.0);
+                    dd_add_t(d, an, Tp, Tl, norb, a, w2 * 64 + __builtin_ctzll(z), -1.0);
                     z &= z - 1;
                 }
             }
@@ -294,16 +358,10 @@ struct RefSlice {
 };
 
 // One distinct bitstring with its numerator: exclusion test, then the term.
-struct Anchor {
-    const uint64_t *key;    // LDS, W words
-    const double *gh, *gl;  // LDS, nso entries each: the g vector, double-double
-    DD d0;                  // E0 - E(anchor)
-};
-
 // k is the record key (W words); the diagonal and the checksum use the
 // bitstring (WB words), which is k itself or, for rank keys, unranked from it.
 template <int W, int WB, bool RK>
-__device__ inline void process_segment(const DevSys &s, const double *Tp, const double *Tl, const Anchor &an,
+__device__ inline void process_segment(const DevSys &s, const double *Tp, const double *Tl, const AncView &an,
                                        const Planes &refs,
                                        const RefSlice &rs, const uint64_t *s_rk, const double *s_rc, double e0,
                                        const uint64_t (&k)[W], double num, Acc &a, const uint64_t *binom,
@@ -366,7 +424,7 @@ __device__ inline void process_segment(const DevSys &s, const double *Tp, const 
         for (int w = 0; w < WB; w++)
             kb[w] = k[w < W ? w : 0];
     }
-    const double den = den_anchor<WB>(Tp, Tl, 2 * s.norb, s.na + s.nb, kb, an.key, an.gh, an.gl, an.d0, e0);
+    const double den = den_anchor<WB>(an, Tp, Tl, s.norb, s.na + s.nb, kb, e0);
     a.n_ext++;
     const double ad = fabs(den);
     a.min_abs = ad < a.min_abs ? ad : a.min_abs;
@@ -409,6 +467,7 @@ __device__ inline int64_t ref_advance(const Planes &refs, int64_t nref, int64_t 
     return cur < nref ? cur : nref;
 }
 
+
 constexpr int RED_Q = RED_TILE + 1;  // segment ends of one tile plus a continuation
 
 // Reference range of every tile: [lo, hi) holds the reference keys between
@@ -431,10 +490,31 @@ __global__ void k_tile_refs(Planes in, int64_t n, Planes refs, int64_t nref, int
     }
 }
 
+// Partial sums of one workgroup, combined in a fixed order.
+__device__ inline void partial_merge(Partial &x, const Partial &y)
+{
+    double sum = x.e_sum, comp = x.e_comp + y.e_comp;
+    neumaier(sum, comp, y.e_sum);
+    x.e_sum = sum, x.e_comp = comp;
+    x.ref_cross += y.ref_cross;
+    x.min_abs_denom = y.min_abs_denom < x.min_abs_denom ? y.min_abs_denom : x.min_abs_denom;
+    x.n_unique += y.n_unique, x.n_external += y.n_external, x.n_hit += y.n_hit;
+    x.n_nonneg += y.n_nonneg, x.key_xor ^= y.key_xor, x.key_sum += y.key_sum;
+}
+
+__device__ inline Partial acc_partial(const Acc &a)
+{
+    Partial me;
+    me.e_sum = a.e_sum, me.e_comp = a.e_comp, me.ref_cross = a.ref_cross, me.min_abs_denom = a.min_abs;
+    me.n_unique = a.n_unique, me.n_external = a.n_ext, me.n_hit = a.n_hit, me.n_nonneg = a.n_nonneg;
+    me.key_xor = a.kx, me.key_sum = a.ks;
+    return me;
+}
+
 // Each workgroup takes a contiguous range of tiles.
 template <int W, int PB, int WB, bool RK>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int64_t n, Planes refs, int64_t nref,
-                                                        double e0, int64_t tiles_per_block, int lds_table,
+                                                        double e0, const AnchorBlk *anc, int nh, int64_t tiles_per_block,
                                                         size_t q_bytes, const int64_t *range, int search,
                                                         Partial *partials, Flags *flags)
 {
@@ -448,40 +528,26 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     __shared__ double s_cv;
     __shared__ int64_t s_lo, s_hi;
     __shared__ int s_cflag;
-    __shared__ uint64_t s_anc[WB];
-    __shared__ double s_er[RED_THREADS / 64], s_erl[RED_THREADS / 64];
     __shared__ Partial s_wp[RED_THREADS / 64];
 
-    const int nso = 2 * s.norb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // queue of owned segment ends: the numerator and the record's index in
     // its tile (the key is read back from the tile, which is in the caches)
     double *q_num = (double *)dyn;                            // [RED_Q]
     uint32_t *q_idx = (uint32_t *)(dyn + (size_t)RED_Q * 8);  // [RED_Q]
-    // g vector of the tile's anchor (nso entries, high then low parts) after
-    // the queue region
-    double *s_g = (double *)(dyn + q_bytes);
-    double *s_gl = s_g + nso;
+    // the evaluation's anchor after the queue region, then the binomial
+    // table for unranking rank keys
+    const AncView an = stage_anchor(anc, dyn + q_bytes, s.norb, nh, RED_THREADS);
     const double *Tp = s.T;
     const double *Tl = s.Tlo;
-    const int ntri = nso * (nso + 1) / 2;
-    if (lds_table) {
-        double *t = (double *)(dyn + q_bytes + (size_t)nso * 16);
-        for (int i = tid; i < ntri; i += RED_THREADS)
-            t[i] = s.T[i];
-        Tp = t;
-    }
-    // binomial table for unranking rank keys, after the pair table
     uint64_t *binom = nullptr;
     if constexpr (RK) {
-        binom = (uint64_t *)(dyn + q_bytes + (size_t)nso * 16 + (lds_table ? (size_t)ntri * 8 : 0));
+        binom = (uint64_t *)(dyn + q_bytes + anc_lds_bytes(s.norb, nh));
         const int nb = (s.norb + 1) * s.kc.stride;
         for (int i = tid; i < nb; i += RED_THREADS)
             binom[i] = s.kc.binom[i];
     }
-    // the staged tables are read by other threads from here on: thread 0
-    // unranks each tile's anchor with the binomial table before the tile's
-    // first barrier
+    // the staged tables are read by every thread from here on
     __syncthreads();
     Acc a;
     acc_init(a);
@@ -492,8 +558,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
     for (int64_t tile = t_begin; tile < t_end; tile++) {
         const int64_t base = tile * RED_TILE;
         const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
-        // this thread's records and their neighbours' keys, requested first so
-        // that the loads overlap the anchor set-up below
         const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
         uint64_t k[RED_ITEMS][W];
         double p[RED_ITEMS];
@@ -518,64 +582,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         if (has_next)
             load_key<W>(in, r0 + RED_ITEMS, kn);
         if (tid == 0) {
-            uint64_t kf[W];
-            load_key<W>(in, base, kf);
-            {
-                s_lo = range[2 * tile];
-                s_hi = range[2 * tile + 1];
-                s_cflag = 0;
-                if constexpr (RK) {
-                    uint64_t kb[WB];
-                    unrank_key<WB>(kf[0], W > 1 ? kf[W > 1 ? 1 : 0] : 0ull, s.norb, s.na, s.nb, s.kc.bb, binom,
-                                   s.kc.stride, kb);
-#pragma unroll
-                    for (int w = 0; w < WB; w++)
-                        s_anc[w] = kb[w];
-                } else {
-#pragma unroll
-                    for (int w = 0; w < WB; w++)
-                        s_anc[w] = kf[w < W ? w : 0];
-                }
-            }
+            s_lo = range[2 * tile];
+            s_hi = range[2 * tile + 1];
+            s_cflag = 0;
         }
         __syncthreads();
-        // anchor of this tile = its first record: g_x for every spin-orbital x
-        // and twice the anchor's energy, sum over its occupied x of h_x + g_x
-        // (each pair counted from both ends), all double-double
-        {
-            DD ex = {0.0, 0.0};
-            if (tid < nso) {
-                const int bx = tid;
-                const bool occ = (s_anc[bx >> 6] >> (bx & 63)) & 1ull;
-                const double hx = Tp[tri_row(bx, nso) + bx];
-                DD gx = {hx, 0.0};
-#pragma unroll
-                for (int w = 0; w < WB; w++) {
-                    uint64_t m = s_anc[w];
-                    while (m) {
-                        const int c = w * 64 + __builtin_ctzll(m);
-                        m &= m - 1;
-                        if (c != bx)
-                            dd_add_pair(gx, Tp, Tl, nso, bx, c, 1.0);
-                    }
-                }
-                s_g[bx] = gx.hi;
-                s_gl[bx] = gx.lo;
-                if (occ) {
-                    ex = gx;
-                    dd_add(ex, hx, 0.0);
-                }
-            }
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const DD y = {__shfl_down(ex.hi, o), __shfl_down(ex.lo, o)};
-                ex = dd_sum(ex, y);
-            }
-            if (lane == 0) {
-                s_er[wave] = ex.hi;
-                s_erl[wave] = ex.lo;
-            }
-        }
         RefSlice rs;
         rs.lo = s_lo, rs.hi = s_hi;
         rs.staged = search && (rs.hi - rs.lo) <= RED_LDS_REFS;
@@ -733,18 +744,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(DevSys s, Planes in, int
         }
         __syncthreads();
         const int qn = (int)qtot + cflag;
-        Anchor an;
-        an.key = s_anc;
-        an.gh = s_g;
-        an.gl = s_gl;
-        {
-            DD e2 = {0.0, 0.0};  // 2 E(anchor)
-#pragma unroll
-            for (int w = 0; w < RED_THREADS / 64; w++)
-                dd_add(e2, s_er[w], s_erl[w]);
-            an.d0.hi = e0, an.d0.lo = 0.0;
-            dd_add(an.d0, -0.5 * e2.hi, -0.5 * e2.lo);
-        }
         for (int e = tid; e < qn; e += RED_THREADS) {
             uint64_t kk[W];
             load_key<W>(in, base + q_idx[e], kk);
@@ -834,6 +833,96 @@ __global__ __launch_bounds__(256) void k_ref_terms(DevSys s, Planes refs, int64_
         p.e_sum = s_s[0], p.e_comp = s_c[0], p.ref_cross = 0.0, p.min_abs_denom = __builtin_inf();
         p.n_unique = p.n_external = p.n_hit = p.n_nonneg = p.key_xor = p.key_sum = 0;
         partials[blockIdx.x] = p;
+    }
+}
+
+// The anchor block of an evaluation: A is the first sorted reference (an
+// empty determinant when there is none, for which the same formulas hold).
+// One workgroup: the hot rows (J and K of the spatial orbitals occupied in A
+// in either spin, if they fit), g_x(A) for every spin-orbital x (one thread
+// per x) and E0 - E(A), where E(A) is half the sum over occupied x of
+// h_x + g_x (every pair is counted from both ends), all double-double.
+template <int WB>
+__global__ __launch_bounds__(256) void k_anchor(DevSys s, Planes bits, int64_t nref, double e0, AnchorBlk *out)
+{
+    __shared__ uint64_t s_k[MAXW];
+    __shared__ int16_t s_hr[MAXORB];
+    __shared__ int s_nh;
+    __shared__ double s_row[256 / 64], s_rowl[256 / 64];
+    const int norb = s.norb, nso = 2 * norb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < MAXW)
+        s_k[tid] = tid < WB && nref > 0 ? pl_get<WB>(bits, tid, 0) : 0ull;
+    __syncthreads();
+    if (tid == 0) {
+        int nh = 0;
+        for (int p = 0; p < norb; p++) {
+            const int b = p + norb;
+            const bool occ = ((s_k[p >> 6] >> (p & 63)) & 1ull) || ((s_k[b >> 6] >> (b & 63)) & 1ull);
+            s_hr[p] = occ ? (int16_t)nh++ : (int16_t)-1;
+        }
+        if (nh * norb > ANC_HOT_MAX) {
+            for (int p = 0; p < norb; p++)
+                s_hr[p] = -1;
+            nh = 0;
+        }
+        s_nh = nh;
+    }
+    __syncthreads();
+    if (tid < MAXW)
+        out->bits[tid] = s_k[tid];
+    for (int p = tid; p < MAXORB; p += 256)
+        out->hr[p] = p < norb ? s_hr[p] : (int16_t)-1;
+    if (tid == 0)
+        out->nh = s_nh;
+    const int64_t n = norb;
+    for (int x = tid; x < norb * norb; x += 256) {
+        const int p = x / norb, q = x - p * norb, r = s_hr[p];
+        if (r >= 0) {
+            out->Jh[r * norb + q] = s.V[((p * n + p) * n + q) * n + q];
+            out->Kh[r * norb + q] = s.V[((p * n + q) * n + q) * n + p];
+        }
+    }
+    DD ex = {0.0, 0.0};
+    if (tid < nso) {
+        const int bx = tid;
+        const bool occ = (s_k[bx >> 6] >> (bx & 63)) & 1ull;
+        const double hx = s.T[tri_row(bx, nso) + bx];
+        DD gx = {hx, 0.0};
+#pragma unroll
+        for (int w = 0; w < MAXW; w++) {
+            uint64_t m = s_k[w];
+            while (m) {
+                const int c = w * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                if (c != bx)
+                    dd_add_pair(gx, s.T, s.Tlo, nso, bx, c, 1.0);
+            }
+        }
+        out->gh[bx] = gx.hi;
+        out->gl[bx] = gx.lo;
+        if (occ) {
+            ex = gx;
+            dd_add(ex, hx, 0.0);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const DD y = {__shfl_down(ex.hi, o), __shfl_down(ex.lo, o)};
+        ex = dd_sum(ex, y);
+    }
+    if (lane == 0) {
+        s_row[wave] = ex.hi;
+        s_rowl[wave] = ex.lo;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        DD e2 = {0.0, 0.0};
+        for (int w = 0; w < 256 / 64; w++)
+            dd_add(e2, s_row[w], s_rowl[w]);
+        DD d = {e0, 0.0};
+        dd_add(d, -0.5 * e2.hi, -0.5 * e2.lo);
+        out->d0h = d.hi;
+        out->d0l = d.lo;
     }
 }
 
@@ -1203,27 +1292,6 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Pl
     const uint64_t m = key_mix<WB>(k);
     a.kx ^= m;
     a.ks += m;
-}
-
-// Partial sums of one workgroup, combined in a fixed order.
-__device__ inline void partial_merge(Partial &x, const Partial &y)
-{
-    double sum = x.e_sum, comp = x.e_comp + y.e_comp;
-    neumaier(sum, comp, y.e_sum);
-    x.e_sum = sum, x.e_comp = comp;
-    x.ref_cross += y.ref_cross;
-    x.min_abs_denom = y.min_abs_denom < x.min_abs_denom ? y.min_abs_denom : x.min_abs_denom;
-    x.n_unique += y.n_unique, x.n_external += y.n_external, x.n_hit += y.n_hit;
-    x.n_nonneg += y.n_nonneg, x.key_xor ^= y.key_xor, x.key_sum += y.key_sum;
-}
-
-__device__ inline Partial acc_partial(const Acc &a)
-{
-    Partial me;
-    me.e_sum = a.e_sum, me.e_comp = a.e_comp, me.ref_cross = a.ref_cross, me.min_abs_denom = a.min_abs;
-    me.n_unique = a.n_unique, me.n_external = a.n_ext, me.n_hit = a.n_hit, me.n_nonneg = a.n_nonneg;
-    me.key_xor = a.kx, me.key_sum = a.ks;
-    return me;
 }
 
 // Tree sum of the workgroup's per-thread partials (s_p holds RED_THREADS).
@@ -1793,21 +1861,15 @@ static int64_t red_workers(const void *kernel, size_t dyn)
 }
 
 hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted, int64_t n, const Planes &refs,
-                         int64_t nref, double e0, int64_t *range, int search, Partial *partials, Flags *flags,
-                         hipStream_t st)
+                         int64_t nref, double e0, const AnchorBlk *anc, int nh, int64_t *range, int search,
+                         Partial *partials, Flags *flags, hipStream_t st)
 {
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
-    const int nso = 2 * s.norb;
-    const size_t tri_bytes = (size_t)nso * (nso + 1) / 2 * 8;
-    int lds_table = tri_bytes <= RED_LDS_TABLE_MAX ? 1 : 0;
     const bool rk = s.kc.on != 0;
     size_t q_bytes = (size_t)RED_Q * (8 + 4);
     q_bytes = (q_bytes + 15) & ~(size_t)15;
     const size_t binom_bytes = rk ? (size_t)(s.norb + 1) * s.kc.stride * 8 : 0;
-    const size_t fixed = q_bytes + (size_t)nso * 16 + binom_bytes;
-    if (fixed + (lds_table ? tri_bytes : 0) > RED_LDS_MAX)
-        lds_table = 0;  // the pair table is then read through the caches
-    const size_t dyn = fixed + (lds_table ? tri_bytes : 0);
+    const size_t dyn = q_bytes + anc_lds_bytes(s.norb, nh) + binom_bytes;
     if (dyn > RED_LDS_MAX)
         return hipErrorInvalidValue;
     if (ntiles > 0 && search) {
@@ -1826,8 +1888,8 @@ hipError_t launch_reduce(const DevSys &s, int fp32, int kw, const Planes &sorted
     do {                                                                                                       \
         const int64_t ge = red_workers((const void *)&k_reduce<WW, PB, WBB, RKK>, dyn);                         \
         const int64_t per = (ntiles + ge - 1) / ge;                                                            \
-        hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, per,        \
-                           lds_table, q_bytes, range, search, partials, flags);                                 \
+        hipLaunchKernelGGL((k_reduce<WW, PB, WBB, RKK>), g, b, dyn, st, s, sorted, n, refs, nref, e0, anc, nh,    \
+                           per, q_bytes, range, search, partials, flags);                                       \
     } while (0)
 #define RD2(WW, WBB, RKK)      \
     do {                       \
@@ -1969,6 +2031,22 @@ hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint6
     case 2: hipLaunchKernelGGL((k_refs_aos<2>), g, b, 0, st, bits, n, ra); break;
     case 3: hipLaunchKernelGGL((k_refs_aos<3>), g, b, 0, st, bits, n, ra); break;
     case 4: hipLaunchKernelGGL((k_refs_aos<4>), g, b, 0, st, bits, n, ra); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_anchor(const DevSys &s, const Planes &bits, int64_t nref, double e0, AnchorBlk *anc,
+                         hipStream_t st)
+{
+    if (2 * s.norb > 256)
+        return hipErrorInvalidValue;
+    dim3 g(1), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_anchor<1>), g, b, 0, st, s, bits, nref, e0, anc); break;
+    case 2: hipLaunchKernelGGL((k_anchor<2>), g, b, 0, st, s, bits, nref, e0, anc); break;
+    case 3: hipLaunchKernelGGL((k_anchor<3>), g, b, 0, st, s, bits, nref, e0, anc); break;
+    case 4: hipLaunchKernelGGL((k_anchor<4>), g, b, 0, st, s, bits, nref, e0, anc); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

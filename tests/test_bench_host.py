@@ -49,3 +49,9 @@ def test_host_threads_and_neumaier():
     assert 1 <= bench.host_threads() <= len(__import__("os").sched_getaffinity(0))
     vals = [1e16, 1.0, -1e16, 1.0]
     assert bench.neumaier(vals) == 2.0
+
+
+def test_split_scope_states_partial_runs():
+    import bench
+    assert bench.split_scope(512, 512, 20).startswith("all 512 subsets")
+    assert bench.split_scope(512, 4, 2).startswith("PARTIAL: the first 4 of the 512")

@@ -157,6 +157,20 @@ def test_c1_listed_subsets_match_oracle(c1):
     assert_matches(got, ref)
 
 
+def test_c1_listed_subsets_any_order_and_no_repeats(pt2, c1):
+    """Listed subsets in any order give the energies of those subsets (the
+    count pass counts only the listed ones); a subset listed twice is
+    rejected."""
+    parts = [17, 0, 31, 5]
+    got, ep = c1["ctx"].evaluate_parts(c1["dets"], c1["c"], c1["e0"], 5, parts)
+    ref, rp = c1["O"].pt2(c1["dets"], c1["c"], c1["e0"], log2p=5, parts=parts)
+    np.testing.assert_allclose(ep, rp, rtol=0, atol=1e-11)
+    assert_matches(got, ref)
+    with pytest.raises(pt2.PT2Error) as e:
+        c1["ctx"].evaluate_parts(c1["dets"], c1["c"], c1["e0"], 5, [3, 9, 3])
+    assert e.value.code == pt2.PT2_E_INVALID
+
+
 def test_c1_fp32_payload_form(pt2, c1):
     ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, precision="fp32")
     got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
