@@ -577,9 +577,10 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
     int rc;
     const int Pn = 1 << P.log2p;
     const int pm = c->opt.precision;
-    // the bucketed count takes only the listed subsets; the enumerating count
-    // (a cutoff, the spin flip) takes every subset
-    const bool listed = P.target && cutoff <= 0.0 && !sys.z2;
+    // the bucketed count takes only the listed subsets (with a cutoff or the
+    // spin flip: their bucket walks with the filter); without bucketing, the
+    // enumerating count takes every subset
+    const bool listed = P.target;
     const size_t ncols = listed ? P.parts.size() : (size_t)Pn;
     if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * ncols * 4)))
         return rc;
@@ -588,9 +589,12 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
         (rc = buf_ensure(ws.A, ws.parts_dev, P.parts.size() * 4)))
         return rc;
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
-    if (listed)
+    if (listed && cutoff <= 0.0 && !sys.z2)
         HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (const uint32_t *)ws.parts_dev.p,
                                    (int)P.parts.size(), (uint32_t *)ws.cnt.p, st));
+    else if (listed)
+        HIPCHK(launch_count_target_cut(sys, L, pm, refs, nref, P.log2p, (const uint32_t *)ws.parts_dev.p,
+                                       (int)P.parts.size(), cutoff, (uint32_t *)ws.cnt.p, st));
     else
         HIPCHK(launch_count(sys, L, pm, refs, nref, P.chunk, P.log2p, cutoff, (uint32_t *)ws.cnt.p, P.nchunks, st));
     HIPCHK(launch_chunk_scan((const uint32_t *)ws.cnt.p, P.nchunks, listed ? nullptr : (const uint32_t *)ws.parts_dev.p,

@@ -1085,6 +1085,96 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
         cnt[(int64_t)j * nref + det] = hist[j];
 }
 
+// Counts of the listed subsets with a cutoff (or the spin flip filter): the
+// bucket walk of k_gen_target for each listed subset, counting the walked
+// terms that are kept, so a call costs its own subsets' terms, not an
+// enumeration of every candidate.  cnt[j * nref + det] as k_count_target.
+template <int W, int PM>
+__global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcLayout L, const Planes refs,
+                                                                  int64_t nref, int log2p, const uint32_t *parts,
+                                                                  int nparts, double cutoff, uint32_t *cnt)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    const int64_t det = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, B = 1 << log2p;
+    __shared__ uint32_t s_cnt[GEN_THREADS / 64];
+    det_setup<W>(g, s, L, refs, det);
+    const DivConsts D = div_consts(L);
+    const uint64_t zp = g.head->z;
+    for (int b = tid; b < B; b += GEN_THREADS)
+        t.pmap[b] = 0xFFFFu;
+    __syncthreads();
+    for (int j = tid; j < nparts; j += GEN_THREADS) {
+        t.plist[j] = (uint16_t)parts[j];
+        t.pmap[parts[j]] = (uint16_t)j;
+    }
+    __syncthreads();
+    // the singles of all listed subsets in one enumeration (a few per subset),
+    // counted by atomics into this determinant's output entries; then the
+    // doubles, subset by subset, by block sums
+    for (int j = tid; j < nparts; j += GEN_THREADS)
+        cnt[(int64_t)j * nref + det] = 0;
+    __syncthreads();
+    for (int64_t k = tid; k < L.o2; k += GEN_THREADS) {
+        const Exc e = decode(g, L, D, k);
+        uint64_t key[W], z;
+        exc_key<W>(g, s.norb, e, key, z);
+        const uint32_t j = t.pmap[top_bits(z, log2p)];
+        if (j != 0xFFFFu && keep_term<W, PM>(g, s, L, e, cutoff, key))
+            atomicAdd(&cnt[(int64_t)j * nref + det], 1u);
+    }
+    for (int kind = 2; kind <= 4; kind++) {
+        const int no = n_outer(L, kind);
+        if (no == 0 || n_inner(L, kind) == 0)
+            continue;
+        build_buckets(g, t, L, s.norb, kind, log2p, true);
+        for (int j = 0; j < nparts; j++) {
+            const uint32_t part = t.plist[j];
+            for (int o = tid; o < no; o += GEN_THREADS) {
+                const uint32_t b = part ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p);
+                t.tgt[o] = (uint16_t)b;
+                t.pre[o] = t.bstart[b] - bucket_lo(t, b);
+            }
+            if (tid == 0)
+                t.pre[no] = 0;
+            __syncthreads();
+            const uint32_t T = block_scan_excl(t.pre, no + 1, t.wsum);
+            uint32_t kept = 0;
+            for (uint32_t f = tid; f < T; f += GEN_THREADS) {
+                int lo = 0, hi = no;  // pre[lo] <= f < pre[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (t.pre[mid] <= f)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
+                const Exc e = make_exc(g, L, kind, lo, q);
+                uint64_t key[W], z;
+                exc_key<W>(g, s.norb, e, key, z);
+                kept += keep_term<W, PM>(g, s, L, e, cutoff, key) ? 1u : 0u;
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+                kept += __shfl_xor(kept, o);
+            if (lane == 0)
+                s_cnt[wave] = kept;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t x = 0;
+                for (int w = 0; w < GEN_THREADS / 64; w++)
+                    x += s_cnt[w];
+                cnt[(int64_t)j * nref + det] += x;
+            }
+            // t.pre and t.tgt are rebuilt for the next subset
+            __syncthreads();
+        }
+    }
+}
+
 // Rank keys of the sorted bitstring references, same order, with their
 // coefficients (the single pass matches records against these).
 template <int W>
@@ -1269,6 +1359,17 @@ hipError_t gen_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs,
                        log2p, part, cutoff, off, tot, out, flags);
     return hipGetLastError();
 }
+template <int W, int PM>
+hipError_t count_target_cut_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                              const uint32_t *parts, int nparts, double cutoff, uint32_t *cnt, hipStream_t st)
+{
+    if (nref == 0 || nparts == 0)
+        return hipSuccess;
+    const size_t lds = target_lds_bytes(L, log2p);
+    hipLaunchKernelGGL((k_count_target_cut<W, PM>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs,
+                       nref, log2p, parts, nparts, cutoff, cnt);
+    return hipGetLastError();
+}
 }  // namespace
 
 hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref, int64_t chunk, int log2p, double cutoff, uint32_t *cnt, int64_t nchunks,
@@ -1301,6 +1402,17 @@ hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes
     case 4: return count_target_t<4>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_count_target_cut(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
+                                   int log2p, const uint32_t *parts, int nparts, double cutoff, uint32_t *cnt,
+                                   hipStream_t st)
+{
+    if (!target_ok(L, nref, log2p))
+        return hipErrorInvalidValue;
+#define CALL(W, F) count_target_cut_t<W, F>(s, L, refs, nref, log2p, parts, nparts, cutoff, cnt, st)
+    PT2_DISPATCH(s.W, pm, CALL)
+#undef CALL
 }
 
 hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,

@@ -401,6 +401,12 @@ size_t target_lds_bytes(const ExcLayout &L, int log2p);
 // list of nparts distinct subsets).
 hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
                                const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st);
+// As launch_count_target, with a cutoff or the spin flip filter applied to
+// the terms of the listed subsets (their bucket walks; pm sets the value's
+// precision for the cutoff test).
+hipError_t launch_count_target_cut(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
+                                   int log2p, const uint32_t *parts, int nparts, double cutoff, uint32_t *cnt,
+                                   hipStream_t st);
 hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                              int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
                              Planes out, Flags *flags, hipStream_t st);
