@@ -167,6 +167,14 @@ typedef struct {
                                       alpha-alpha doubles, grouped by alpha string;
                                       2: also beta-beta doubles, grouped by beta
                                       string; 0: each reference computes its own   */
+    int compact_refs;              /* hash records: 1 (default): when every
+                                      reference is within four excitations of the
+                                      first sorted one, the single pass rebuilds
+                                      parents from that one and up to eight flipped
+                                      spin-orbitals per reference (8 B each, kept
+                                      in the L2 cache) instead of a full bitstring
+                                      per reference; results are identical.  0:
+                                      always the full bitstrings                   */
 } pt2_options;
 
 typedef struct {

@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", C.c_void_p),
                 ("stream", C.c_void_p), ("timing", C.c_int), ("compress_keys", C.c_int),
                 ("exclusion", C.c_int), ("hash_bits", C.c_int), ("spin_flip", C.c_int),
-                ("string_reuse", C.c_int)]
+                ("string_reuse", C.c_int), ("compact_refs", C.c_int)]
 
 
 class Result(C.Structure):
@@ -172,7 +172,7 @@ class Context:
     def __init__(self, h, eri, norb, nalpha, nbeta, precision="fp64", cutoff=0.0,
                  log2_partitions=-1, device=0, n_streams=4, device_budget_bytes=0,
                  max_partition_bytes=0, timing=False, stream=None, allocator=None, compress_keys=-1,
-                 exclusion="search", hash_bits=0, spin_flip=False, string_reuse=1):
+                 exclusion="search", hash_bits=0, spin_flip=False, string_reuse=1, compact_refs=True):
         self.norb, self.nalpha, self.nbeta = int(norb), int(nalpha), int(nbeta)
         self.W = key_words(self.norb)
         o = default_options()
@@ -190,6 +190,7 @@ class Context:
         o.hash_bits = int(hash_bits)
         o.spin_flip = 1 if spin_flip else 0
         o.string_reuse = int(string_reuse)
+        o.compact_refs = 1 if compact_refs else 0
         if stream is not None:
             o.stream = int(getattr(stream, "cuda_stream", stream))
         self._alloc = None

@@ -176,6 +176,8 @@ struct Small {  // one device block for small control data
     Partial result;
     unsigned long long n_out;
     AnchorBlk anc;            // the anchor of the diagonals (one evaluation)
+    uint32_t ref_far;         // hash records: a reference is beyond the compact table's reach
+    uint32_t pad2;
 };
 
 struct Workspace {
@@ -187,6 +189,7 @@ struct Workspace {
     Buf refH0, refH1;        // hash records: reference hashes with indices (sort ping-pong)
     Buf hp, gv;              // hash records: E0 - energy and g vector of every reference (double-double)
     Buf refX;                // hash records: reference bitstrings record by record
+    Buf refE;                // hash records: references as flips relative to the first (compact)
     Buf recA, recB;          // record planes
     int64_t rec_cap = 0;
     int rec_W = 0, rec_pb = 0, rec_topb = 0;
@@ -209,7 +212,7 @@ struct Workspace {
     void release()
     {
         buf_free(A, dets), buf_free(A, coef), buf_free(A, refA), buf_free(A, refB), buf_free(A, refK);
-        buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv), buf_free(A, refX);
+        buf_free(A, tref), buf_free(A, refH0), buf_free(A, refH1), buf_free(A, hp), buf_free(A, gv), buf_free(A, refX), buf_free(A, refE);
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev), buf_free(A, agrp);
@@ -580,7 +583,8 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
     // the bucketed count takes only the listed subsets (with a cutoff or the
     // spin flip: their bucket walks with the filter); without bucketing, the
     // enumerating count takes every subset
-    const bool listed = P.target;
+    const bool listed = P.target && ((cutoff <= 0.0 && !sys.z2) ||
+                                     count_cut_ok(L, nref, P.log2p, (int)P.parts.size()));
     const size_t ncols = listed ? P.parts.size() : (size_t)Pn;
     if ((rc = buf_ensure(ws.A, ws.cnt, (size_t)P.nchunks * ncols * 4)))
         return rc;
@@ -845,6 +849,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     // hash records: the references' hashes sorted, with their indices, and
     // every reference's energy and g vector (H_aa is taken from the parent)
     Planes refs_hash{};
+    uint64_t anc_hash[MAXW] = {0, 0, 0, 0};
+    bool ref_compact = false;
     if (RL.hash) {
         if (J.n >= ((int64_t)1 << 32))
             return fail(PT2_E_INVALID, "hash records take fewer than 2^32 reference determinants");
@@ -857,6 +863,20 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
         HIPCHK(launch_parent_g(sys, refs, J.n, J.e0, (double *)ws.hp.p, (double *)ws.gv.p, st));
+        // the compact form of the same table, when every reference is within
+        // four excitations of the first
+        if ((rc = buf_ensure(ws.A, ws.refE, (size_t)std::max<int64_t>(J.n, 1) * 8)))
+            return rc;
+        Small *d0 = ws.dsmall();
+        HIPCHK(launch_zero_u32(&d0->ref_far, 1, st));
+        HIPCHK(launch_refs_ex(sys, refs, J.n, (uint64_t *)ws.refE.p, d0->anc.bits, &d0->ref_far, st));
+        HIPCHK(hipMemcpyAsync(ws.host_small->anc.bits, d0->anc.bits, sizeof(d0->anc.bits), hipMemcpyDeviceToHost,
+                              st));
+        HIPCHK(hipMemcpyAsync(&ws.host_small->ref_far, &d0->ref_far, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int w = 0; w < MAXW; w++)
+            anc_hash[w] = ws.host_small->anc.bits[w];
+        ref_compact = ws.host_small->ref_far == 0 && c->opt.compact_refs != 0;
     }
     // the anchor of the diagonals of bitstring and rank-key records: the first
     // sorted reference, its energy and g vector, and its hot pair rows (their
@@ -991,7 +1011,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if ((rc = buf_ensure(ws.A, ws.tref, (size_t)((n + RED_TILE - 1) / RED_TILE + 1) * 16)))
             return rc;
         if (RL.hash)
-            HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p, refs_hash, J.n,
+            HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p,
+                                      ref_compact ? (const uint64_t *)ws.refE.p : nullptr, anc_hash, refs_hash, J.n,
                                       (const double *)ws.hp.p, (const double *)ws.gv.p, J.e0, subtract ? 0 : 1,
                                       ds->partials, ds->coll, &ds->flags, st));
         else
@@ -1552,6 +1573,7 @@ PT2_API void pt2_default_options(pt2_options *o)
     o->device = 0;
     o->n_streams = 4;
     o->string_reuse = 1;
+    o->compact_refs = 1;
 }
 
 PT2_API int pt2_key_words(int norb) { return (2 * norb + 63) / 64; }

@@ -1089,6 +1089,15 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
 // bucket walk of k_gen_target for each listed subset, counting the walked
 // terms that are kept, so a call costs its own subsets' terms, not an
 // enumeration of every candidate.  cnt[j * nref + det] as k_count_target.
+// The walk needs generation's bucket lists, which occupy the region where the
+// bucketed count keeps its counts and subset map, so this kernel keeps them
+// in LDS of their own after the target layout (count_cut_lds_extra bytes):
+// the counts of the listed subsets, then the map from subset to list position.
+__host__ __device__ inline size_t count_cut_lds_extra(int log2p, int nparts)
+{
+    return align16((size_t)4 * nparts) + align16((size_t)2 << log2p);
+}
+
 template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcLayout L, const Planes refs,
                                                                   int64_t nref, int log2p, const uint32_t *parts,
@@ -1097,6 +1106,10 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
     Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    size_t o[8];
+    char *extra = lds + gen_lds_bytes_dev(L) + tgt_lds_layout(L, log2p, o);
+    uint32_t *ccount = (uint32_t *)extra;                                     // [nparts]
+    uint16_t *cmap = (uint16_t *)(extra + align16((size_t)4 * nparts));      // [B]
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, B = 1 << log2p;
     __shared__ uint32_t s_cnt[GEN_THREADS / 64];
@@ -1104,34 +1117,30 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
     const DivConsts D = div_consts(L);
     const uint64_t zp = g.head->z;
     for (int b = tid; b < B; b += GEN_THREADS)
-        t.pmap[b] = 0xFFFFu;
-    __syncthreads();
-    for (int j = tid; j < nparts; j += GEN_THREADS) {
-        t.plist[j] = (uint16_t)parts[j];
-        t.pmap[parts[j]] = (uint16_t)j;
-    }
-    __syncthreads();
-    // the singles of all listed subsets in one enumeration (a few per subset),
-    // counted by atomics into this determinant's output entries; then the
-    // doubles, subset by subset, by block sums
+        cmap[b] = 0xFFFFu;
     for (int j = tid; j < nparts; j += GEN_THREADS)
-        cnt[(int64_t)j * nref + det] = 0;
+        ccount[j] = 0;
     __syncthreads();
+    for (int j = tid; j < nparts; j += GEN_THREADS)
+        cmap[parts[j]] = (uint16_t)j;
+    __syncthreads();
+    // the singles of all listed subsets in one enumeration (a few per subset)
     for (int64_t k = tid; k < L.o2; k += GEN_THREADS) {
         const Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        const uint32_t j = t.pmap[top_bits(z, log2p)];
+        const uint32_t j = cmap[top_bits(z, log2p)];
         if (j != 0xFFFFu && keep_term<W, PM>(g, s, L, e, cutoff, key))
-            atomicAdd(&cnt[(int64_t)j * nref + det], 1u);
+            atomicAdd(&ccount[j], 1u);
     }
+    // the doubles, subset by subset, by block sums
     for (int kind = 2; kind <= 4; kind++) {
         const int no = n_outer(L, kind);
         if (no == 0 || n_inner(L, kind) == 0)
             continue;
         build_buckets(g, t, L, s.norb, kind, log2p, true);
         for (int j = 0; j < nparts; j++) {
-            const uint32_t part = t.plist[j];
+            const uint32_t part = parts[j];
             for (int o = tid; o < no; o += GEN_THREADS) {
                 const uint32_t b = part ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p);
                 t.tgt[o] = (uint16_t)b;
@@ -1158,8 +1167,8 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
                 kept += keep_term<W, PM>(g, s, L, e, cutoff, key) ? 1u : 0u;
             }
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1)
-                kept += __shfl_xor(kept, o);
+            for (int sh = 32; sh >= 1; sh >>= 1)
+                kept += __shfl_xor(kept, sh);
             if (lane == 0)
                 s_cnt[wave] = kept;
             __syncthreads();
@@ -1167,12 +1176,15 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
                 uint32_t x = 0;
                 for (int w = 0; w < GEN_THREADS / 64; w++)
                     x += s_cnt[w];
-                cnt[(int64_t)j * nref + det] += x;
+                ccount[j] += x;
             }
-            // t.pre and t.tgt are rebuilt for the next subset
+            // t.pre, t.tgt and s_cnt are rewritten for the next subset
             __syncthreads();
         }
     }
+    __syncthreads();
+    for (int j = tid; j < nparts; j += GEN_THREADS)
+        cnt[(int64_t)j * nref + det] = ccount[j];
 }
 
 // Rank keys of the sorted bitstring references, same order, with their
@@ -1265,6 +1277,11 @@ size_t target_lds_bytes(const ExcLayout &L, int log2p)
 bool spin_reuse_ok(const ExcLayout &L, int W)
 {
     return gen_lds_bytes(L) + (size_t)REUSE_GROUP * (W * 8 + 16) <= 65536;
+}
+
+bool count_cut_ok(const ExcLayout &L, int64_t nref, int log2p, int nparts)
+{
+    return target_ok(L, nref, log2p) && target_lds_bytes(L, log2p) + count_cut_lds_extra(log2p, nparts) <= 65536;
 }
 
 bool target_ok(const ExcLayout &L, int64_t nref, int log2p)
@@ -1365,7 +1382,9 @@ hipError_t count_target_cut_t(const DevSys &s, const ExcLayout &L, const Planes 
 {
     if (nref == 0 || nparts == 0)
         return hipSuccess;
-    const size_t lds = target_lds_bytes(L, log2p);
+    if (!count_cut_ok(L, nref, log2p, nparts))
+        return hipErrorInvalidValue;
+    const size_t lds = target_lds_bytes(L, log2p) + count_cut_lds_extra(log2p, nparts);
     hipLaunchKernelGGL((k_count_target_cut<W, PM>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs,
                        nref, log2p, parts, nparts, cutoff, cnt);
     return hipGetLastError();

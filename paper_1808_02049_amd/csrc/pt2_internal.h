@@ -396,6 +396,9 @@ hipError_t launch_count(const DevSys &s, const ExcLayout &L, int pm, const Plane
 // reference determinant per chunk (chunk = nper, nchunks = nref): the count
 // needs cutoff 0; generation walks only the terms of the subset.
 bool target_ok(const ExcLayout &L, int64_t nref, int log2p);
+// launch_count_target_cut fits (its subset counts and map need LDS beyond
+// the target layout)
+bool count_cut_ok(const ExcLayout &L, int64_t nref, int log2p, int nparts);
 size_t target_lds_bytes(const ExcLayout &L, int log2p);
 // Counts of the listed subsets only: cnt[j * nref + det] for parts[j] (device
 // list of nparts distinct subsets).
@@ -478,8 +481,15 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
 hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ra, hipStream_t st);
 // pm: the payload mode (PM_*), which sets the FP32 rounding bound.
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
+                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
+                              const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
                               int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st);
+// The references' flips relative to the first sorted reference (up to eight,
+// one byte each, 0xFF unused) into ex (n words), that reference's words into
+// anc_bits (MAXW words), and *far = 1 (set, never cleared) if some reference
+// differs from it in more than eight spin-orbitals.
+hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint64_t *anc_bits,
+                          uint32_t *far, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
 // Inspection: unique keys and numerators (n_out on device).

@@ -1032,10 +1032,38 @@ __global__ void k_refs_aos(Planes bits, int64_t n, uint64_t *ra)
             ra[i * ref_stride<WB>() + w] = w < WB ? pl_get<WB>(bits, w, i) : 0ull;
 }
 
+// Where a single pass finds a parent's bitstring: the record-by-record table
+// above, or, when every reference is within four excitations of the anchor A
+// (the first sorted reference), the anchor's bitstring with up to eight
+// flipped spin-orbitals per reference (one byte each, 0xFF unused): 8 B per
+// reference instead of 32, a table that stays in the L2 cache while records
+// stream past it.
+struct RefTab {
+    const uint64_t *full;  // ref_stride words per reference
+    const uint64_t *ex;    // flips relative to the anchor, or null
+    uint64_t a[MAXW];      // the anchor's bitstring
+};
+
 template <int WB>
-__device__ inline void ref_bits(const uint64_t *ra, int64_t p, uint64_t (&k)[WB])
+__device__ inline void ref_bits(const RefTab &t, int64_t p, uint64_t (&k)[WB])
 {
-    const uint64_t *r = ra + p * ref_stride<WB>();
+    if (t.ex) {
+        const uint64_t e = t.ex[p];
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            k[w] = t.a[w];
+#pragma unroll
+        for (int f = 0; f < 8; f++) {
+            const uint32_t b = (uint32_t)(e >> (8 * f)) & 0xFFu;
+            if (b != FLIP_NONE) {
+#pragma unroll
+                for (int w = 0; w < WB; w++)
+                    k[w] ^= (w == (int)(b >> 6)) ? (1ull << (b & 63)) : 0ull;
+            }
+        }
+        return;
+    }
+    const uint64_t *r = t.full + p * ref_stride<WB>();
     if constexpr (WB == 2 || WB == 4) {
         const ulonglong2 *r2 = (const ulonglong2 *)r;
 #pragma unroll
@@ -1050,9 +1078,42 @@ __device__ inline void ref_bits(const uint64_t *ra, int64_t p, uint64_t (&k)[WB]
     }
 }
 
+// The compact table: every reference's flips relative to the anchor (the
+// first of the sorted bitstrings); *far gets 1 if some reference differs
+// from the anchor in more than eight spin-orbitals; the anchor's words go to
+// anc_bits.
+template <int WB>
+__global__ void k_refs_ex(Planes bits, int64_t n, uint64_t *ex, uint64_t *anc_bits, uint32_t *far)
+{
+    uint64_t a[WB];
+#pragma unroll
+    for (int w = 0; w < WB; w++)
+        a[w] = pl_get<WB>(bits, w, 0);
+    if (blockIdx.x == 0 && threadIdx.x < MAXW)
+        anc_bits[threadIdx.x] = threadIdx.x < WB ? a[threadIdx.x] : 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t e = ~0ull;
+        int nf = 0;
+#pragma unroll
+        for (int w = 0; w < WB; w++) {
+            uint64_t d = pl_get<WB>(bits, w, i) ^ a[w];
+            while (d) {
+                const int b = w * 64 + __builtin_ctzll(d);
+                d &= d - 1;
+                if (nf < 8)
+                    e = (e & ~(0xFFull << (8 * nf))) | ((uint64_t)b << (8 * nf));
+                nf++;
+            }
+        }
+        if (nf > 8)
+            atomicOr(far, 1u);
+        ex[i] = e;
+    }
+}
+
 // Bitstring of a hash record: its parent's bitstring with the flips applied.
 template <int WB>
-__device__ inline void hash_key(const uint64_t *ra, uint64_t aux, uint64_t (&k)[WB])
+__device__ inline void hash_key(const RefTab &ra, uint64_t aux, uint64_t (&k)[WB])
 {
     const int64_t p = (int64_t)(aux >> 32);
     ref_bits<WB>(ra, p, k);
@@ -1072,7 +1133,7 @@ __device__ inline void hash_key(const uint64_t *ra, uint64_t aux, uint64_t (&k)[
 //   D0[p] + sum_R g_r - sum_A g_a - sum_{r<r'} T - sum_{a<a'} T + sum_{a,r} T.
 template <int WB>
 __device__ inline double den_parent(const double *Tp, const double *Tl, int nso, const uint64_t (&k)[WB],
-                                    const uint64_t *ra, int64_t p, const double *G, const double *D0)
+                                    const RefTab &ra, int64_t p, const double *G, const double *D0)
 {
     int rm[2], ad[2], nr = 0, na = 0;
     uint64_t pk[WB];
@@ -1160,7 +1221,7 @@ __device__ inline int spin_phase(const uint64_t (&k)[WB], int norb, int sp, int 
 //   same-spin r<q->a<b: ph(r->a) ph(q->b after r->a) [(ra|qb) - (rb|qa)]
 //   alpha r->a, beta q->b: ph_alpha ph_beta (ra|qb)
 template <int WB>
-__device__ inline double rec_value64(const DevSys &s, const uint64_t *ra, const double *coef, uint64_t aux)
+__device__ inline double rec_value64(const DevSys &s, const RefTab &ra, const double *coef, uint64_t aux)
 {
     const int64_t p = (int64_t)(aux >> 32);
     uint64_t pk[WB];
@@ -1214,7 +1275,7 @@ constexpr double REFINE_RATIO = 1e-3;
 constexpr double REFINE_TOL = 1e-11;
 
 template <int WB>
-__device__ inline double refine_num(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+__device__ inline double refine_num(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
                                     uint64_t h, int64_t tail, double num, double den, double eps)
 {
     int64_t head = tail;
@@ -1235,7 +1296,7 @@ __device__ inline double refine_num(const DevSys &s, const Planes &in, const Pla
 // tail: index of the segment's last record (FP32 refinement); refine < 0: the
 // numerator is already FP64.
 template <int WB, int PB>
-__device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+__device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
                                      const Planes &rh, int64_t lo, int64_t hi, const uint64_t *s_rh, const int64_t *s_ri,
                                      bool staged, uint64_t h, const uint64_t (&k)[WB], int64_t parent, int64_t tail,
                                      double num, const double *D0, const double *G, Acc &a, bool search, double eps)
@@ -1350,7 +1411,7 @@ __device__ inline bool bits_eq(const uint64_t (&x)[WB], const uint64_t (&y)[WB])
 
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in, int64_t n, Planes bits,
-                                                             const uint64_t *ra, Planes rh,
+                                                             RefTab ra, Planes rh,
                                                              int64_t nref, const double *D0, const double *G,
                                                              int64_t tiles_per_block, int search, double eps,
                                                              Partial *partials, CollList *coll, Flags *flags)
@@ -1659,7 +1720,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
 // each distinct determinant, taken at its first record, gets the sum of its
 // records' payloads (with FP32 payloads, of their FP64 values) and its term.
 template <int WB, int PB>
-__device__ inline void coll_segment(const DevSys &s, const Planes &in, const Planes &bits, const uint64_t *ra,
+__device__ inline void coll_segment(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
                                     const Planes &rh, int64_t nref, const double *D0, const double *G, int64_t i,
                                     int64_t e, Acc &a, bool search)
 {
@@ -1697,7 +1758,7 @@ __device__ inline void coll_segment(const DevSys &s, const Planes &in, const Pla
 // once.
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
-                                                                  const uint64_t *ra, Planes rh, int64_t nref, const double *D0,
+                                                                  RefTab ra, Planes rh, int64_t nref, const double *D0,
                                                                   const double *G,
                                                                   int64_t tiles_per_block, int search, Partial *partials,
                                                                   const CollList *coll, Flags *flags)
@@ -2070,10 +2131,33 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
     return hipGetLastError();
 }
 
+hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint64_t *anc_bits,
+                          uint32_t *far, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t gg = (n + 255) / 256;
+    dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
+    switch (s.W) {
+    case 1: hipLaunchKernelGGL((k_refs_ex<1>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
+    case 2: hipLaunchKernelGGL((k_refs_ex<2>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
+    case 3: hipLaunchKernelGGL((k_refs_ex<3>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
+    case 4: hipLaunchKernelGGL((k_refs_ex<4>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra, const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
+                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
+                              const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
                               int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st)
 {
+    RefTab ra;
+    ra.full = ra_full;
+    ra.ex = ra_ex;
+    for (int w = 0; w < MAXW; w++)
+        ra.a[w] = ra_ex ? anc_bits[w] : 0ull;
     (void)e0;  // carried by D0
     // relative rounding of a stored FP32 payload: once (FP64 arithmetic), or
     // FP32 integrals and arithmetic (a looser bound)

@@ -322,6 +322,25 @@ def test_rank_keys_give_identical_results(pt2, norb, na, nb, nref, log2p, prec):
         assert_matches(res[1], ref, tol=1e-6, cross_tol=1e-7)
 
 
+@pytest.mark.parametrize("log2p", [-1, 3])
+def test_hash_compact_reference_table_is_exact(pt2, log2p):
+    """Hash records rebuild each parent from the first sorted reference and
+    its flips (every reference of C2 is within three excitations of it) or
+    from its full bitstring: the same records, so every result field is
+    bit-identical either way."""
+    w, h, eri, dets, c, e0 = load("c2")
+    dets, c = dets[:400], c[:400]
+    res = []
+    for compact in (True, False):
+        ctx = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, compress_keys=2, log2_partitions=log2p,
+                          compact_refs=compact)
+        res.append(ctx.evaluate(dets, c, e0))
+        ctx.close()
+    for k in ("e_pt2", "n_contrib", "n_unique", "n_external", "n_in_ref_hit", "n_nonneg_denom", "min_abs_denom",
+              "ref_cross", "key_xor", "key_sum"):
+        assert res[0][k] == res[1][k], (k, res[0][k], res[1][k])
+
+
 @pytest.mark.parametrize("norb,na,nb,nref,log2p,prec,hash_bits", [
     (12, 4, 4, 40, -1, "fp64", 0), (12, 4, 4, 40, -1, "fp64", 10), (20, 6, 3, 60, 3, "fp64", 0),
     (20, 6, 3, 60, 2, "fp64", 12), (33, 3, 2, 25, -1, "fp32", 0), (40, 10, 10, 30, -1, "fp64", 16),
