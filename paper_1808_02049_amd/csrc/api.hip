@@ -401,8 +401,11 @@ void carve_slice(Workspace &ws, char *p, int W, int pb, int topb, int64_t cap)
 
 // Stable LSD sort of n records held in *src (ping-pong with *dst) on key bits
 // [0, nbits).  On return *src holds the sorted records.
+// digits: when nonzero, the bit mask of the digit positions to sort (the
+// others are known to hold one value): no all-digit histogram pass, and each
+// pass takes its bucket starts from its own tile counts.
 int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n, int nbits, hipStream_t st,
-               Timing &tm, uint32_t *passes_out, double *bytes_out, int items = SORT_ITEMS)
+               Timing &tm, uint32_t *passes_out, double *bytes_out, int items = SORT_ITEMS, uint32_t digits = 0)
 {
     if (n <= 1)
         return PT2_OK;
@@ -413,31 +416,38 @@ int radix_sort(Workspace &ws, int W, int pb, Planes &src, Planes &dst, int64_t n
     if (rc)
         return rc;
     Small *ds = ws.dsmall();
-    hipEvent_t a;
-    if ((rc = timed_begin(ws, tm, st, a)))
-        return rc;
-    HIPCHK(launch_zero_u64(ds->hist, ndig * 256, st));
-    HIPCHK(launch_zero_u32(ds->tile_ctr, MAX_PASS_CTR, st));
-    HIPCHK(launch_hist(W, src, n, ndig, ds->hist, st));
-    HIPCHK(launch_hist_scan(ds->hist, ndig, ds->bucket, st));
-    HIPCHK(hipMemcpyAsync(ws.host_small->hist, ds->hist, sizeof(uint64_t) * ndig * 256, hipMemcpyDeviceToHost, st));
-    if ((rc = timed_end(ws, tm, st, a, 3)))
-        return rc;
-    HIPCHK(hipStreamSynchronize(st));
+    if (!digits) {
+        hipEvent_t a;
+        if ((rc = timed_begin(ws, tm, st, a)))
+            return rc;
+        HIPCHK(launch_zero_u64(ds->hist, ndig * 256, st));
+        HIPCHK(launch_hist(W, src, n, ndig, ds->hist, st));
+        HIPCHK(launch_hist_scan(ds->hist, ndig, ds->bucket, st));
+        HIPCHK(hipMemcpyAsync(ws.host_small->hist, ds->hist, sizeof(uint64_t) * ndig * 256, hipMemcpyDeviceToHost,
+                              st));
+        if ((rc = timed_end(ws, tm, st, a, 3)))
+            return rc;
+        HIPCHK(hipStreamSynchronize(st));
+    }
     for (int d = 0; d < ndig; d++) {
-        const uint64_t *h = ws.host_small->hist + d * 256;
-        bool trivial = false;
-        for (int v = 0; v < 256; v++)
-            if (h[v] == (uint64_t)n)
-                trivial = true;
-        if (trivial)
-            continue;
+        if (digits) {
+            if (!((digits >> d) & 1u))
+                continue;
+        } else {
+            const uint64_t *h = ws.host_small->hist + d * 256;
+            bool trivial = false;
+            for (int v = 0; v < 256; v++)
+                if (h[v] == (uint64_t)n)
+                    trivial = true;
+            if (trivial)
+                continue;
+        }
         hipEvent_t pa, mid = nullptr;
         if ((rc = timed_begin(ws, tm, st, pa)))
             return rc;
         if (tm.on && !(mid = ws.event()))
             return fail(PT2_E_DEVICE, "hipEventCreate failed");
-        HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, ds->bucket + d * 256, (uint16_t *)ws.counts.p,
+        HIPCHK(launch_radix_pass(W, pb, src, dst, n, d, digits ? nullptr : ds->bucket + d * 256, (uint16_t *)ws.counts.p,
                                  (uint64_t *)ws.csum.p, (uint64_t *)ws.coff.p, (uint32_t *)ws.offs.p, &ds->flags,
                                  st, mid, items));
         if (tm.on) {
@@ -849,6 +859,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     // hash records: the references' hashes sorted, with their indices, and
     // every reference's energy and g vector (H_aa is taken from the parent)
     Planes refs_hash{};
+    uint32_t hash_digits = 0;  // digit positions a hash-record sort must take (0: from histograms)
     uint64_t anc_hash[MAXW] = {0, 0, 0, 0};
     bool ref_compact = false;
     if (RL.hash) {
@@ -941,6 +952,13 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             b = c->opt.hash_bits >= 64 ? 64 : c->opt.hash_bits;
         }
         key_bits = (uint32_t)b;
+        if (c->opt.hash_bits == 0) {
+            // the digits that can vary: bytes holding kept bits below the
+            // subset's fixed top log2p bits (the others hold one value)
+            for (int d = 0; d < 8; d++)
+                if (8 * d + 8 > 64 - b && 8 * d < 64 - P.log2p)
+                    hash_digits |= 1u << d;
+        }
         // the references' hashes (same bits), sorted, with their indices
         Planes h0 = planes_of(ws.refH0, 1, J.n, 8, 8), h1 = planes_of(ws.refH1, 1, J.n, 8, 8);
         HIPCHK(launch_refs_hash(sys, refs, J.n, h0, st));
@@ -998,7 +1016,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         if (J.dump == 1)
             break;  // generation order: the records are in recA
         if ((rc = radix_sort(ws, W, pb, A, B, n, RL.bits, st, tm, &res.n_sort_passes, &res.bytes_sort,
-                             RL.hash ? SORT_ITEMS_WIDE : SORT_ITEMS)))
+                             RL.hash ? SORT_ITEMS_WIDE : SORT_ITEMS, hash_digits)))
             return rc;
         if (J.dump == 2 || J.dump == 3) {
             // hand the sorted planes to the inspection copy below (it reads recA)

@@ -230,11 +230,25 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const uint16_t *counts, int64
 }
 
 // Step 2b: exclusive scan of the chunk sums per digit, starting at the
-// digit's bucket start.
+// digit's bucket start: from the all-digit histograms, or, when bucket is
+// null, the exclusive scan over digit values of this digit's totals.
 __global__ __launch_bounds__(256) void k_chunk_scan(const uint64_t *csum, int64_t nchunks, const uint64_t *bucket,
                                                     uint64_t *coff)
 {
-    uint64_t run = bucket[threadIdx.x];
+    uint64_t run;
+    if (bucket) {
+        run = bucket[threadIdx.x];
+    } else {
+        __shared__ uint64_t s_tot[256];
+        uint64_t t = 0;
+        for (int64_t c = 0; c < nchunks; c++)
+            t += csum[c * 256 + threadIdx.x];
+        s_tot[threadIdx.x] = t;
+        __syncthreads();
+        run = 0;
+        for (int v = 0; v < (int)threadIdx.x; v++)
+            run += s_tot[v];
+    }
     int64_t c = 0;
     for (; c + 8 <= nchunks; c += 8) {
         uint64_t x[8];
