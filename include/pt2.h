@@ -139,7 +139,7 @@ typedef struct {
                                       which the expected number of colliding pairs
                                       among the largest subset's N records,
                                       N^2 / 2^(bits - log2p + 1) with 2^log2p
-                                      subsets, is 16384 or fewer (collided runs are
+                                      subsets, is N/512 or fewer (collided runs are
                                       resolved exactly).  1-64: exactly that many
                                       low bits (few bits make collisions common, to
                                       test their handling)                          */

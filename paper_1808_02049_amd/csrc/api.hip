@@ -924,13 +924,16 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     if (RL.hash) {
         // sort on the top b bits of the hash, the fewest digit passes for
         // which the expected number of colliding pairs among the largest
-        // subset's N records, N^2 / 2^(b - log2p + 1), stays at 16384 or fewer
-        // (the subset fixes the top log2p bits; collided runs are resolved
-        // exactly, each by a revisit of its own records, about 4 per
-        // single-pass workgroup at that bound); among choices with equal
-        // passes, the most bits.  A byte of the hash with no kept, varying
-        // bit is a digit with one value, which the sort skips: with 512
-        // subsets, 56 bits take 6 passes.
+        // subset's N records, N^2 / 2^(b - log2p + 1), stays at N/512 or
+        // fewer (the subset fixes the top log2p bits; N bounds the number of
+        // distinct determinants).  Collided runs are resolved exactly, each by
+        // a revisit of its own records: at the bound, with every record a
+        // distinct determinant, the revisits would cost about as much as the
+        // 24-byte digit pass the bits save; with several records per
+        // determinant, as generation gives, far less.  Among choices with
+        // equal passes, the most bits.  A byte of the hash with no kept,
+        // varying bit is a digit with one value, which the sort skips: with
+        // 512 subsets of 1.9e9 records, 48 bits take 5 passes.
         int b = 64;
         if (c->opt.hash_bits == 0) {
             auto passes = [&](int bits) {
@@ -941,7 +944,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             };
             int best = 64;
             for (int bits = 64; bits >= 32; bits -= 8) {
-                if ((double)mx * (double)mx / std::ldexp(1.0, bits - P.log2p + 1) > 16384.0)
+                if ((double)mx * (double)mx / std::ldexp(1.0, bits - P.log2p + 1) > (double)mx / 512.0)
                     break;
                 if (passes(bits) < passes(best))
                     best = bits;
@@ -1032,7 +1035,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p,
                                       ref_compact ? (const uint64_t *)ws.refE.p : nullptr, anc_hash, refs_hash, J.n,
                                       (const double *)ws.hp.p, (const double *)ws.gv.p, J.e0, subtract ? 0 : 1,
-                                      ds->partials, ds->coll, &ds->flags, st));
+                                      ds->partials, ds->coll, (int64_t *)B.key[0], &ds->flags, st));
         else
             HIPCHK(launch_reduce(sys, fp32, W, A, n, refs_red, J.n, J.e0, &ds->anc, anc_nh, (int64_t *)ws.tref.p,
                                  subtract ? 0 : 1, ds->partials, &ds->flags, st));

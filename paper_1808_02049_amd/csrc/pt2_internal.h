@@ -223,13 +223,13 @@ __device__ inline void pl_put(const Planes &p, int w, int64_t i, uint64_t v)
 }
 
 // Hash records: the collided segments (runs of one hash holding more than one
-// determinant) a single-pass workgroup found, by the index of their last
-// record, ascending; n > COLL_LIST means the list overflowed and the
-// workgroup's whole record range is revisited.
-constexpr int COLL_LIST = 32;
+// determinant) a single-pass workgroup found.  Their last records' indices are
+// listed in record order in the workgroup's region of a list buffer (from
+// index first_tile * RED_TILE; it never holds more entries than records).
 struct CollList {
-    uint32_t n, pad;
-    int64_t tail[COLL_LIST];
+    uint32_t n, pad;  // collided segments listed (their last records' indices, in record order,
+                      // in the workgroup's region of the list buffer)
+    int64_t lo, hi;   // the references whose hash lies in the workgroup's hash range
 };
 
 // Per-block partial of the single pass; summed in block order.
@@ -483,7 +483,8 @@ hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint6
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
                               const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
                               const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
-                              int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st);
+                              int search, Partial *partials, CollList *coll, int64_t *ctail, Flags *flags,
+                              hipStream_t st);
 // The references' flips relative to the first sorted reference (up to eight,
 // one byte each, 0xFF unused) into ex (n words), that reference's words into
 // anc_bits (MAXW words), and *far = 1 (set, never cleared) if some reference

@@ -1414,7 +1414,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                                                              RefTab ra, Planes rh,
                                                              int64_t nref, const double *D0, const double *G,
                                                              int64_t tiles_per_block, int search, double eps,
-                                                             Partial *partials, CollList *coll, Flags *flags)
+                                                             Partial *partials, CollList *coll, int64_t *ctail,
+                                                             Flags *flags)
 {
     // queue of owned segment ends (hash, parent word, sum, collided, index of
     // the last record relative to the tile); the block's partials reuse it at
@@ -1435,16 +1436,16 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     __shared__ HashScan s_cont;
     __shared__ uint64_t s_ch;
     __shared__ int s_cflag;
-    __shared__ uint32_t s_ncoll;
-    __shared__ int64_t s_coll_t[COLL_LIST];
+    __shared__ int s_tcoll;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
     const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
     const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
     Acc a;
     acc_init(a);
-    if (tid == 0)
-        s_ncoll = 0;
+    // the workgroup's collided segments, listed by wave 0 in record order
+    int64_t *my_tail = ctail + t_begin * RED_TILE;
+    uint32_t ncoll = 0;
     // references whose hash lies in the workgroup's hash range, staged in LDS
     // when few
     int64_t lo = 0, hi = 0;
@@ -1485,7 +1486,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
         const int64_t base = tile * RED_TILE;
         const int64_t tend = base + RED_TILE < n ? base + RED_TILE : n;
         if (tid == 0)
-            s_cflag = 0;
+            s_cflag = 0, s_tcoll = 0;
         const int64_t r0 = base + (int64_t)tid * RED_ITEMS;
         uint64_t h[RED_ITEMS], ax[RED_ITEMS], kb[RED_ITEMS][WB];
         double p[RED_ITEMS];
@@ -1631,6 +1632,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 q_a[slot] = hh[j] ? rha[j] : carry.a;
                 q_c[slot] = hh[j] ? rc[j] : (carry.c | rc[j]);
                 q_t[slot] = (uint32_t)(idx - base);
+                if (q_c[slot])
+                    s_tcoll = 1;
                 slot++;
             }
         }
@@ -1675,17 +1678,28 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 // with the segment's first record
                 q_c[qtot] = s_cont.c | col;
                 q_t[qtot] = (uint32_t)(pos - 1 - base);
+                if (q_c[qtot])
+                    s_tcoll = 1;
             }
         }
         __syncthreads();
         const int qn = (int)qtot + cflag;
-        for (int e = tid; e < qn; e += RED_THREADS) {
-            if (q_c[e]) {
-                const uint32_t i = atomicAdd(&s_ncoll, 1u);
-                if (i < COLL_LIST)
-                    s_coll_t[i] = base + (int64_t)q_t[e];
-                continue;
+        if (s_tcoll && wave == 0) {
+            // collided segments are left to k_reduce_hash_coll: wave 0 lists
+            // them in queue (record) order
+            const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+            for (int e0 = 0; e0 < qn; e0 += 64) {
+                const int e = e0 + lane;
+                const bool c = e < qn && q_c[e] != 0;
+                const uint64_t m = __ballot(c);
+                if (c)
+                    my_tail[ncoll + (uint32_t)__popcll(m & lt)] = base + (int64_t)q_t[e];
+                ncoll += (uint32_t)__popcll(m);
             }
+        }
+        for (int e = tid; e < qn; e += RED_THREADS) {
+            if (q_c[e])
+                continue;
             uint64_t k0[WB];
             const uint64_t aux = q_a[e];
             hash_key<WB>(ra, aux, k0);
@@ -1701,28 +1715,24 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     block_partial(s_p);
     if (tid == 0) {
         partials[blockIdx.x] = s_p[0];
-        // the collided segments in ascending order, so that the revisit sums
-        // them in an order independent of the threads' timing
-        const uint32_t nc = s_ncoll, m = nc < COLL_LIST ? nc : COLL_LIST;
-        for (uint32_t i = 1; i < m; i++)
-            for (uint32_t j = i; j > 0 && s_coll_t[j - 1] > s_coll_t[j]; j--) {
-                const int64_t t = s_coll_t[j];
-                s_coll_t[j] = s_coll_t[j - 1];
-                s_coll_t[j - 1] = t;
-            }
-        coll[blockIdx.x].n = nc;
-        for (uint32_t i = 0; i < m; i++)
-            coll[blockIdx.x].tail[i] = s_coll_t[i];
+        CollList cl;
+        cl.n = ncoll;  // wave 0's count (lane 0 holds it)
+        cl.pad = 0;
+        // (from LDS: holding lo and hi in registers to here costs occupancy)
+        cl.lo = t_begin < t_end ? s_lo : 0;
+        cl.hi = t_begin < t_end ? s_hi : 0;
+        coll[blockIdx.x] = cl;
     }
 }
 
 // Records [i, e) are one collided segment (one hash, several determinants):
 // each distinct determinant, taken at its first record, gets the sum of its
 // records' payloads (with FP32 payloads, of their FP64 values) and its term.
+// One thread; references searched over [lo, hi).
 template <int WB, int PB>
 __device__ inline void coll_segment(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
-                                    const Planes &rh, int64_t nref, const double *D0, const double *G, int64_t i,
-                                    int64_t e, Acc &a, bool search)
+                                    const Planes &rh, int64_t lo, int64_t hi, const double *D0, const double *G,
+                                    int64_t i, int64_t e, Acc &a, bool search)
 {
     const uint64_t h = in.key[0][i];
     for (int64_t x = i; x < e; x++) {
@@ -1745,70 +1755,151 @@ __device__ inline void coll_segment(const DevSys &s, const Planes &in, const Pla
             if (bits_eq<WB>(ky, kx))
                 nx += PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ay) : load_pay<PB>(in, y);
         }
-        // references searched in global memory over the whole list
-        hash_key_term<WB, PB>(s, in, bits, ra, rh, 0, nref, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), -1,
+        hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), -1,
                               nx, D0, G, a, search, 0.0);
     }
 }
 
-// The collided segments k_reduce_hash listed, per workgroup: one thread per
-// listed segment (in ascending order), or, when a workgroup's list
-// overflowed, its whole record range again.  The workgroup's partial is
-// merged into the one k_reduce_hash wrote.  Workgroups with none return at
-// once.
+// Distinct determinants one wavefront tracks in a collided segment.
+constexpr int COLL_DETS = 8;
+
+// One collided segment [i, e) split by one wavefront, 64 records at a time
+// (record c + lane): each lane rebuilds its record's bitstring and matches it
+// against the determinants met so far (kept in LDS, in order of first
+// appearance; a record matching none opens the next); each lane keeps one sum
+// per determinant over its records.  At the end the sums are reduced over the
+// wavefront and lane 0 adds each determinant's term.  A segment with more
+// than COLL_DETS determinants (only with hashes truncated far below 64 bits)
+// is split by lane 0 alone.
+template <int WB, int PB>
+__device__ inline void coll_segment_wave(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
+                                         const Planes &rh, int64_t lo, int64_t hi, const double *D0,
+                                         const double *G, int64_t i, int64_t e, uint64_t *s_dk, uint64_t *s_dax,
+                                         Acc &a, bool search)
+{
+    const int lane = threadIdx.x & 63;
+    double dv[COLL_DETS];
+#pragma unroll
+    for (int d = 0; d < COLL_DETS; d++)
+        dv[d] = 0.0;
+    int nd = 0;
+    bool over = false;
+    for (int64_t c0 = i; c0 < e && !over; c0 += 64) {
+        const int64_t x = c0 + lane;
+        const bool valid = x < e;
+        uint64_t k[WB], ax = 0ull;
+        double v = 0.0;
+        if (valid) {
+            ax = in.key[1][x];
+            hash_key<WB>(ra, ax, k);
+            v = PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ax) : load_pay<PB>(in, x);
+        } else {
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                k[w] = 0ull;
+        }
+        int my = -1;
+        for (int d = 0; d < nd; d++) {
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                eq = eq && s_dk[d * WB + w] == k[w];
+            my = (my < 0 && eq) ? d : my;
+        }
+        uint64_t un = __ballot(valid && my < 0);
+        while (un) {
+            if (nd == COLL_DETS) {
+                over = true;
+                break;
+            }
+            const int l = __builtin_ctzll(un);
+            uint64_t kx[WB];
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                kx[w] = __shfl(k[w], l);
+            const uint64_t axl = __shfl(ax, l);
+            if (lane == 0) {
+#pragma unroll
+                for (int w = 0; w < WB; w++)
+                    s_dk[nd * WB + w] = kx[w];
+                s_dax[nd] = axl;
+            }
+            if (valid && my < 0 && bits_eq<WB>(k, kx))
+                my = nd;
+            nd++;
+            un = __ballot(valid && my < 0);
+        }
+        // lane 0's LDS writes stay ahead of the other lanes' later reads
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int d = 0; d < COLL_DETS; d++)
+            dv[d] += my == d ? v : 0.0;
+    }
+    if (over) {
+        if (lane == 0)
+            coll_segment<WB, PB>(s, in, bits, ra, rh, lo, hi, D0, G, i, e, a, search);
+        return;
+    }
+    const uint64_t h = in.key[0][i];
+#pragma unroll
+    for (int d = 0; d < COLL_DETS; d++) {
+        if (d >= nd)
+            break;
+        double nx = dv[d];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            nx += __shfl_down(nx, o);
+        if (lane == 0) {
+            uint64_t kx[WB];
+#pragma unroll
+            for (int w = 0; w < WB; w++)
+                kx[w] = s_dk[d * WB + w];
+            hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, nullptr, nullptr, false, h, kx,
+                                  (int64_t)(s_dax[d] >> 32), -1, nx, D0, G, a, search, 0.0);
+        }
+    }
+}
+
+// The collided segments k_reduce_hash listed, per workgroup, in record
+// order: entry e on wavefront e mod 4 (so the sums are reproducible), each
+// walked back to its first record and split by determinant.  The
+// workgroup's partial is merged into the one k_reduce_hash wrote.
+// Workgroups with none return at once.
 template <int WB, int PB>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Planes in, int64_t n, Planes bits,
-                                                                  RefTab ra, Planes rh, int64_t nref, const double *D0,
-                                                                  const double *G,
-                                                                  int64_t tiles_per_block, int search, Partial *partials,
-                                                                  const CollList *coll, Flags *flags)
+                                                                  RefTab ra, Planes rh, const double *D0,
+                                                                  const double *G, int64_t tiles_per_block,
+                                                                  int search, Partial *partials,
+                                                                  const CollList *coll, const int64_t *ctail,
+                                                                  Flags *flags)
 {
     __shared__ Partial s_p[RED_THREADS];
-    const uint32_t ncoll = coll[blockIdx.x].n;
-    if (ncoll == 0)
+    __shared__ uint64_t s_dk[RED_THREADS / 64][COLL_DETS * WB];
+    __shared__ uint64_t s_dax[RED_THREADS / 64][COLL_DETS];
+    const CollList cl = coll[blockIdx.x];
+    if (cl.n == 0)
         return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t *my_tail = ctail + (int64_t)blockIdx.x * tiles_per_block * RED_TILE;
     Acc a;
     acc_init(a);
-    if (ncoll <= COLL_LIST) {
-        if (tid < (int)ncoll) {
-            const int64_t t = coll[blockIdx.x].tail[tid];
-            const uint64_t h = in.key[0][t];
-            int64_t b = t;
-            while (b > 0 && in.key[0][b - 1] == h)
-                b--;
-            coll_segment<WB, PB>(s, in, bits, ra, rh, nref, D0, G, b, t + 1, a, search != 0);
-        }
-    } else {
-        const int64_t ntiles = (n + RED_TILE - 1) / RED_TILE;
-        const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
-        const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
-        const int64_t b0 = t_begin * RED_TILE;
-        const int64_t b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
-        for (int64_t t0 = b0; t0 < b1; t0 += RED_TILE) {
-            const int64_t i0 = t0 + (int64_t)tid * RED_ITEMS;
-            for (int j = 0; j < RED_ITEMS; j++) {
-                const int64_t i = i0 + j;
-                if (i >= b1)
-                    break;
-                const uint64_t h = in.key[0][i];
-                if (i > 0 && in.key[0][i - 1] == h)
-                    continue;  // not a segment head
-                int64_t e = i;
-                while (e < n && in.key[0][e] == h)
-                    e++;
-                uint64_t k0[WB];
-                hash_key<WB>(ra, in.key[1][i], k0);
-                bool collided = false;
-                for (int64_t y = i + 1; y < e && !collided; y++) {
-                    uint64_t ky[WB];
-                    hash_key<WB>(ra, in.key[1][y], ky);
-                    collided = !bits_eq<WB>(ky, k0);
-                }
-                if (collided)  // otherwise k_reduce_hash took it
-                    coll_segment<WB, PB>(s, in, bits, ra, rh, nref, D0, G, i, e, a, search != 0);
+    for (uint32_t e = wave; e < cl.n; e += RED_THREADS / 64) {
+        const int64_t t = my_tail[e];
+        const uint64_t h = in.key[0][t];
+        // the segment's first record: 64 records back at a time
+        int64_t b = t;
+        while (true) {
+            const int64_t y = b - 1 - lane;
+            const bool same = y >= 0 && in.key[0][y] == h;
+            const uint64_t m = __ballot(same);  // a prefix of the lanes
+            if (m != ~0ull) {
+                b -= __builtin_ctzll(~m);
+                break;
             }
+            b -= 64;
         }
+        coll_segment_wave<WB, PB>(s, in, bits, ra, rh, cl.lo, cl.hi, D0, G, b, t + 1, s_dk[wave], s_dax[wave], a,
+                                  search != 0);
     }
     s_p[tid] = acc_partial(a);
     if (a.singular)
@@ -2151,7 +2242,8 @@ hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
                               const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
                               const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
-                              int search, Partial *partials, CollList *coll, Flags *flags, hipStream_t st)
+                              int search, Partial *partials, CollList *coll, int64_t *ctail, Flags *flags,
+                              hipStream_t st)
 {
     RefTab ra;
     ra.full = ra_full;
@@ -2170,9 +2262,9 @@ hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int
         const int64_t ge = red_workers((const void *)&k_reduce_hash<WB, PB>, 0);                                    \
         const int64_t per = (ntiles + ge - 1) / ge;                                                                \
         hipLaunchKernelGGL((k_reduce_hash<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, D0, G, per,         \
-                           search, eps, partials, coll, flags);                                                    \
-        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, nref, D0, G, per,     \
-                           search, partials, coll, flags);                                                         \
+                           search, eps, partials, coll, ctail, flags);                                             \
+        hipLaunchKernelGGL((k_reduce_hash_coll<WB, PB>), g, b, 0, st, s, sorted, n, bits, ra, rh, D0, G, per, search, \
+                           partials, coll, ctail, flags);                                                          \
     } while (0)
     switch (s.W * 2 + (fp32 ? 0 : 1)) {
     case 2: RH(1, 4); break;
