@@ -544,6 +544,7 @@ struct Plan {
     std::vector<uint32_t> parts;
     std::vector<uint64_t> sizes;  // records per listed subset
     std::vector<uint64_t> structural;  // structural candidates per listed subset
+    uint64_t cap_hint = 0;  // record capacity for any subset of the split (0: the listed ones' largest)
 };
 
 struct Job {
@@ -711,8 +712,15 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
         uint64_t mx = 0;
         for (auto t : tot)
             mx = std::max(mx, t);
-        if (subset_bytes(W, pb, RL.topb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0)
+        if (subset_bytes(W, pb, RL.topb, (double)mx) <= cap_bytes || J.forced_log2p >= 0 || c->opt.log2_partitions >= 0) {
+            // record buffers sized for the split's expected subset (as the
+            // planner projects it), so that later calls listing other
+            // subsets of the same split reuse them instead of growing them
+            const double want = total / (double)(1 << k) * 1.02 + 4096.0;
+            if ((double)mx < want && subset_bytes(W, pb, RL.topb, want) <= cap_bytes)
+                P.cap_hint = (uint64_t)want;
             return PT2_OK;
+        }
         k++;
     }
     return fail(PT2_E_NOMEM, "planner could not fit a subset into the device budget");
@@ -970,7 +978,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         refs_hash = h0;
     }
-    if ((rc = ensure_records(ws, W, pb, RL.topb, (int64_t)std::max<uint64_t>(mx, 1))))
+    if ((rc = ensure_records(ws, W, pb, RL.topb, (int64_t)std::max<uint64_t>(std::max(mx, P.cap_hint), 1))))
         return rc;
     const double rbytes = record_bytes(W, pb, RL.topb);
     res.record_bytes = (uint32_t)rbytes;

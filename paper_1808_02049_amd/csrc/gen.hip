@@ -34,6 +34,7 @@ struct GenHead {
     uint64_t R[2 * MAXORB];
     uint8_t occ[2][MAXORB];   // [spin][k]: spin 0 = alpha, 1 = beta
     uint8_t vir[2][MAXORB];
+    uint64_t zw[GEN_THREADS / 64];  // per-wavefront parts of z while it is formed
 };
 
 struct GenLds {
@@ -117,15 +118,20 @@ __device__ inline int between_sign(const uint64_t *key, int norb, int spin, int 
     return (cnt & 1) ? -1 : 1;
 }
 
-// pair index k of n items -> (i, j), i < j, lexicographic
+// pair index k of n items -> (i, j), i < j, lexicographic.  Row i starts at
+// s(i) = i (2n - i - 1) / 2; i is the root estimate of s(i) = k, fixed up to
+// the largest i with s(i) <= k.
 __device__ inline void pair_decode(int k, int n, int &i, int &j)
 {
-    i = 0;
-    while (k >= n - 1 - i) {
-        k -= n - 1 - i;
-        i++;
-    }
-    j = i + 1 + k;
+    const float b = (float)(2 * n - 1);
+    int r = (int)((b - sqrtf(b * b - 8.0f * (float)k)) * 0.5f);
+    r = r < 0 ? 0 : (r > n - 2 ? n - 2 : r);
+    while (r > 0 && r * (2 * n - r - 1) / 2 > k)
+        r--;
+    while (r + 1 <= n - 2 && (r + 1) * (2 * n - r - 2) / 2 <= k)
+        r++;
+    i = r;
+    j = i + 1 + (k - r * (2 * n - r - 1) / 2);
 }
 
 template <int W>
@@ -141,21 +147,41 @@ __device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, 
     for (int b = tid; b < 2 * s.norb; b += blockDim.x)
         H->R[b] = s.R[b];
     __syncthreads();
-    if (tid < 2) {
-        // occupied / virtual lists of one spin
-        int spin = tid, off = spin == 0 ? s.norb : 0, no = 0, nv = 0;
-        for (int p = 0; p < s.norb; p++) {
-            if (get_bit(H->key, off + p))
-                H->occ[spin][no++] = (uint8_t)p;
-            else
-                H->vir[spin][nv++] = (uint8_t)p;
+    {
+        // occupied / virtual lists: thread b places spin-orbital b by the
+        // count of occupied ones of its spin below it; the Zobrist hash is
+        // the XOR of the occupied ones' words, reduced per wavefront
+        uint64_t zx = 0;
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int b = tid; b < 2 * s.norb; b += blockDim.x) {
+            const int spin = b < s.norb ? 1 : 0, off = spin == 0 ? s.norb : 0, p = b - off;
+            int below = 0;  // occupied spin-orbitals in [off, b)
+            for (int w = off >> 6; w <= (b >> 6); w++) {
+                uint64_t m = ~0ull;
+                if (w == (off >> 6))
+                    m &= ~0ull << (off & 63);
+                if (w == (b >> 6))
+                    m &= (b & 63) ? (~0ull >> (64 - (b & 63))) : 0ull;
+                below += __popcll(H->key[w] & m);
+            }
+            if (get_bit(H->key, b)) {
+                H->occ[spin][below] = (uint8_t)p;
+                zx ^= H->R[b];
+            } else {
+                H->vir[spin][p - below] = (uint8_t)p;
+            }
         }
-    } else if (tid == 64) {
-        uint64_t z = 0;
-        for (int b = 0; b < 2 * s.norb; b++)
-            if (get_bit(H->key, b))
-                z ^= H->R[b];
-        H->z = z;
+        for (int o = 32; o >= 1; o >>= 1)
+            zx ^= __shfl_xor(zx, o);
+        if (lane == 0)
+            H->zw[wave] = zx;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t z = 0;
+            for (int w = 0; w < GEN_THREADS / 64; w++)
+                z ^= H->zw[w];
+            H->z = z;
+        }
     }
     __syncthreads();
     for (int idx = tid; idx < L.na * L.va; idx += blockDim.x) {
