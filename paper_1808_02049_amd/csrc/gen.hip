@@ -469,6 +469,31 @@ __device__ inline void store_rec_key(const GenLds &g, const DevSys &s, const Exc
     }
 }
 
+// The hash record words of an excitation without its bitstring: the Zobrist
+// hash z of the excited determinant and the flipped spin-orbitals (one byte
+// each, FLIP_NONE unused), as store_rec_key writes them.
+__device__ inline void exc_flips(const GenLds &g, int norb, const Exc &e, uint64_t &z, uint32_t &fl)
+{
+    const GenHead *H = g.head;
+    uint32_t f0, f1, f2 = FLIP_NONE, f3 = FLIP_NONE;
+    if (e.kind <= 1) {
+        const int off = e.kind == 0 ? norb : 0;
+        f0 = off + H->occ[e.kind][e.oi], f1 = off + H->vir[e.kind][e.vi];
+        z = H->z ^ H->R[f0] ^ H->R[f1];
+    } else {
+        if (e.kind <= 3) {
+            const int sp = e.kind - 2, off = sp == 0 ? norb : 0;
+            f0 = off + H->occ[sp][e.oi], f1 = off + H->occ[sp][e.oj];
+            f2 = off + H->vir[sp][e.vi], f3 = off + H->vir[sp][e.vj];
+        } else {
+            f0 = norb + H->occ[0][e.oi], f1 = norb + H->vir[0][e.vi];
+            f2 = H->occ[1][e.oj], f3 = H->vir[1][e.vj];
+        }
+        z = H->z ^ H->R[f0] ^ H->R[f1] ^ H->R[f2] ^ H->R[f3];
+    }
+    fl = f0 | (f1 << 8) | (f2 << 16) | (f3 << 24);
+}
+
 // The payload H_ai * c_i: FP64; FP64 arithmetic rounded once to FP32; or
 // FP32 integrals and arithmetic.
 template <int PM>
@@ -896,13 +921,13 @@ __device__ void build_buckets(const GenLds &g, const Tgt &t, const ExcLayout &L,
     __syncthreads();
 }
 
-__device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, int kind, int o, int q)
+__device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, const DivConsts &D, int kind, int o, int q)
 {
     Exc e;
     e.kind = kind;
     if (kind == 4) {
-        e.oi = o / L.va, e.vi = o - e.oi * L.va;
-        e.oj = q / L.vb, e.vj = q - e.oj * L.vb;
+        e.oi = (int)udiv((uint32_t)o, (uint32_t)L.va, D.inv_va), e.vi = o - e.oi * L.va;
+        e.oj = (int)udiv((uint32_t)q, (uint32_t)L.vb, D.inv_vb), e.vj = q - e.oj * L.vb;
     } else {
         const int sp = kind - 2;
         const uint16_t op = sp == 0 ? g.op[0][o] : g.op[1][o];
@@ -1012,9 +1037,26 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
                         hi = mid;
                 }
                 const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
-                e = make_exc(g, L, kind, lo, q);
+                e = make_exc(g, L, D, kind, lo, q);
             }
-            if (direct) {
+            if (direct && s.kc.hash) {
+                // hash records: no bitstring is formed
+                if (have) {
+                    uint64_t z;
+                    uint32_t fl;
+                    exc_flips(g, s.norb, e, z, fl);
+                    if (part_of(z, log2p) != part)
+                        bad = true;  // bucketing is inconsistent
+                    const uint64_t p = pos + f;
+                    if (p < end) {
+                        out.key[0][p] = z & s.kc.hash_mask;
+                        out.key[1][p] = ((uint64_t)det << 32) | fl;
+                        store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
+                    } else {
+                        atomicOr(&flags->err, ERR_OVERFLOW);
+                    }
+                }
+            } else if (direct) {
                 // every walked candidate is kept: its slot is its walk index
                 if (have) {
                     uint64_t key[W], z;
@@ -1187,7 +1229,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
                         hi = mid;
                 }
                 const int q = t.blist[bucket_lo(t, t.tgt[lo]) + (f - t.pre[lo])];
-                const Exc e = make_exc(g, L, kind, lo, q);
+                const Exc e = make_exc(g, L, D, kind, lo, q);
                 uint64_t key[W], z;
                 exc_key<W>(g, s.norb, e, key, z);
                 kept += keep_term<W, PM>(g, s, L, e, cutoff, key) ? 1u : 0u;
