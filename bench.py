@@ -2,8 +2,9 @@
 
 Default: workload C5, the largest that one GPU holds: (18a,18b) electrons in
 100 orbitals, 300,000 reference determinants, 959,326,200,000 single+double
-contributions, FP64, hash records, split into the 512 subsets of a hash split
-(Algorithm 2).  The timed region evaluates every subset exactly once, as
+contributions, FP64, hash records, split into the 256 subsets of a hash split
+(Algorithm 2; the fewest whose two record buffers fit the device: 3.75e9
+records, 90 GB each).  The timed region evaluates every subset exactly once, as
 --steps contiguous groups of subsets (one pt2_evaluate_parts_device call per
 step, each a complete pass of generation, sort and single pass over its
 subsets); the subset energies are summed in subset order.  Inputs are
@@ -18,7 +19,8 @@ and written once: 2 x record_bytes per record) over its average duration,
 measured with HIP events on the stream the passes run on, inside the timed
 region.  Beside the headline: the FP64 oracle timed on the host cores on a
 sample of the same workload (with the engine's result on that sample), the
-energy of one benchmarked subset against the stored oracle result, a few
+energy of one subset against the stored oracle result (evaluated alone when
+the stored records form a subset of a finer split than the timed one), a few
 subsets in the FP32-payload form, and workload C2 (one subset, 1.3e9
 contributions) as a second line.
 
@@ -42,7 +44,7 @@ METRIC = "PT2 contributions/s at |dE_PT2| <= 1e-6 Eh vs FP64 oracle; p50/p99 lat
 SORT_SRC = os.path.join(ROOT, "paper_1808_02049_amd", "csrc", "sort.hip")
 GOLDENS = os.path.join(ROOT, "tests", "golden", "oracle_goldens.json")
 # default hash split and oracle sample per workload
-SPLIT = {"c2": 0, "c3": 5, "c5": 9}
+SPLIT = {"c2": 0, "c3": 5, "c5": 8}
 CPU_SAMPLE = {"c2": 2000, "c3": 150, "c5": 24}
 
 
@@ -369,11 +371,22 @@ def split_bench(args):
         sh = 12 - log2p
         top = {p >> sh for p in g["parts"]}
         whole = len(top) == 1 and sorted(g["parts"]) == list(range(min(top) << sh, (min(top) + 1) << sh))
+        key = "parity_vs_oracle" if args.cutoff <= 0 else "cutoff_dE_vs_cutoff0_oracle"
         if whole and min(top) < nsub:
             p = min(top)
-            key = "parity_vs_oracle" if args.cutoff <= 0 else "cutoff_dE_vs_cutoff0_oracle"
             line[key] = {"subset": int(p), "of": P, "engine": float(eparts[p]),
                          "oracle": g["e"], "abs_dE": abs(float(eparts[p]) - g["e"])}
+        else:
+            # the stored records are one whole subset of a finer split:
+            # evaluate that subset alone, after the timed region
+            gk = 12 - (len(g["parts"]).bit_length() - 1)
+            gp = min(g["parts"]) >> (12 - gk)
+            if len(g["parts"]) == 1 << (12 - gk) and sorted(g["parts"]) == list(range(gp << (12 - gk),
+                                                                                       (gp + 1) << (12 - gk))):
+                _, ep = ctx.evaluate_parts(d_dets, d_c, e0, gk, [gp])
+                torch.cuda.synchronize()
+                line[key] = {"subset": int(gp), "of": 1 << gk, "engine": float(ep[0]),
+                             "oracle": g["e"], "abs_dE": abs(float(ep[0]) - g["e"])}
     ctx.close()
     torch.cuda.synchronize()
     extra = {}
@@ -392,9 +405,18 @@ def split_bench(args):
             "subsets": sel, "value": r32["n_contrib"] / el32, "unit": "contributions/s",
             "max_abs_dE_vs_fp64_path_per_subset": float(np.max(np.abs(e32 - eparts[sel]))),
             "record_bytes": r32["record_bytes"]}
-        if "parity_vs_oracle" in line and line["parity_vs_oracle"]["subset"] in sel:
-            j = sel.index(line["parity_vs_oracle"]["subset"])
+        pv = line.get("parity_vs_oracle")
+        if pv and pv["of"] == P and pv["subset"] in sel:
+            j = sel.index(pv["subset"])
             extra["fp32_payload_form"]["abs_dE_vs_oracle_subset"] = abs(float(e32[j]) - g["e"])
+        elif pv:
+            # the oracle's subset belongs to a finer split: evaluated alone
+            ctx32 = pt2.Context(h, eri, w.norb, w.nalpha, w.nbeta, precision="fp32", stream=stream,
+                                compress_keys=args.compress_keys)
+            _, eo = ctx32.evaluate_parts(d_dets, d_c, e0, pv["of"].bit_length() - 1, [pv["subset"]])
+            ctx32.close()
+            extra["fp32_payload_form"]["abs_dE_vs_oracle_subset"] = abs(float(eo[0]) - g["e"])
+            extra["fp32_payload_form"]["oracle_subset"] = {"subset": pv["subset"], "of": pv["of"]}
     del d_dets, d_c
     torch.cuda.synchronize()
     cpu = None
@@ -510,7 +532,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--cutoff", type=float, default=0.0,
                     help="drop terms with |H_ai c_i| below this (the paper's production setting is 1e-8)")
-    ap.add_argument("--log2p", type=int, default=-1, help="hash split (default: 9 for c5, 5 for c3)")
+    ap.add_argument("--log2p", type=int, default=-1, help="hash split (default: 8 for c5, 5 for c3)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="reference determinants in the oracle's timed sample (0: skip; default per workload)")
     ap.add_argument("--fp32-subsets", type=int, default=4,
