@@ -376,9 +376,10 @@ def split_bench(args):
             p = min(top)
             line[key] = {"subset": int(p), "of": P, "engine": float(eparts[p]),
                          "oracle": g["e"], "abs_dE": abs(float(eparts[p]) - g["e"])}
-        else:
+        elif nsub == P:
             # the stored records are one whole subset of a finer split:
-            # evaluate that subset alone, after the timed region
+            # evaluate that subset alone, after the timed region (not in
+            # profiling runs of a few subsets, whose traces it would mix)
             gk = 12 - (len(g["parts"]).bit_length() - 1)
             gp = min(g["parts"]) >> (12 - gk)
             if len(g["parts"]) == 1 << (12 - gk) and sorted(g["parts"]) == list(range(gp << (12 - gk),

@@ -197,6 +197,7 @@ struct Workspace {
     int64_t scan_tiles = 0;
     Buf small;
     Buf cnt, off, tot, parts_dev;
+    Buf bkt;                 // targeted generation: every reference's bucket table for the call's split
     Buf agrp;                              // groups of references sharing a spin string (spin_groups)
     std::vector<uint64_t> agrp_keys;       // host copy of the sorted reference keys, for grouping
     std::vector<uint32_t> agrp_host;       // source of the last upload of agrp
@@ -216,6 +217,7 @@ struct Workspace {
         buf_free(A, recA), buf_free(A, recB), buf_free(A, small);
         buf_free(A, counts), buf_free(A, csum), buf_free(A, coff), buf_free(A, offs);
         buf_free(A, cnt), buf_free(A, off), buf_free(A, tot), buf_free(A, parts_dev), buf_free(A, agrp);
+        buf_free(A, bkt);
         rec_cap = scan_tiles = 0;
         if (host_small && own_host_small)
             (void)hipHostFree(host_small);
@@ -545,6 +547,7 @@ struct Plan {
     std::vector<uint64_t> sizes;  // records per listed subset
     std::vector<uint64_t> structural;  // structural candidates per listed subset
     uint64_t cap_hint = 0;  // record capacity for any subset of the split (0: the listed ones' largest)
+    const uint16_t *bk = nullptr;  // bucket tables of the targeted generation (null: built per subset)
 };
 
 struct Job {
@@ -606,7 +609,7 @@ int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws,
     HIPCHK(hipMemcpyAsync(ws.parts_dev.p, P.parts.data(), P.parts.size() * 4, hipMemcpyHostToDevice, st));
     if (listed && cutoff <= 0.0 && !sys.z2)
         HIPCHK(launch_count_target(sys, L, refs, nref, P.log2p, (const uint32_t *)ws.parts_dev.p,
-                                   (int)P.parts.size(), (uint32_t *)ws.cnt.p, st));
+                                   (int)P.parts.size(), (uint32_t *)ws.cnt.p, P.bk, st));
     else if (listed)
         HIPCHK(launch_count_target_cut(sys, L, pm, refs, nref, P.log2p, (const uint32_t *)ws.parts_dev.p,
                                        (int)P.parts.size(), cutoff, (uint32_t *)ws.cnt.p, st));
@@ -685,9 +688,22 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
             return PT2_OK;
         }
         P.target = target_ok(L, nref, k);
+        P.bk = nullptr;
         if (P.target) {
             P.chunk = std::max<int64_t>(L.nper, 1);
             P.nchunks = nref;
+            // the references' bucket tables, built once for the call's
+            // subsets, when they take at most 1/32 of the budget (the record
+            // buffers are planned against the rest); not from the static
+            // scratch of the allocation-free entry point
+            const double bk_bytes = (double)nref * (double)gen_bucket_words(L, k) * 2.0;
+            if (!ws.A.arena && gen_buckets_ok(L, k) && bk_bytes <= cap_bytes / 32.0) {
+                int rc0;
+                if ((rc0 = buf_ensure(ws.A, ws.bkt, (size_t)bk_bytes)))
+                    return rc0;
+                HIPCHK(launch_gen_buckets(sys, L, refs, nref, k, (uint16_t *)ws.bkt.p, st));
+                P.bk = (const uint16_t *)ws.bkt.p;
+            }
         } else {
             const int64_t max_chunks =
                 std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 23, ((int64_t)1 << 27) >> k));
@@ -1015,7 +1031,7 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         else if (P.target)
             HIPCHK(launch_gen_target(sys, L, pm, refs, J.n, P.log2p, P.parts[q], c->opt.cutoff,
                                      (const uint64_t *)ws.off.p + (size_t)q * P.nchunks,
-                                     (const uint64_t *)ws.tot.p + q, A, &ds->flags, st));
+                                     (const uint64_t *)ws.tot.p + q, A, &ds->flags, P.bk, st));
         else
             HIPCHK(launch_gen_compact(sys, L, pm, refs, J.n, P.chunk,
                                       P.log2p, P.parts[q], c->opt.cutoff,

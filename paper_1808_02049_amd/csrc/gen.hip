@@ -856,6 +856,32 @@ __device__ uint32_t block_scan_excl(uint32_t *a, int n, uint32_t *wsum)
     return tot;
 }
 
+// Exclusive prefix of one value per thread over the block (thread order);
+// tot gets the block's total.  wsum: GEN_THREADS / 64 words of scratch.
+__device__ uint32_t block_excl_one(uint32_t v, uint32_t *wsum, uint32_t &tot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    __syncthreads();
+    if (lane == 63)
+        wsum[wave] = x;
+    __syncthreads();
+    uint32_t wpre = 0;
+    tot = 0;
+    for (int w = 0; w < GEN_THREADS / 64; w++) {
+        const uint32_t t = wsum[w];
+        wpre += w < wave ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    return wpre + x - v;
+}
+
 // Hash words of the inner / outer parts (kind 2, 3: spin sp; kind 4: alpha-beta).
 __device__ inline uint64_t inner_hash(const GenLds &g, const ExcLayout &L, int norb, int kind, int q)
 {
@@ -921,6 +947,35 @@ __device__ void build_buckets(const GenLds &g, const Tgt &t, const ExcLayout &L,
     __syncthreads();
 }
 
+// Layout of one determinant's bucket table (u16 words): for kinds 2, 3 and 4
+// in turn, the B bucket ends, then the kind's inner indices bucket by bucket
+// in ascending order (what build_buckets leaves in LDS).
+__host__ __device__ inline int64_t bucket_kind_off(const ExcLayout &L, int log2p, int kind)
+{
+    const int64_t B = (int64_t)1 << log2p;
+    return kind == 2 ? 0 : kind == 3 ? B + L.nvpa : 2 * B + L.nvpa + L.nvpb;
+}
+__host__ __device__ inline int64_t bucket_table_words(const ExcLayout &L, int log2p)
+{
+    const int64_t w = bucket_kind_off(L, log2p, 4) + ((int64_t)1 << log2p) + L.nSb;
+    return (w + 7) & ~(int64_t)7;
+}
+
+// The state build_buckets(fill = true) leaves, read from a determinant's
+// bucket table (src: that kind's part); with lists = false only the ends.
+__device__ void load_buckets(const Tgt &t, const ExcLayout &L, int kind, int log2p, const uint16_t *src, bool lists)
+{
+    const int tid = threadIdx.x, B = 1 << log2p, ni = n_inner(L, kind);
+    for (int b = tid; b < B; b += GEN_THREADS)
+        t.bstart[b] = src[b];
+    if (tid == 0)
+        t.bstart[B] = (uint32_t)ni;
+    if (lists)
+        for (int q = tid; q < ni; q += GEN_THREADS)
+            t.blist[q] = src[B + q];
+    __syncthreads();
+}
+
 __device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, const DivConsts &D, int kind, int o, int q)
 {
     Exc e;
@@ -983,7 +1038,7 @@ template <int W, int PM>
 __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
                                                             int log2p, uint32_t part, double cutoff,
                                                             const uint64_t *off, const uint64_t *tot, Planes out,
-                                                            Flags *flags)
+                                                            Flags *flags, const uint16_t *bk)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
@@ -996,23 +1051,67 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
     const uint64_t end = det + 1 < nref ? off[det + 1] : *tot;
     const uint64_t zp = g.head->z;
     bool bad = false;
-    // singles: filtered
-    for (int64_t k0 = 0; k0 < L.o2; k0 += GEN_THREADS) {
-        const int64_t k = k0 + tid;
-        Exc e;
-        const bool have = k < L.o2;
-        if (have)
-            e = decode(g, L, D, k);
-        emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
-    }
     // doubles: alpha-alpha, beta-beta, alpha-beta; without a cutoff or the
     // spin flip every candidate the bucket walk visits is kept
     const bool direct = cutoff <= 0.0 && !s.z2;
+    // singles: filtered by their subset
+    if (direct) {
+        // each thread takes a contiguous range of single-excitation indices
+        // and writes those in the subset after the earlier threads' ones:
+        // index order, as the filtered path below
+        const int64_t per = (L.o2 + GEN_THREADS - 1) / GEN_THREADS;
+        const int64_t k0 = (int64_t)tid * per, k1 = k0 + per < L.o2 ? k0 + per : L.o2;
+        uint32_t mine = 0;
+        for (int64_t k = k0; k < k1; k++) {
+            uint64_t z;
+            uint32_t fl;
+            exc_flips(g, s.norb, decode(g, L, D, k), z, fl);
+            mine += part_of(z, log2p) == part ? 1u : 0u;
+        }
+        uint32_t tot_s;
+        uint64_t p = pos + block_excl_one(mine, t.wsum, tot_s);
+        for (int64_t k = k0; k < k1; k++) {
+            const Exc e = decode(g, L, D, k);
+            uint64_t z;
+            uint32_t fl;
+            exc_flips(g, s.norb, e, z, fl);
+            if (part_of(z, log2p) != part)
+                continue;
+            if (p < end) {
+                if (s.kc.hash) {
+                    out.key[0][p] = z & s.kc.hash_mask;
+                    out.key[1][p] = ((uint64_t)det << 32) | fl;
+                } else {
+                    uint64_t key[W], zk;
+                    exc_key<W>(g, s.norb, e, key, zk);
+                    store_rec_key<W>(g, s, L, e, key, zk, det, out, (int64_t)p);
+                }
+                store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
+            } else {
+                atomicOr(&flags->err, ERR_OVERFLOW);
+            }
+            p++;
+        }
+        pos += tot_s;
+    } else {
+        for (int64_t k0 = 0; k0 < L.o2; k0 += GEN_THREADS) {
+            const int64_t k = k0 + tid;
+            Exc e;
+            const bool have = k < L.o2;
+            if (have)
+                e = decode(g, L, D, k);
+            emit_step<W, PM>(g, s, L, have, e, true, log2p, part, cutoff, pos, end, out, flags, t.wsum, bad, det);
+        }
+    }
     for (int kind = 2; kind <= 4; kind++) {
         const int no = n_outer(L, kind);
         if (no == 0 || n_inner(L, kind) == 0)
             continue;
-        build_buckets(g, t, L, s.norb, kind, log2p, true);
+        if (bk)
+            load_buckets(t, L, kind, log2p, bk + det * bucket_table_words(L, log2p) + bucket_kind_off(L, log2p, kind),
+                         true);
+        else
+            build_buckets(g, t, L, s.norb, kind, log2p, true);
         for (int o = tid; o < no; o += GEN_THREADS) {
             const uint32_t b = part ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, o), log2p);
             t.tgt[o] = (uint16_t)b;
@@ -1089,7 +1188,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
 template <int W>
 __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
                                                               int log2p, const uint32_t *parts, int nparts,
-                                                              uint32_t *cnt)
+                                                              uint32_t *cnt, const uint16_t *bk)
 {
     extern __shared__ __align__(16) char lds[];
     GenLds g = carve(lds, L);
@@ -1126,12 +1225,17 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
             // bucket counts, then every (outer part, listed subset) pair: the
             // inner parts completing o into subset p are the bucket
             // p ^ top(z(D) ^ h_o)
-            build_buckets(g, t, L, s.norb, kind, log2p, false);
+            if (bk)
+                load_buckets(t, L, kind, log2p,
+                             bk + det * bucket_table_words(L, log2p) + bucket_kind_off(L, log2p, kind), false);
+            else
+                build_buckets(g, t, L, s.norb, kind, log2p, false);
             const uint32_t np = (uint32_t)no * (uint32_t)nparts;
             for (uint32_t x = tid; x < np; x += GEN_THREADS) {
                 const uint32_t o = x / (uint32_t)nparts, j = x - o * (uint32_t)nparts;
-                const uint32_t c =
-                    t.bstart[t.plist[j] ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, (int)o), log2p)];
+                const uint32_t b = t.plist[j] ^ top_bits(zp ^ outer_hash(g, L, s.norb, kind, (int)o), log2p);
+                // loaded tables hold bucket ends, built ones counts
+                const uint32_t c = bk ? t.bstart[b] - bucket_lo(t, (int)b) : t.bstart[b];
                 if (c)
                     atomicAdd(&hist[j], c);
             }
@@ -1151,6 +1255,38 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
     __syncthreads();
     for (int j = tid; j < nparts; j += GEN_THREADS)
         cnt[(int64_t)j * nref + det] = hist[j];
+}
+
+// The bucket table of every reference determinant (layout at
+// bucket_table_words), written once per evaluation call: the buckets depend
+// on the determinant and the split, not on the subset, so each subset's
+// generation and the count pass load them instead of building them.
+template <int W>
+__global__ __launch_bounds__(GEN_THREADS) void k_gen_buckets(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
+                                                             int log2p, uint16_t *bk)
+{
+    extern __shared__ __align__(16) char lds[];
+    GenLds g = carve(lds, L);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    const int64_t det = blockIdx.x;
+    const int tid = threadIdx.x, B = 1 << log2p;
+    det_setup<W>(g, s, L, refs, det, false);
+    uint16_t *dst0 = bk + det * bucket_table_words(L, log2p);
+    for (int kind = 2; kind <= 4; kind++) {
+        const int ni = n_inner(L, kind);
+        uint16_t *dst = dst0 + bucket_kind_off(L, log2p, kind);
+        if (n_outer(L, kind) == 0 || ni == 0) {
+            for (int b = tid; b < B; b += GEN_THREADS)
+                dst[b] = 0;
+            continue;
+        }
+        build_buckets(g, t, L, s.norb, kind, log2p, true);
+        for (int b = tid; b < B; b += GEN_THREADS)
+            dst[b] = (uint16_t)t.bstart[b];
+        for (int q = tid; q < ni; q += GEN_THREADS)
+            dst[B + q] = t.blist[q];
+        __syncthreads();  // the next kind's buckets reuse the arrays
+    }
 }
 
 // Counts of the listed subsets with a cutoff (or the spin flip filter): the
@@ -1422,26 +1558,37 @@ hipError_t gen_compact_t(const DevSys &s, const ExcLayout &L, const Planes &refs
 }
 template <int W>
 hipError_t count_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                          const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st)
+                          const uint32_t *parts, int nparts, uint32_t *cnt, const uint16_t *bk, hipStream_t st)
 {
     if (nref == 0 || nparts == 0)
         return hipSuccess;
     const size_t lds = target_lds_bytes(L, log2p);
     hipLaunchKernelGGL((k_count_target<W>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
-                       log2p, parts, nparts, cnt);
+                       log2p, parts, nparts, cnt, bk);
+    return hipGetLastError();
+}
+template <int W>
+hipError_t gen_buckets_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                         uint16_t *bk, hipStream_t st)
+{
+    if (nref == 0)
+        return hipSuccess;
+    const size_t lds = target_lds_bytes(L, log2p);
+    hipLaunchKernelGGL((k_gen_buckets<W>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
+                       log2p, bk);
     return hipGetLastError();
 }
 
 template <int W, int PM>
 hipError_t gen_target_t(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
                         uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot, Planes out,
-                        Flags *flags, hipStream_t st)
+                        Flags *flags, const uint16_t *bk, hipStream_t st)
 {
     if (nref == 0)
         return hipSuccess;
     const size_t lds = target_lds_bytes(L, log2p);
     hipLaunchKernelGGL((k_gen_target<W, PM>), dim3((unsigned)nref), dim3(GEN_THREADS), lds, st, s, L, refs, nref,
-                       log2p, part, cutoff, off, tot, out, flags);
+                       log2p, part, cutoff, off, tot, out, flags, bk);
     return hipGetLastError();
 }
 template <int W, int PM>
@@ -1478,15 +1625,37 @@ hipError_t launch_gen_compact(const DevSys &s, const ExcLayout &L, int pm, const
 }
 
 hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                               const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st)
+                               const uint32_t *parts, int nparts, uint32_t *cnt, const uint16_t *bk, hipStream_t st)
 {
     if (!target_ok(L, nref, log2p))
         return hipErrorInvalidValue;
     switch (s.W) {
-    case 1: return count_target_t<1>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
-    case 2: return count_target_t<2>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
-    case 3: return count_target_t<3>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
-    case 4: return count_target_t<4>(s, L, refs, nref, log2p, parts, nparts, cnt, st);
+    case 1: return count_target_t<1>(s, L, refs, nref, log2p, parts, nparts, cnt, bk, st);
+    case 2: return count_target_t<2>(s, L, refs, nref, log2p, parts, nparts, cnt, bk, st);
+    case 3: return count_target_t<3>(s, L, refs, nref, log2p, parts, nparts, cnt, bk, st);
+    case 4: return count_target_t<4>(s, L, refs, nref, log2p, parts, nparts, cnt, bk, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int64_t gen_bucket_words(const ExcLayout &L, int log2p) { return bucket_table_words(L, log2p); }
+
+bool gen_buckets_ok(const ExcLayout &L, int log2p)
+{
+    // u16 ends and indices
+    return L.nvpa <= 65535 && L.nvpb <= 65535 && L.nSb <= 65535 && log2p <= 12;
+}
+
+hipError_t launch_gen_buckets(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                              uint16_t *bk, hipStream_t st)
+{
+    if (!gen_buckets_ok(L, log2p))
+        return hipErrorInvalidValue;
+    switch (s.W) {
+    case 1: return gen_buckets_t<1>(s, L, refs, nref, log2p, bk, st);
+    case 2: return gen_buckets_t<2>(s, L, refs, nref, log2p, bk, st);
+    case 3: return gen_buckets_t<3>(s, L, refs, nref, log2p, bk, st);
+    case 4: return gen_buckets_t<4>(s, L, refs, nref, log2p, bk, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1504,11 +1673,11 @@ hipError_t launch_count_target_cut(const DevSys &s, const ExcLayout &L, int pm, 
 
 hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                              int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
-                             Planes out, Flags *flags, hipStream_t st)
+                             Planes out, Flags *flags, const uint16_t *bk, hipStream_t st)
 {
     if (!target_ok(L, nref, log2p))
         return hipErrorInvalidValue;
-#define CALL(W, F) gen_target_t<W, F>(s, L, refs, nref, log2p, part, cutoff, off, tot, out, flags, st)
+#define CALL(W, F) gen_target_t<W, F>(s, L, refs, nref, log2p, part, cutoff, off, tot, out, flags, bk, st)
     PT2_DISPATCH(s.W, pm, CALL)
 #undef CALL
 }

@@ -403,7 +403,14 @@ size_t target_lds_bytes(const ExcLayout &L, int log2p);
 // Counts of the listed subsets only: cnt[j * nref + det] for parts[j] (device
 // list of nparts distinct subsets).
 hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
-                               const uint32_t *parts, int nparts, uint32_t *cnt, hipStream_t st);
+                               const uint32_t *parts, int nparts, uint32_t *cnt, const uint16_t *bk, hipStream_t st);
+// Bucket tables of every reference determinant for a 2^log2p split (u16
+// words per determinant: gen_bucket_words), read by launch_count_target and
+// launch_gen_target when passed (bk == nullptr: they build their own).
+int64_t gen_bucket_words(const ExcLayout &L, int log2p);
+bool gen_buckets_ok(const ExcLayout &L, int log2p);
+hipError_t launch_gen_buckets(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
+                              uint16_t *bk, hipStream_t st);
 // As launch_count_target, with a cutoff or the spin flip filter applied to
 // the terms of the listed subsets (their bucket walks; pm sets the value's
 // precision for the cutoff test).
@@ -412,7 +419,7 @@ hipError_t launch_count_target_cut(const DevSys &s, const ExcLayout &L, int pm, 
                                    hipStream_t st);
 hipError_t launch_gen_target(const DevSys &s, const ExcLayout &L, int pm, const Planes &refs, int64_t nref,
                              int log2p, uint32_t part, double cutoff, const uint64_t *off, const uint64_t *tot,
-                             Planes out, Flags *flags, hipStream_t st);
+                             Planes out, Flags *flags, const uint16_t *bk, hipStream_t st);
 // Exclusive scan of cnt[p][*] into off[k][*] for each listed subset p = parts[k]
 // (parts == nullptr: p = k); tot[k] = N of that subset.
 hipError_t launch_chunk_scan(const uint32_t *cnt, int64_t nchunks, const uint32_t *parts, int nparts,
