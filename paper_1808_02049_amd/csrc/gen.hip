@@ -508,6 +508,19 @@ __device__ inline void store_pay(const GenLds &g, const DevSys &s, const ExcLayo
         ((float *)out.pay)[i] = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c;
 }
 
+// store_pay with a non-temporal store
+template <int PM>
+__device__ inline void store_pay_stream(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e, double c,
+                                        const Planes &out, int64_t i)
+{
+    if (PM == PM_FP64)
+        __builtin_nontemporal_store(exc_value<double>(g, s, L, e, s.V, s.h) * c, (double *)out.pay + i);
+    else if (PM == PM_FP32_PAYLOAD)
+        __builtin_nontemporal_store((float)(exc_value<double>(g, s, L, e, s.V, s.h) * c), (float *)out.pay + i);
+    else
+        __builtin_nontemporal_store(exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c, (float *)out.pay + i);
+}
+
 // ---------------------------------------------------------------------------
 // Every term of every reference determinant, at its place in the reference's
 // block of nper records.  skip_kinds = 1 leaves the alpha-alpha doubles
@@ -1148,9 +1161,12 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout 
                         bad = true;  // bucketing is inconsistent
                     const uint64_t p = pos + f;
                     if (p < end) {
-                        out.key[0][p] = z & s.kc.hash_mask;
-                        out.key[1][p] = ((uint64_t)det << 32) | fl;
-                        store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
+                        // records are written once and read by the next
+                        // kernel: non-temporal stores keep the L2 for the
+                        // integrals the terms gather
+                        __builtin_nontemporal_store(z & s.kc.hash_mask, out.key[0] + p);
+                        __builtin_nontemporal_store(((uint64_t)det << 32) | fl, out.key[1] + p);
+                        store_pay_stream<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
                     } else {
                         atomicOr(&flags->err, ERR_OVERFLOW);
                     }

@@ -141,6 +141,27 @@ def test_c1_forced_split(pt2, c1, log2p):
     ctx.close()
 
 
+def test_c1_bucket_tables_equal_built_buckets(pt2, c1):
+    """Targeted generation and its count pass read the references' bucket
+    tables, built once per call, unless those would take more than 1/32 of
+    the budget; then each subset builds its own.  Both forms give the same
+    records, so every result is bit-identical."""
+    fields = ("e_pt2", "n_contrib", "n_unique", "n_external", "n_in_ref_hit", "key_xor", "key_sum",
+              "n_partitions", "min_abs_denom", "ref_cross")
+    res = []
+    for budget in (0, 100_000):
+        ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, log2_partitions=3, max_partition_bytes=budget)
+        got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
+        _, ep = ctx.evaluate_parts(c1["dets"], c1["c"], c1["e0"], 3, [6, 1, 3])
+        res.append((got, ep))
+        ctx.close()
+    (a, ea), (b, eb) = res
+    for k in fields:
+        assert a[k] == b[k], (k, a[k], b[k])
+    assert list(ea) == list(eb)
+    assert_matches(a, c1["ref"])
+
+
 def test_c1_small_budget_makes_planner_split(pt2, c1):
     ctx = pt2.Context(c1["h"], c1["eri"], 12, 4, 4, max_partition_bytes=2_000_000)
     got = ctx.evaluate(c1["dets"], c1["c"], c1["e0"])
