@@ -176,7 +176,7 @@ struct Small {  // one device block for small control data
     Partial result;
     unsigned long long n_out;
     AnchorBlk anc;            // the anchor of the diagonals (one evaluation)
-    uint32_t ref_far;         // hash records: a reference is beyond the compact table's reach
+    uint32_t ref_far;         // hash records: most flips of a reference from the first, when beyond four
     uint32_t pad2;
 };
 
@@ -885,7 +885,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
     Planes refs_hash{};
     uint32_t hash_digits = 0;  // digit positions a hash-record sort must take (0: from histograms)
     uint64_t anc_hash[MAXW] = {0, 0, 0, 0};
-    bool ref_compact = false;
+    bool ref_compact = false, ref_compact4 = false;
+    const uint32_t *ref_ex4 = nullptr;
     if (RL.hash) {
         if (J.n >= ((int64_t)1 << 32))
             return fail(PT2_E_INVALID, "hash records take fewer than 2^32 reference determinants");
@@ -898,20 +899,25 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         HIPCHK(launch_refs_aos(sys, refs, J.n, (uint64_t *)ws.refX.p, st));
         HIPCHK(launch_parent_g(sys, refs, J.n, J.e0, (double *)ws.hp.p, (double *)ws.gv.p, st));
-        // the compact form of the same table, when every reference is within
-        // four excitations of the first
-        if ((rc = buf_ensure(ws.A, ws.refE, (size_t)std::max<int64_t>(J.n, 1) * 8)))
+        // the compact forms of the same table: 8 bytes per reference when
+        // every reference is within four excitations of the first, 4 bytes
+        // within two (the single pass reads one entry per record)
+        const size_t ex_bytes = ((size_t)std::max<int64_t>(J.n, 1) * 8 + 255) & ~(size_t)255;
+        if ((rc = buf_ensure(ws.A, ws.refE, ex_bytes + (size_t)std::max<int64_t>(J.n, 1) * 4)))
             return rc;
         Small *d0 = ws.dsmall();
         HIPCHK(launch_zero_u32(&d0->ref_far, 1, st));
-        HIPCHK(launch_refs_ex(sys, refs, J.n, (uint64_t *)ws.refE.p, d0->anc.bits, &d0->ref_far, st));
+        HIPCHK(launch_refs_ex(sys, refs, J.n, (uint64_t *)ws.refE.p, (uint32_t *)((char *)ws.refE.p + ex_bytes),
+                              d0->anc.bits, &d0->ref_far, st));
         HIPCHK(hipMemcpyAsync(ws.host_small->anc.bits, d0->anc.bits, sizeof(d0->anc.bits), hipMemcpyDeviceToHost,
                               st));
         HIPCHK(hipMemcpyAsync(&ws.host_small->ref_far, &d0->ref_far, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         for (int w = 0; w < MAXW; w++)
             anc_hash[w] = ws.host_small->anc.bits[w];
-        ref_compact = ws.host_small->ref_far == 0 && c->opt.compact_refs != 0;
+        ref_compact = ws.host_small->ref_far <= 8 && c->opt.compact_refs != 0;
+        ref_compact4 = ws.host_small->ref_far <= 4 && c->opt.compact_refs != 0;
+        ref_ex4 = (const uint32_t *)((const char *)ws.refE.p + ex_bytes);
     }
     // the anchor of the diagonals of bitstring and rank-key records: the first
     // sorted reference, its energy and g vector, and its hot pair rows (their
@@ -1057,7 +1063,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
             return rc;
         if (RL.hash)
             HIPCHK(launch_reduce_hash(sys, pm, A, n, refs, (const uint64_t *)ws.refX.p,
-                                      ref_compact ? (const uint64_t *)ws.refE.p : nullptr, anc_hash, refs_hash, J.n,
+                                      ref_compact && !ref_compact4 ? (const uint64_t *)ws.refE.p : nullptr,
+                                      ref_compact4 ? ref_ex4 : nullptr, anc_hash, refs_hash, J.n,
                                       (const double *)ws.hp.p, (const double *)ws.gv.p, J.e0, subtract ? 0 : 1,
                                       ds->partials, ds->coll, (int64_t *)B.key[0], &ds->flags, st));
         else

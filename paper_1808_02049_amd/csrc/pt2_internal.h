@@ -488,16 +488,17 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
 hipError_t launch_refs_aos(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ra, hipStream_t st);
 // pm: the payload mode (PM_*), which sets the FP32 rounding bound.
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
+                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint32_t *ra_ex4,
+                              const uint64_t *anc_bits,
                               const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
                               int search, Partial *partials, CollList *coll, int64_t *ctail, Flags *flags,
                               hipStream_t st);
 // The references' flips relative to the first sorted reference (up to eight,
-// one byte each, 0xFF unused) into ex (n words), that reference's words into
-// anc_bits (MAXW words), and *far = 1 (set, never cleared) if some reference
-// differs from it in more than eight spin-orbitals.
-hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint64_t *anc_bits,
-                          uint32_t *far, hipStream_t st);
+// one byte each, 0xFF unused) into ex (n words) and their first four into
+// ex4 (n 32-bit words), that reference's words into anc_bits (MAXW words),
+// and into *far (only raised) the most flips of a reference beyond four.
+hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint32_t *ex4,
+                          uint64_t *anc_bits, uint32_t *far, hipStream_t st);
 // Sum RED_GRID partials in order into *out (device).
 hipError_t launch_final(const Partial *partials, Partial *out, hipStream_t st);
 // Inspection: unique keys and numerators (n_out on device).

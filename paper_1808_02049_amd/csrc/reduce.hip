@@ -1040,13 +1040,30 @@ __global__ void k_refs_aos(Planes bits, int64_t n, uint64_t *ra)
 // stream past it.
 struct RefTab {
     const uint64_t *full;  // ref_stride words per reference
-    const uint64_t *ex;    // flips relative to the anchor, or null
+    const uint64_t *ex;    // flips relative to the anchor (up to eight), or null
+    const uint32_t *ex4;   // the same when every reference is within four flips (half the bytes), or null
     uint64_t a[MAXW];      // the anchor's bitstring
 };
 
 template <int WB>
 __device__ inline void ref_bits(const RefTab &t, int64_t p, uint64_t (&k)[WB])
 {
+    if (t.ex4) {
+        const uint32_t e = t.ex4[p];
+#pragma unroll
+        for (int w = 0; w < WB; w++)
+            k[w] = t.a[w];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            const uint32_t b = (e >> (8 * f)) & 0xFFu;
+            if (b != FLIP_NONE) {
+#pragma unroll
+                for (int w = 0; w < WB; w++)
+                    k[w] ^= (w == (int)(b >> 6)) ? (1ull << (b & 63)) : 0ull;
+            }
+        }
+        return;
+    }
     if (t.ex) {
         const uint64_t e = t.ex[p];
 #pragma unroll
@@ -1083,7 +1100,7 @@ __device__ inline void ref_bits(const RefTab &t, int64_t p, uint64_t (&k)[WB])
 // from the anchor in more than eight spin-orbitals; the anchor's words go to
 // anc_bits.
 template <int WB>
-__global__ void k_refs_ex(Planes bits, int64_t n, uint64_t *ex, uint64_t *anc_bits, uint32_t *far)
+__global__ void k_refs_ex(Planes bits, int64_t n, uint64_t *ex, uint32_t *ex4, uint64_t *anc_bits, uint32_t *far)
 {
     uint64_t a[WB];
 #pragma unroll
@@ -1105,9 +1122,10 @@ __global__ void k_refs_ex(Planes bits, int64_t n, uint64_t *ex, uint64_t *anc_bi
                 nf++;
             }
         }
-        if (nf > 8)
-            atomicOr(far, 1u);
+        if (nf > 4)
+            atomicMax(far, (uint32_t)nf);
         ex[i] = e;
+        ex4[i] = (uint32_t)e;
     }
 }
 
@@ -2222,25 +2240,26 @@ hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint64_t *anc_bits,
-                          uint32_t *far, hipStream_t st)
+hipError_t launch_refs_ex(const DevSys &s, const Planes &bits, int64_t n, uint64_t *ex, uint32_t *ex4,
+                          uint64_t *anc_bits, uint32_t *far, hipStream_t st)
 {
     if (n <= 0)
         return hipSuccess;
     const int64_t gg = (n + 255) / 256;
     dim3 g((unsigned)(gg < 4096 ? gg : 4096)), b(256);
     switch (s.W) {
-    case 1: hipLaunchKernelGGL((k_refs_ex<1>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
-    case 2: hipLaunchKernelGGL((k_refs_ex<2>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
-    case 3: hipLaunchKernelGGL((k_refs_ex<3>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
-    case 4: hipLaunchKernelGGL((k_refs_ex<4>), g, b, 0, st, bits, n, ex, anc_bits, far); break;
+    case 1: hipLaunchKernelGGL((k_refs_ex<1>), g, b, 0, st, bits, n, ex, ex4, anc_bits, far); break;
+    case 2: hipLaunchKernelGGL((k_refs_ex<2>), g, b, 0, st, bits, n, ex, ex4, anc_bits, far); break;
+    case 3: hipLaunchKernelGGL((k_refs_ex<3>), g, b, 0, st, bits, n, ex, ex4, anc_bits, far); break;
+    case 4: hipLaunchKernelGGL((k_refs_ex<4>), g, b, 0, st, bits, n, ex, ex4, anc_bits, far); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int64_t n, const Planes &bits,
-                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint64_t *anc_bits,
+                              const uint64_t *ra_full, const uint64_t *ra_ex, const uint32_t *ra_ex4,
+                              const uint64_t *anc_bits,
                               const Planes &rh, int64_t nref, const double *D0, const double *G, double e0,
                               int search, Partial *partials, CollList *coll, int64_t *ctail, Flags *flags,
                               hipStream_t st)
@@ -2248,8 +2267,9 @@ hipError_t launch_reduce_hash(const DevSys &s, int pm, const Planes &sorted, int
     RefTab ra;
     ra.full = ra_full;
     ra.ex = ra_ex;
+    ra.ex4 = ra_ex4;
     for (int w = 0; w < MAXW; w++)
-        ra.a[w] = ra_ex ? anc_bits[w] : 0ull;
+        ra.a[w] = ra_ex || ra_ex4 ? anc_bits[w] : 0ull;
     (void)e0;  // carried by D0
     // relative rounding of a stored FP32 payload: once (FP64 arithmetic), or
     // FP32 integrals and arithmetic (a looser bound)
