@@ -283,7 +283,7 @@ struct pt2_ctx {
     int norb, na, nb, W;
     int topb;  // bytes of the last key plane of a record
     Alloc A;
-    Buf h, V, h32, V32, T, Tlo, R, binom;
+    Buf h, V, h32, V32, T, Tlo, R, binom, A2;
     DevSys sys;
     ExcLayout L;
     hipStream_t stream = nullptr;
@@ -1760,6 +1760,25 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     HIPCHK(hipMemcpy(c->T.p, T.data(), ntri * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->Tlo.p, Tlo.data(), ntri * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->R.p, R.data(), nso * 8, hipMemcpyHostToDevice));
+    // same-spin doubles' integral differences (ra|qb) - (rb|qa), r < q and
+    // a < b, formed once (the FP64 subtraction the terms would make), when
+    // the table is small beside the integrals' own footprint
+    const size_t npair = (size_t)norb * (norb - 1) / 2;
+    if (o.precision != PT2_FP32_ARITH && npair > 0 && npair * npair * 8 <= ((size_t)1 << 30)) {
+        std::vector<double> A2(npair * npair);
+        auto pidx = [&](size_t i, size_t j) { return i * (2 * norb - i - 1) / 2 + j - i - 1; };
+        for (size_t r = 0; r < (size_t)norb; r++)
+            for (size_t q = r + 1; q < (size_t)norb; q++) {
+                double *row = A2.data() + pidx(r, q) * npair;
+                for (size_t a = 0; a < (size_t)norb; a++)
+                    for (size_t b = a + 1; b < (size_t)norb; b++)
+                        row[pidx(a, b)] = eri[((r * norb + a) * norb + q) * norb + b] -
+                                          eri[((r * norb + b) * norb + q) * norb + a];
+            }
+        if ((rc = buf_alloc(c->A, c->A2, npair * npair * 8)))
+            return rc;
+        HIPCHK(hipMemcpy(c->A2.p, A2.data(), npair * npair * 8, hipMemcpyHostToDevice));
+    }
     if (o.precision == PT2_FP32_ARITH) {
         std::vector<float> h32(n2), V32(n4);
         for (size_t i = 0; i < n2; i++)
@@ -1778,6 +1797,7 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.V32 = (const float *)c->V32.p;
     c->sys.T = (const double *)c->T.p;
     c->sys.Tlo = (const double *)c->Tlo.p;
+    c->sys.A2 = (const double *)c->A2.p;
     c->sys.R = (const uint64_t *)c->R.p;
     c->sys.z2 = o.spin_flip;
 
@@ -2085,6 +2105,7 @@ PT2_API int pt2_destroy(pt2_ctx *c)
             (void)hipStreamSynchronize(c->stream);
         c->ws.release();
         buf_free(c->A, c->h), buf_free(c->A, c->V), buf_free(c->A, c->h32), buf_free(c->A, c->V32);
+        buf_free(c->A, c->A2);
         buf_free(c->A, c->T), buf_free(c->A, c->Tlo), buf_free(c->A, c->R), buf_free(c->A, c->binom);
         if (c->own_stream && c->stream)
             (void)hipStreamDestroy(c->stream);

@@ -374,7 +374,18 @@ __device__ inline F exc_value(const GenLds &g, const DevSys &s, const ExcLayout 
             ph2 = -ph2;
         if (a > lo && a < hi)
             ph2 = -ph2;
-        F v = V[eidx(n, r, a, q, b)] - V[eidx(n, r, b, q, a)];
+        F v;
+        if constexpr (sizeof(F) == 8) {
+            if (s.A2) {
+                // the same difference, formed once per context (r < q, a < b)
+                const size_t np = (size_t)n * (n - 1) / 2;
+                v = s.A2[(size_t)(r * (2 * n - r - 1) / 2 + q - r - 1) * np + (size_t)(a * (2 * n - a - 1) / 2 + b - a - 1)];
+            } else {
+                v = V[eidx(n, r, a, q, b)] - V[eidx(n, r, b, q, a)];
+            }
+        } else {
+            v = V[eidx(n, r, a, q, b)] - V[eidx(n, r, b, q, a)];
+        }
         return (F)(ph1 * ph2) * v;
     }
     int r = H->occ[0][e.oi], a = H->vir[0][e.vi];

@@ -96,6 +96,9 @@ struct DevSys {
                         // diagonal, row b1 at b1*nso - b1*(b1-1)/2 - b1, column b2 >= b1:
                         // T[b][b] = h_pp; T[b1][b2] = (pp|qq) - [same spin](pq|qp)
     const double *Tlo;  // the exact rounding error of each T entry (T + Tlo is exact)
+    const double *A2;   // (ra|qb) - (rb|qa) for r < q, a < b at [pair(r, q) * npair + pair(a, b)],
+                        // pair(i, j) = i (2 norb - i - 1) / 2 + j - i - 1, npair = norb (norb - 1) / 2
+                        // (same-spin doubles: one read instead of two), or null
     const uint64_t *R;  // Zobrist words, one per bit (2 norb)
     int z2;             // spin flip: generate alpha >= beta only, weight alpha != beta by 2
 };
