@@ -363,7 +363,7 @@ int ensure_scan(Workspace &ws, int64_t n)
         int rc;
         if ((rc = buf_alloc(ws.A, ws.counts, (size_t)tiles * 256 * 2)) ||
             (rc = buf_alloc(ws.A, ws.offs, (size_t)tiles * 256 * 4)) ||
-            (rc = buf_alloc(ws.A, ws.csum, (size_t)chunks * 256 * 8)) ||
+            (rc = buf_alloc(ws.A, ws.csum, (size_t)(chunks + 1) * 256 * 8)) ||
             (rc = buf_alloc(ws.A, ws.coff, (size_t)chunks * 256 * 8)))
             return rc;
         ws.scan_tiles = tiles;
@@ -378,7 +378,8 @@ size_t slice_bytes(int W, int pb, int topb, int64_t cap)
     const int64_t tiles = std::max<int64_t>(1, (cap + SORT_TILE - 1) / SORT_TILE);
     const int64_t chunks = (tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     return 2 * planes_bytes(W, cap, pb, topb) + align256((size_t)tiles * 256 * 2) +
-           align256((size_t)tiles * 256 * 4) + 2 * align256((size_t)chunks * 256 * 8);
+           align256((size_t)tiles * 256 * 4) + align256((size_t)(chunks + 1) * 256 * 8) +
+           align256((size_t)chunks * 256 * 8);
 }
 
 // Point a workspace's record and scan buffers into a slice of slice_bytes().
@@ -395,7 +396,7 @@ void carve_slice(Workspace &ws, char *p, int W, int pb, int topb, int64_t cap)
     take(ws.recB, planes_bytes(W, cap, pb, topb));
     take(ws.counts, align256((size_t)tiles * 256 * 2));
     take(ws.offs, align256((size_t)tiles * 256 * 4));
-    take(ws.csum, align256((size_t)chunks * 256 * 8));
+    take(ws.csum, align256((size_t)(chunks + 1) * 256 * 8));  // the last row: the digits' totals
     take(ws.coff, align256((size_t)chunks * 256 * 8));
     ws.rec_cap = cap, ws.rec_W = W, ws.rec_pb = pb, ws.rec_topb = topb;
     ws.scan_tiles = tiles;

@@ -438,8 +438,8 @@ hipError_t launch_hist(int W, const Planes &in, int64_t n, int ndig, uint64_t *h
 // bucket[d*256 + v] = exclusive scan of hist[d][*].
 hipError_t launch_hist_scan(const uint64_t *hist, int ndig, uint64_t *bucket, hipStream_t st);
 // One stable LSD digit pass: per-tile counts, offset scan, rank and scatter
-// (in -> out by digit `dig`).  counts: ntiles*256 u16; csum, coff:
-// nchunks*256 u64; rel: ntiles*256 u32 (offset within the chunk of
+// (in -> out by digit `dig`).  counts: ntiles*256 u16; csum:
+// (nchunks+1)*256 u64; coff: nchunks*256 u64; rel: ntiles*256 u32 (offset within the chunk of
 // SCAN_CHUNK tiles).  `mid` (optional) is recorded between the counting/scan
 // kernels and the scatter.
 hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Planes &out, int64_t n, int dig,

@@ -6,11 +6,12 @@
 // Each 8-bit digit is one pass of three steps (reduce-then-scan):
 //   1. k_tile_count: every tile of SORT_TILE records counts its digits (one
 //      read of the plane holding the digit, LDS histograms per wavefront);
-//   2. k_chunk_sum / k_chunk_scan / k_tile_offsets: exclusive scan of the
-//      counts over tiles, per digit value: the offset of every chunk of
-//      SCAN_CHUNK tiles from the digit's bucket start (u64), and of every tile
-//      within its chunk (u32; counts are u16, a tile holding at most 4096
-//      records), so the per-tile arrays move 6 B per digit value, not 12;
+//   2. k_tile_offsets / k_chunk_scan / k_chunk_start: exclusive scan of the
+//      counts over tiles, per digit value: the offset of every tile within
+//      its chunk of SCAN_CHUNK tiles (u32; counts are u16, a tile holding at
+//      most 4096 records, so the per-tile arrays move 6 B per digit value,
+//      not 12) with the chunk's totals, then of every chunk from the digit's
+//      bucket start (u64; one workgroup per digit value);
 //   3. k_scatter: every tile ranks its records by digit with wavefront
 //      ballots (stable), stages each plane through LDS in digit order and
 //      writes it out in runs of consecutive addresses.
@@ -20,7 +21,9 @@
 // about 40% of the pass.)
 // Digit histograms of all positions are computed up front in one read of the
 // key planes; they give the bucket starts, and a digit whose histogram has a
-// single nonzero bin is skipped.
+// single nonzero bin is skipped.  (Hash records skip them: their varying
+// digits are known, and each pass takes its bucket starts from its own
+// totals.)
 #include "pt2_internal.h"
 
 namespace pt2 {
@@ -218,61 +221,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_tile_count(Planes in, int64_t 
     counts[(int64_t)blockIdx.x * 256 + tid] = (uint16_t)t;
 }
 
-// Step 2a: per chunk of SCAN_CHUNK tiles, the sum of each digit's counts.
-__global__ __launch_bounds__(256) void k_chunk_sum(const uint16_t *counts, int64_t ntiles, uint64_t *csum)
-{
-    const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
-    const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
-    uint64_t acc = 0;
-    for (int64_t t = t0; t < t1; t++)
-        acc += counts[t * 256 + threadIdx.x];
-    csum[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc;
-}
-
-// Step 2b: exclusive scan of the chunk sums per digit, starting at the
-// digit's bucket start: from the all-digit histograms, or, when bucket is
-// null, the exclusive scan over digit values of this digit's totals.
-__global__ __launch_bounds__(256) void k_chunk_scan(const uint64_t *csum, int64_t nchunks, const uint64_t *bucket,
-                                                    uint64_t *coff)
-{
-    uint64_t run;
-    if (bucket) {
-        run = bucket[threadIdx.x];
-    } else {
-        __shared__ uint64_t s_tot[256];
-        uint64_t t = 0;
-        for (int64_t c = 0; c < nchunks; c++)
-            t += csum[c * 256 + threadIdx.x];
-        s_tot[threadIdx.x] = t;
-        __syncthreads();
-        run = 0;
-        for (int v = 0; v < (int)threadIdx.x; v++)
-            run += s_tot[v];
-    }
-    int64_t c = 0;
-    for (; c + 8 <= nchunks; c += 8) {
-        uint64_t x[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-            x[i] = csum[(c + i) * 256 + threadIdx.x];
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            coff[(c + i) * 256 + threadIdx.x] = run;
-            run += x[i];
-        }
-    }
-    for (; c < nchunks; c++) {
-        const uint64_t x = csum[c * 256 + threadIdx.x];
-        coff[c * 256 + threadIdx.x] = run;
-        run += x;
-    }
-}
-
-static_assert((int64_t)SCAN_CHUNK * SORT_THREADS * SORT_ITEMS_WIDE <= 0xFFFFFFFFll, "in-chunk offsets are u32");
-
-// Step 2c: offset of each tile's first record of each digit from its chunk's
-// (the record goes to coff[chunk][digit] + rel[tile][digit]).
-__global__ __launch_bounds__(256) void k_tile_offsets(const uint16_t *counts, int64_t ntiles, uint32_t *rel)
+// Step 2a: per chunk of SCAN_CHUNK tiles, the offset of each tile's first
+// record of each digit from its chunk's (the record goes to
+// coff[chunk][digit] + rel[tile][digit]), and the chunk's count of each digit.
+__global__ __launch_bounds__(256) void k_tile_offsets(const uint16_t *counts, int64_t ntiles, uint32_t *rel,
+                                                      uint64_t *csum)
 {
     const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK;
     const int64_t t1 = t0 + SCAN_CHUNK < ntiles ? t0 + SCAN_CHUNK : ntiles;
@@ -281,6 +234,67 @@ __global__ __launch_bounds__(256) void k_tile_offsets(const uint16_t *counts, in
         rel[t * 256 + threadIdx.x] = run;
         run += counts[t * 256 + threadIdx.x];
     }
+    csum[(int64_t)blockIdx.x * 256 + threadIdx.x] = run;
+}
+
+static_assert((int64_t)SCAN_CHUNK * SORT_THREADS * SORT_ITEMS_WIDE <= 0xFFFFFFFFll, "in-chunk offsets are u32");
+
+// Exclusive prefix of s[0..256) in place (thread 0; the values are few), the
+// total returned to thread 0.
+__device__ inline uint64_t excl256_serial(uint64_t *s)
+{
+    uint64_t run = 0;
+    for (int v = 0; v < 256; v++) {
+        const uint64_t x = s[v];
+        s[v] = run;
+        run += x;
+    }
+    return run;
+}
+
+// Step 2b: one workgroup per digit value: the exclusive scan of that digit's
+// chunk counts over the chunks (each thread a contiguous range of chunks), and
+// the digit's total in tot[digit].
+__global__ __launch_bounds__(256) void k_chunk_scan(const uint64_t *csum, int64_t nchunks, uint64_t *coff,
+                                                    uint64_t *tot)
+{
+    __shared__ uint64_t s_part[256];
+    const int v = blockIdx.x, tid = threadIdx.x;
+    const int64_t per = (nchunks + 255) / 256;
+    const int64_t c0 = (int64_t)tid * per < nchunks ? (int64_t)tid * per : nchunks;
+    const int64_t c1 = c0 + per < nchunks ? c0 + per : nchunks;
+    uint64_t sum = 0;
+    for (int64_t c = c0; c < c1; c++)
+        sum += csum[c * 256 + v];
+    s_part[tid] = sum;
+    __syncthreads();
+    if (tid == 0)
+        tot[v] = excl256_serial(s_part);
+    __syncthreads();
+    uint64_t run = s_part[tid];
+    for (int64_t c = c0; c < c1; c++) {
+        const uint64_t x = csum[c * 256 + v];
+        coff[c * 256 + v] = run;
+        run += x;
+    }
+}
+
+// Step 2c: each digit's bucket start added to its chunk offsets: from the
+// all-digit histograms, or, when bucket is null, the exclusive scan over
+// digit values of the totals.
+__global__ __launch_bounds__(256) void k_chunk_start(uint64_t *coff, int64_t nchunks, const uint64_t *bucket,
+                                                     const uint64_t *tot)
+{
+    __shared__ uint64_t s_start[256];
+    const int tid = threadIdx.x;
+    s_start[tid] = bucket ? bucket[tid] : tot[tid];
+    __syncthreads();
+    if (!bucket && tid == 0)
+        (void)excl256_serial(s_start);
+    __syncthreads();
+    const uint64_t st = s_start[tid];
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x)
+        coff[c * 256 + tid] += st;
 }
 
 // Step 3: rank and scatter one tile.
@@ -565,9 +579,12 @@ hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Plane
     default: return hipErrorInvalidValue;
     }
 #undef TC
-    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, csum);
-    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(256), 0, st, csum, nchunks, bucket, coff);
-    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, rel);
+    // csum holds nchunks + 1 rows: the last takes the digits' totals
+    uint64_t *tot = csum + nchunks * 256;
+    hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)nchunks), dim3(256), 0, st, counts, ntiles, rel, csum);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(256), dim3(256), 0, st, csum, nchunks, coff, tot);
+    hipLaunchKernelGGL(k_chunk_start, dim3((unsigned)(nchunks < 1024 ? nchunks : 1024)), dim3(256), 0, st, coff,
+                       nchunks, bucket, tot);
     if (mid)
         (void)hipEventRecord(mid, st);
 #define SC(WW, PB)                                                                                            \
