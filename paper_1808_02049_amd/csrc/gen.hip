@@ -50,8 +50,12 @@ struct GenLds {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// vp = false: no virtual-pair tables (the targeted kernels decode pair
+// indices in closed form instead; the tables are the largest part of the
+// layout, and LDS decides how many of those workgroups share a CU).
 __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, size_t *o_ph1, size_t *o_op0,
-                                             size_t *o_vp0, size_t *o_op1, size_t *o_vp1, size_t *o_sr = nullptr)
+                                             size_t *o_vp0, size_t *o_op1, size_t *o_vp1, size_t *o_sr = nullptr,
+                                             bool vp = true)
 {
     size_t o = align16(sizeof(GenHead));
     *o_ph0 = o;
@@ -61,11 +65,11 @@ __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, 
     *o_op0 = o;
     o = align16(o + 2 * (size_t)L.nopa);
     *o_vp0 = o;
-    o = align16(o + 2 * (size_t)L.nvpa);
+    o = align16(o + (vp ? 2 * (size_t)L.nvpa : 0));
     *o_op1 = o;
     o = align16(o + 2 * (size_t)L.nopb);
     *o_vp1 = o;
-    o = align16(o + 2 * (size_t)L.nvpb);
+    o = align16(o + (vp ? 2 * (size_t)L.nvpb : 0));
     if (o_sr)
         *o_sr = o;
     if (L.rank)
@@ -73,24 +77,24 @@ __host__ __device__ inline size_t lds_layout(const ExcLayout &L, size_t *o_ph0, 
     return o;
 }
 
-__host__ __device__ inline size_t gen_lds_bytes_dev(const ExcLayout &L)
-{
-    size_t a, b, c, d, e, f;
-    return lds_layout(L, &a, &b, &c, &d, &e, &f);
-}
-
-__device__ inline GenLds carve(char *base, const ExcLayout &L)
+__host__ __device__ inline size_t gen_lds_bytes_dev(const ExcLayout &L, bool vp = true)
 {
     size_t a, b, c, d, e, f, r;
-    lds_layout(L, &a, &b, &c, &d, &e, &f, &r);
+    return lds_layout(L, &a, &b, &c, &d, &e, &f, &r, vp);
+}
+
+__device__ inline GenLds carve(char *base, const ExcLayout &L, bool vp = true)
+{
+    size_t a, b, c, d, e, f, r;
+    lds_layout(L, &a, &b, &c, &d, &e, &f, &r, vp);
     GenLds g;
     g.head = (GenHead *)base;
     g.ph[0] = (int8_t *)(base + a);
     g.ph[1] = (int8_t *)(base + b);
     g.op[0] = (uint16_t *)(base + c);
-    g.vp[0] = (uint16_t *)(base + d);
+    g.vp[0] = vp ? (uint16_t *)(base + d) : nullptr;
     g.op[1] = (uint16_t *)(base + e);
-    g.vp[1] = (uint16_t *)(base + f);
+    g.vp[1] = vp ? (uint16_t *)(base + f) : nullptr;
     g.sr[0] = (uint64_t *)(base + r);
     g.sr[1] = (uint64_t *)(base + r) + L.nSa;
     return g;
@@ -197,7 +201,7 @@ __device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, 
         pair_decode(idx, L.na, i, j);
         g.op[0][idx] = (uint16_t)(i | (j << 8));
     }
-    for (int idx = tid; idx < L.nvpa; idx += blockDim.x) {
+    for (int idx = tid; g.vp[0] && idx < L.nvpa; idx += blockDim.x) {
         int i, j;
         pair_decode(idx, L.va, i, j);
         g.vp[0][idx] = (uint16_t)(i | (j << 8));
@@ -207,7 +211,7 @@ __device__ void det_setup(const GenLds &g, const DevSys &s, const ExcLayout &L, 
         pair_decode(idx, L.nb, i, j);
         g.op[1][idx] = (uint16_t)(i | (j << 8));
     }
-    for (int idx = tid; idx < L.nvpb; idx += blockDim.x) {
+    for (int idx = tid; g.vp[1] && idx < L.nvpb; idx += blockDim.x) {
         int i, j;
         pair_decode(idx, L.vb, i, j);
         g.vp[1][idx] = (uint16_t)(i | (j << 8));
@@ -253,6 +257,18 @@ struct DivConsts {
     float inv_va, inv_vb, inv_nvpa, inv_nvpb, inv_nSb;
 };
 
+// Virtual pair q of spin sp (i | j << 8, indices into the virtual list):
+// from the LDS table, or decoded when the layout has none.
+__device__ inline uint16_t vpair(const GenLds &g, const ExcLayout &L, int sp, int q)
+{
+    const uint16_t *t = sp == 0 ? g.vp[0] : g.vp[1];
+    if (t)
+        return t[q];
+    int i, j;
+    pair_decode(q, sp == 0 ? L.va : L.vb, i, j);
+    return (uint16_t)(i | (j << 8));
+}
+
 __device__ inline Exc decode(const GenLds &g, const ExcLayout &L, const DivConsts &D, int64_t k)
 {
     Exc e;
@@ -269,13 +285,13 @@ __device__ inline Exc decode(const GenLds &g, const ExcLayout &L, const DivConst
     } else if (k < L.o3) {
         uint32_t x = (uint32_t)(k - L.o2);
         uint32_t pi = udiv(x, L.nvpa, D.inv_nvpa), qi = x - pi * L.nvpa;
-        uint16_t op = g.op[0][pi], vp = g.vp[0][qi];
+        uint16_t op = g.op[0][pi], vp = vpair(g, L, 0, (int)qi);
         e.kind = 2;
         e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
     } else if (k < L.o4) {
         uint32_t x = (uint32_t)(k - L.o3);
         uint32_t pi = udiv(x, L.nvpb, D.inv_nvpb), qi = x - pi * L.nvpb;
-        uint16_t op = g.op[1][pi], vp = g.vp[1][qi];
+        uint16_t op = g.op[1][pi], vp = vpair(g, L, 1, (int)qi);
         e.kind = 3;
         e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
     } else {
@@ -915,7 +931,7 @@ __device__ inline uint64_t inner_hash(const GenLds &g, const ExcLayout &L, int n
         return H->R[H->occ[1][oj]] ^ H->R[H->vir[1][vj]];
     }
     const int sp = kind - 2, off = sp == 0 ? norb : 0;
-    const uint16_t vp = sp == 0 ? g.vp[0][q] : g.vp[1][q];
+    const uint16_t vp = vpair(g, L, sp, q);
     return H->R[off + H->vir[sp][vp & 255]] ^ H->R[off + H->vir[sp][vp >> 8]];
 }
 
@@ -1010,7 +1026,7 @@ __device__ inline Exc make_exc(const GenLds &g, const ExcLayout &L, const DivCon
     } else {
         const int sp = kind - 2;
         const uint16_t op = sp == 0 ? g.op[0][o] : g.op[1][o];
-        const uint16_t vp = sp == 0 ? g.vp[0][q] : g.vp[1][q];
+        const uint16_t vp = vpair(g, L, sp, q);
         e.oi = op & 255, e.oj = op >> 8, e.vi = vp & 255, e.vj = vp >> 8;
     }
     return e;
@@ -1059,14 +1075,14 @@ __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayo
 }
 
 template <int W, int PM>
-__global__ __launch_bounds__(GEN_THREADS) void k_gen_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
+__global__ __launch_bounds__(GEN_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_gen_target(DevSys s, ExcLayout L, const Planes refs, int64_t nref,
                                                             int log2p, uint32_t part, double cutoff,
                                                             const uint64_t *off, const uint64_t *tot, Planes out,
                                                             Flags *flags, const uint16_t *bk)
 {
     extern __shared__ __align__(16) char lds[];
-    GenLds g = carve(lds, L);
-    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    GenLds g = carve(lds, L, false);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L, false), L, log2p);
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x;
     det_setup<W>(g, s, L, refs, det);
@@ -1218,8 +1234,8 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target(DevSys s, ExcLayou
                                                               uint32_t *cnt, const uint16_t *bk)
 {
     extern __shared__ __align__(16) char lds[];
-    GenLds g = carve(lds, L);
-    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    GenLds g = carve(lds, L, false);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L, false), L, log2p);
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x, B = 1 << log2p;
     uint32_t *hist = t.hist;  // [nparts]
@@ -1293,8 +1309,8 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_buckets(DevSys s, ExcLayout
                                                              int log2p, uint16_t *bk)
 {
     extern __shared__ __align__(16) char lds[];
-    GenLds g = carve(lds, L);
-    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    GenLds g = carve(lds, L, false);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L, false), L, log2p);
     const int64_t det = blockIdx.x;
     const int tid = threadIdx.x, B = 1 << log2p;
     det_setup<W>(g, s, L, refs, det, false);
@@ -1335,10 +1351,10 @@ __global__ __launch_bounds__(GEN_THREADS) void k_count_target_cut(DevSys s, ExcL
                                                                   int nparts, double cutoff, uint32_t *cnt)
 {
     extern __shared__ __align__(16) char lds[];
-    GenLds g = carve(lds, L);
-    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L), L, log2p);
+    GenLds g = carve(lds, L, false);
+    Tgt t = carve_tgt(lds + gen_lds_bytes_dev(L, false), L, log2p);
     size_t o[8];
-    char *extra = lds + gen_lds_bytes_dev(L) + tgt_lds_layout(L, log2p, o);
+    char *extra = lds + gen_lds_bytes_dev(L, false) + tgt_lds_layout(L, log2p, o);
     uint32_t *ccount = (uint32_t *)extra;                                     // [nparts]
     uint16_t *cmap = (uint16_t *)(extra + align16((size_t)4 * nparts));      // [B]
     const int64_t det = blockIdx.x;
@@ -1502,7 +1518,7 @@ size_t gen_lds_bytes(const ExcLayout &L)
 size_t target_lds_bytes(const ExcLayout &L, int log2p)
 {
     size_t o[8];
-    return gen_lds_bytes(L) + tgt_lds_layout(L, log2p, o);
+    return gen_lds_bytes_dev(L, false) + tgt_lds_layout(L, log2p, o);
 }
 
 bool spin_reuse_ok(const ExcLayout &L, int W)
