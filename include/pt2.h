@@ -171,10 +171,11 @@ typedef struct {
                                       reference is within four excitations of the
                                       first sorted one, the single pass rebuilds
                                       parents from that one and up to eight flipped
-                                      spin-orbitals per reference (8 B each, kept
-                                      in the L2 cache) instead of a full bitstring
-                                      per reference; results are identical.  0:
-                                      always the full bitstrings                   */
+                                      spin-orbitals per reference (8 B each; 4 B
+                                      with up to four flips when every reference
+                                      is within two excitations) instead of a full
+                                      bitstring per reference; results are
+                                      identical.  0: always the full bitstrings    */
 } pt2_options;
 
 typedef struct {
