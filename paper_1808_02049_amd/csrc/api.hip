@@ -576,17 +576,25 @@ struct Job {
 // enables them (not for the inspection dumps, which return bitstrings).
 struct RecLayout {
     int W, topb, bits;
-    bool rank;  // rank keys
-    bool hash;  // hash records: (hash, parent and flips, payload), sorted on the hash
+    bool rank;    // rank keys
+    bool hash;    // hash records: (hash, parent and flips, payload), sorted on the hash
+    int pb;       // bytes of the payload plane (0: packed into the key words)
+    bool packed;  // FP32 hash records packed into two 8-byte words (hash_pack)
 };
 
-RecLayout rec_layout(const pt2_ctx *c, bool dump)
+// nref: references of the job (packed hash records hold parents below
+// HC_MAX_REFS)
+RecLayout rec_layout(const pt2_ctx *c, bool dump, int64_t nref)
 {
-    if (c->sys.kc.hash && !dump)
-        return {2, 8, 64, false, true};
+    const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
+    if (c->sys.kc.hash && !dump) {
+        if (pb == 4 && c->opt.hash_bits == 0 && c->norb <= HC_MAX_NORB && nref <= HC_MAX_REFS)
+            return {2, 8, 64, false, true, 0, true};
+        return {2, 8, 64, false, true, pb, false};
+    }
     if (c->sys.kc.on && !dump)
-        return {c->sys.kc.kw, c->sys.kc.ktop, c->sys.kc.kbits, true, false};
-    return {c->W, c->topb, 2 * c->norb, false, false};
+        return {c->sys.kc.kw, c->sys.kc.ktop, c->sys.kc.kbits, true, false, pb, false};
+    return {c->W, c->topb, 2 * c->norb, false, false, pb, false};
 }
 
 int count_pass(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, Workspace &ws, const Planes &refs, int64_t nref,
@@ -630,7 +638,7 @@ int plan_job(pt2_ctx *c, const DevSys &sys, const ExcLayout &L, const RecLayout 
              const Planes &refs, int64_t nref, const Job &J, hipStream_t st, Plan &P)
 {
     const int W = RL.W;
-    const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
+    const int pb = RL.pb;
     const double total = (double)nref * (double)L.nper;
     uint64_t budget = J.plan_budget > 0.0 ? (uint64_t)J.plan_budget : c->budget;
     if (!c->opt.device_budget_bytes && J.live_budget) {
@@ -827,7 +835,7 @@ int spin_groups(Workspace &ws, const Planes &refs, int W, int norb, int64_t n, b
 int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result *out)
 {
     const double t0 = now_ms();
-    const RecLayout RL = rec_layout(c, J.dump != 0);
+    const RecLayout RL = rec_layout(c, J.dump != 0, J.n);
     const int W = RL.W;  // key words of a stored term
     const bool subtract = c->opt.exclusion == PT2_EXCLUDE_SUBTRACT && !J.dump;
     DevSys sys = c->sys;
@@ -836,9 +844,10 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
         sys.kc.on = 0, L.rank = 0;
     if (!RL.hash)
         sys.kc.hash = 0;
+    sys.kc.hpacked = RL.packed ? 1 : 0;
     const int pm = c->opt.precision;
-    const int fp32 = pm != PT2_FP64;  // 4-byte payload plane
-    const int pb = fp32 ? 4 : 8;
+    const int fp32 = pm != PT2_FP64;  // FP32 payloads
+    const int pb = RL.pb;             // bytes of the payload plane
     int rc;
     Timing tm;
     tm.on = c->opt.timing != 0 && !ws.A.arena;  // no events are created without allocation
@@ -980,7 +989,8 @@ int run_job(pt2_ctx *c, Workspace &ws, hipStream_t st, const Job &J, pt2_result 
                 if (passes(bits) < passes(best))
                     best = bits;
             }
-            b = best;
+            // packed records take the low bits of the hash word
+            b = RL.packed && best > HC_KEPT_BITS ? HC_KEPT_BITS : best;
             sys.kc.hash_mask = b >= 64 ? ~0ull : ~((1ull << (64 - b)) - 1);
         } else {
             b = c->opt.hash_bits >= 64 ? 64 : c->opt.hash_bits;
@@ -1290,7 +1300,8 @@ class Scheduler {
         r->c.assign(coeffs, coeffs + n);
         r->n = n;
         r->e0 = e0;
-        const int pb = c->opt.precision != PT2_FP64 ? 4 : 8;
+        const RecLayout RL = rec_layout(c, false, n);
+        const int pb = RL.pb;
         const double total = (double)n * (double)c->L.nper;
         std::unique_lock<std::mutex> lk0(mu_);
         const double dev_budget = device_budget_locked(c->opt.device);
@@ -1301,7 +1312,6 @@ class Scheduler {
         if (c->opt.max_partition_bytes)
             cap = std::min(cap, (double)c->opt.max_partition_bytes);
         r->cap = cap;
-        const RecLayout RL = rec_layout(c, false);
         double per = subset_bytes(RL.W, pb, RL.topb, total * 1.02 + 4096.0);
         int k = 0;
         while (k < MAX_LOG2P && per > cap) {
@@ -1540,9 +1550,8 @@ class Scheduler {
                 w->ws->release();  // buffers go back to the allocator that made them
             w->ws->A = A;
             if (r->arena_off != SIZE_MAX) {
-                const RecLayout RL = rec_layout(c, false);
-                carve_slice(*w->ws, abase + r->arena_off, RL.W, c->opt.precision != PT2_FP64 ? 4 : 8, RL.topb,
-                            r->cap_records);
+                const RecLayout RL = rec_layout(c, false, r->n);
+                carve_slice(*w->ws, abase + r->arena_off, RL.W, RL.pb, RL.topb, r->cap_records);
             }
             Job J{};
             J.dets = r->dets.data();

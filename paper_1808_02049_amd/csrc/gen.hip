@@ -439,10 +439,24 @@ __device__ inline void put_top(void *plane, int topb, int64_t i, uint64_t v)
         ((uint16_t *)plane)[i] = (uint16_t)v;
 }
 
+// hash_put for payload mode PM: FP64 records are never packed, so their
+// kernels carry no packed branch.
+template <int PM>
+__device__ inline void put_hash_rec(const DevSys &s, const Planes &out, int64_t p, uint64_t z, uint64_t aux, bool nt)
+{
+    if (PM == PM_FP64) {
+        KeyCodec kc = s.kc;
+        kc.hpacked = 0;
+        hash_put(kc, s.norb, out, p, z, aux, nt);
+    } else {
+        hash_put(s.kc, s.norb, out, p, z, aux, nt);
+    }
+}
+
 // Record key of an excitation: its bitstring, or its rank key (KeyCodec).
 // Singles and alpha-beta doubles take their spin-string ranks from the
 // per-determinant tables; same-spin doubles rank the edited string.
-template <int W>
+template <int W, int PM>
 __device__ inline void store_rec_key(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e,
                                      const uint64_t (&key)[W], uint64_t z, int64_t det, const Planes &out,
                                      int64_t pos)
@@ -462,8 +476,7 @@ __device__ inline void store_rec_key(const GenLds &g, const DevSys &s, const Exc
             f0 = n + H->occ[0][e.oi], f1 = n + H->vir[0][e.vi];
             f2 = H->occ[1][e.oj], f3 = H->vir[1][e.vj];
         }
-        out.key[0][pos] = z & s.kc.hash_mask;
-        out.key[1][pos] = ((uint64_t)det << 32) | (f0 | (f1 << 8) | (f2 << 16) | (f3 << 24));
+        put_hash_rec<PM>(s, out, pos, z, ((uint64_t)det << 32) | (f0 | (f1 << 8) | (f2 << 16) | (f3 << 24)), false);
         return;
     }
     if (!s.kc.on) {
@@ -523,16 +536,20 @@ __device__ inline void exc_flips(const GenLds &g, int norb, const Exc &e, uint64
 
 // The payload H_ai * c_i: FP64; FP64 arithmetic rounded once to FP32; or
 // FP32 integrals and arithmetic.
+// (FP32 payloads of packed hash records go to the low half of the second word.)
 template <int PM>
 __device__ inline void store_pay(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e, double c,
                                  const Planes &out, int64_t i)
 {
-    if (PM == PM_FP64)
+    if (PM == PM_FP64) {
         ((double *)out.pay)[i] = exc_value<double>(g, s, L, e, s.V, s.h) * c;
-    else if (PM == PM_FP32_PAYLOAD)
-        ((float *)out.pay)[i] = (float)(exc_value<double>(g, s, L, e, s.V, s.h) * c);
+        return;
+    }
+    float *dst = s.kc.hpacked ? (float *)out.key[1] + 2 * i : (float *)out.pay + i;
+    if (PM == PM_FP32_PAYLOAD)
+        *dst = (float)(exc_value<double>(g, s, L, e, s.V, s.h) * c);
     else
-        ((float *)out.pay)[i] = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c;
+        *dst = exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c;
 }
 
 // store_pay with a non-temporal store
@@ -540,12 +557,15 @@ template <int PM>
 __device__ inline void store_pay_stream(const GenLds &g, const DevSys &s, const ExcLayout &L, const Exc &e, double c,
                                         const Planes &out, int64_t i)
 {
-    if (PM == PM_FP64)
+    if (PM == PM_FP64) {
         __builtin_nontemporal_store(exc_value<double>(g, s, L, e, s.V, s.h) * c, (double *)out.pay + i);
-    else if (PM == PM_FP32_PAYLOAD)
-        __builtin_nontemporal_store((float)(exc_value<double>(g, s, L, e, s.V, s.h) * c), (float *)out.pay + i);
+        return;
+    }
+    float *dst = s.kc.hpacked ? (float *)out.key[1] + 2 * i : (float *)out.pay + i;
+    if (PM == PM_FP32_PAYLOAD)
+        __builtin_nontemporal_store((float)(exc_value<double>(g, s, L, e, s.V, s.h) * c), dst);
     else
-        __builtin_nontemporal_store(exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c, (float *)out.pay + i);
+        __builtin_nontemporal_store(exc_value<float>(g, s, L, e, s.V32, s.h32) * (float)c, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,7 +593,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_direct(DevSys s, ExcLayout 
         Exc e = decode(g, L, D, k);
         uint64_t key[W], z;
         exc_key<W>(g, s.norb, e, key, z);
-        store_rec_key<W>(g, s, L, e, key, z, det, out, base + k);
+        store_rec_key<W, PM>(g, s, L, e, key, z, det, out, base + k);
         store_pay<PM>(g, s, L, e, c, out, base + k);
     }
 }
@@ -745,7 +765,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_gen_compact(DevSys s, ExcLayout
         if (keep) {
             uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
             if (p < cap) {
-                store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
+                store_rec_key<W, PM>(g, s, L, e, key, z, det, out, (int64_t)p);
                 store_pay<PM>(g, s, L, e, c, out, (int64_t)p);
             } else {
                 atomicOr(&flags->err, ERR_OVERFLOW);
@@ -1064,7 +1084,7 @@ __device__ inline void emit_step(const GenLds &g, const DevSys &s, const ExcLayo
     if (keep) {
         const uint64_t p = pos + woff + (uint64_t)__popcll(m & lt);
         if (p < end) {
-            store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
+            store_rec_key<W, PM>(g, s, L, e, key, z, det, out, (int64_t)p);
             store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
         } else {
             atomicOr(&flags->err, ERR_OVERFLOW);
@@ -1119,12 +1139,11 @@ __global__ __launch_bounds__(GEN_THREADS) __attribute__((amdgpu_waves_per_eu(5))
                 continue;
             if (p < end) {
                 if (s.kc.hash) {
-                    out.key[0][p] = z & s.kc.hash_mask;
-                    out.key[1][p] = ((uint64_t)det << 32) | fl;
+                    put_hash_rec<PM>(s, out, (int64_t)p, z, ((uint64_t)det << 32) | fl, false);
                 } else {
                     uint64_t key[W], zk;
                     exc_key<W>(g, s.norb, e, key, zk);
-                    store_rec_key<W>(g, s, L, e, key, zk, det, out, (int64_t)p);
+                    store_rec_key<W, PM>(g, s, L, e, key, zk, det, out, (int64_t)p);
                 }
                 store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
             } else {
@@ -1191,8 +1210,7 @@ __global__ __launch_bounds__(GEN_THREADS) __attribute__((amdgpu_waves_per_eu(5))
                         // records are written once and read by the next
                         // kernel: non-temporal stores keep the L2 for the
                         // integrals the terms gather
-                        __builtin_nontemporal_store(z & s.kc.hash_mask, out.key[0] + p);
-                        __builtin_nontemporal_store(((uint64_t)det << 32) | fl, out.key[1] + p);
+                        put_hash_rec<PM>(s, out, (int64_t)p, z, ((uint64_t)det << 32) | fl, true);
                         store_pay_stream<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
                     } else {
                         atomicOr(&flags->err, ERR_OVERFLOW);
@@ -1207,7 +1225,7 @@ __global__ __launch_bounds__(GEN_THREADS) __attribute__((amdgpu_waves_per_eu(5))
                         bad = true;  // bucketing is inconsistent
                     const uint64_t p = pos + f;
                     if (p < end) {
-                        store_rec_key<W>(g, s, L, e, key, z, det, out, (int64_t)p);
+                        store_rec_key<W, PM>(g, s, L, e, key, z, det, out, (int64_t)p);
                         store_pay<PM>(g, s, L, e, g.head->c, out, (int64_t)p);
                     } else {
                         atomicOr(&flags->err, ERR_OVERFLOW);

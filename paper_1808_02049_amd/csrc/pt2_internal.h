@@ -66,6 +66,7 @@ struct Flags {
 // fewer bits: 60 instead of 80 for (10a,10b) in 40 orbitals.
 struct KeyCodec {
     int hash;               // 1: records carry (Zobrist hash, parent and flips) instead (see below)
+    int hpacked;            // 1: FP32 hash records packed into two 8-byte words (hash_pack)
     uint64_t hash_mask;     // bits of the hash stored: all 64, its top bits (fewer digit
                             // passes), or its low bits (tests that force collisions)
     int on;                 // 1: records carry rank keys
@@ -83,6 +84,64 @@ struct KeyCodec {
 // 8 digit passes whatever norb is; the single pass rebuilds the bitstring from
 // the parent and resolves the rare determinants whose hashes collide.
 constexpr uint32_t FLIP_NONE = 0xFFu;
+
+// Packed FP32 hash records, for norb <= HC_MAX_NORB and fewer than
+// HC_MAX_REFS references, with at most HC_KEPT_BITS kept hash bits: the
+// auxiliary word shrinks to 48 bits, parent << 29 | a 29-bit code of the
+// flips, held in the free low 16 bits of the hash word and the high half of
+// a second word whose low half is the FP32 payload.  16-byte records in two
+// full 8-byte planes (a 4-byte plane would write half lines per bucket run).
+// The code holds four 7-bit spatial orbitals and a bit: a same-spin double
+// (bit 1) stores its removed r1 < r2 in that order for alpha and swapped for
+// beta, then its added a1, a2; an alpha-beta double (bit 0) stores alpha r,
+// a, then beta r, a; a single (bit 0) stores r, a, then 127 and 126 (alpha)
+// or 127 (beta).
+constexpr int HC_MAX_NORB = 126;
+constexpr int64_t HC_MAX_REFS = (int64_t)1 << 19;
+constexpr int HC_KEPT_BITS = 48;
+constexpr int HC_CODE_BITS = 29;
+
+__host__ __device__ inline uint64_t hash_pack(uint64_t aux, int norb)
+{
+    const uint32_t f0 = (uint32_t)aux & 255u, f1 = (uint32_t)(aux >> 8) & 255u;
+    const uint32_t f2 = (uint32_t)(aux >> 16) & 255u, f3 = (uint32_t)(aux >> 24) & 255u;
+    const uint32_t n = (uint32_t)norb;
+    uint32_t x0, x1, x2, x3, bit = 0;
+    if (f2 == FLIP_NONE) {
+        const bool al = f0 >= n;
+        const uint32_t off = al ? n : 0u;
+        x0 = f0 - off, x1 = f1 - off, x2 = 127u, x3 = al ? 126u : 127u;
+    } else if (f0 >= n && f2 < n) {
+        x0 = f0 - n, x1 = f1 - n, x2 = f2, x3 = f3;
+    } else {
+        const bool al = f0 >= n;
+        const uint32_t off = al ? n : 0u;
+        bit = 1;
+        x0 = al ? f0 - off : f1 - off, x1 = al ? f1 - off : f0 - off, x2 = f2 - off, x3 = f3 - off;
+    }
+    const uint64_t code = (uint64_t)(bit << 28 | x0 | x1 << 7 | x2 << 14 | x3 << 21);
+    return (aux >> 32) << HC_CODE_BITS | code;
+}
+
+__host__ __device__ inline uint64_t hash_unpack(uint64_t a48, int norb)
+{
+    const uint32_t c = (uint32_t)(a48 & ((1ull << HC_CODE_BITS) - 1));
+    const uint32_t x0 = c & 127u, x1 = (c >> 7) & 127u, x2 = (c >> 14) & 127u, x3 = (c >> 21) & 127u;
+    const uint32_t n = (uint32_t)norb;
+    uint32_t f0, f1, f2, f3;
+    if (c >> 28) {
+        if (x0 < x1)
+            f0 = n + x0, f1 = n + x1, f2 = n + x2, f3 = n + x3;
+        else
+            f0 = x1, f1 = x0, f2 = x2, f3 = x3;
+    } else if (x2 == 127u) {
+        const uint32_t off = x3 == 126u ? n : 0u;
+        f0 = off + x0, f1 = off + x1, f2 = FLIP_NONE, f3 = FLIP_NONE;
+    } else {
+        f0 = n + x0, f1 = n + x1, f2 = x2, f3 = x3;
+    }
+    return (a48 >> HC_CODE_BITS) << 32 | (uint64_t)(f0 | f1 << 8 | f2 << 16 | f3 << 24);
+}
 
 // Device view of the Hamiltonian (all pointers are device memory).
 struct DevSys {
@@ -223,6 +282,49 @@ __device__ inline void pl_put(const Planes &p, int w, int64_t i, uint64_t v)
         ((uint32_t *)b)[i] = (uint32_t)v;
     else
         ((uint16_t *)b)[i] = (uint16_t)v;
+}
+
+// Hash record i: its kept hash bits; its auxiliary word (parent << 32 | four
+// flipped spin-orbitals) and its FP32 payload in either record form.
+__device__ inline uint64_t hash_at(const KeyCodec &kc, const Planes &in, int64_t i)
+{
+    return in.key[0][i] & kc.hash_mask;
+}
+__device__ inline uint64_t aux_at(const KeyCodec &kc, int norb, const Planes &in, int64_t i)
+{
+    if (!kc.hpacked)
+        return in.key[1][i];
+    return hash_unpack((in.key[0][i] & 0xFFFFull) | (in.key[1][i] >> 32) << 16, norb);
+}
+__device__ inline float pay32_at(const KeyCodec &kc, const Planes &in, int64_t i)
+{
+    return kc.hpacked ? ((const float *)in.key[1])[2 * i] : ((const float *)in.pay)[i];
+}
+// Writes the hash and auxiliary words of hash record p (z: the full hash);
+// the payload is written separately (store_pay).  nt: non-temporal stores
+// (records read only by the next kernel).
+__device__ inline void hash_put(const KeyCodec &kc, int norb, const Planes &out, int64_t p, uint64_t z, uint64_t aux,
+                                bool nt)
+{
+    uint64_t k0 = z & kc.hash_mask;
+    if (kc.hpacked) {
+        const uint64_t a = hash_pack(aux, norb);
+        k0 |= a & 0xFFFFull;
+        const uint32_t hi = (uint32_t)(a >> 16);
+        if (nt) {
+            __builtin_nontemporal_store(k0, out.key[0] + p);
+            __builtin_nontemporal_store(hi, (uint32_t *)out.key[1] + 2 * p + 1);
+        } else {
+            out.key[0][p] = k0;
+            ((uint32_t *)out.key[1])[2 * p + 1] = hi;
+        }
+    } else if (nt) {
+        __builtin_nontemporal_store(k0, out.key[0] + p);
+        __builtin_nontemporal_store(aux, out.key[1] + p);
+    } else {
+        out.key[0][p] = k0;
+        out.key[1][p] = aux;
+    }
 }
 
 // Hash records: the collided segments (runs of one hash holding more than one

@@ -71,6 +71,28 @@ __device__ inline double load_pay(const Planes &p, int64_t i)
     return (double)((const float *)p.pay)[i];
 }
 
+// Hash and auxiliary words of hash record i: FP64 records are never packed,
+// so their kernels read the words as stored.
+template <int PB>
+__device__ inline uint64_t rec_hash(const KeyCodec &kc, const Planes &in, int64_t i)
+{
+    return PB == 8 ? in.key[0][i] : hash_at(kc, in, i);
+}
+template <int PB>
+__device__ inline uint64_t rec_aux(const KeyCodec &kc, int norb, const Planes &in, int64_t i)
+{
+    return PB == 8 ? in.key[1][i] : aux_at(kc, norb, in, i);
+}
+
+// Payload of hash record i (FP32 payloads may be packed; see hash_put).
+template <int PB>
+__device__ inline double hpay_at(const KeyCodec &kc, const Planes &in, int64_t i)
+{
+    if (PB == 8)
+        return ((const double *)in.pay)[i];
+    return (double)pay32_at(kc, in, i);
+}
+
 // first index in [lo, hi) whose reference key is >= k (upper == false) or > k
 template <int W>
 __device__ int64_t ref_bound(const Planes &refs, int64_t lo, int64_t hi, const uint64_t (&k)[W], bool upper)
@@ -1297,16 +1319,16 @@ __device__ inline double refine_num(const DevSys &s, const Planes &in, const Pla
                                     uint64_t h, int64_t tail, double num, double den, double eps)
 {
     int64_t head = tail;
-    double absum = fabs((double)((const float *)in.pay)[tail]);
-    while (head > 0 && in.key[0][head - 1] == h) {
+    double absum = fabs((double)pay32_at(s.kc, in, tail));
+    while (head > 0 && hash_at(s.kc, in, head - 1) == h) {
         head--;
-        absum += fabs((double)((const float *)in.pay)[head]);
+        absum += fabs((double)pay32_at(s.kc, in, head));
     }
     if (2.0 * fabs(num / den) * absum * eps <= REFINE_TOL)
         return num;
     double n64 = 0.0;
     for (int64_t x = head; x <= tail; x++)
-        n64 += rec_value64<WB>(s, ra, (const double *)bits.pay, in.key[1][x]);
+        n64 += rec_value64<WB>(s, ra, (const double *)bits.pay, aux_at(s.kc, s.norb, in, x));
     return n64;
 }
 
@@ -1471,7 +1493,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
     if (t_begin < t_end) {
         if (tid == 0) {
             const int64_t b0 = t_begin * RED_TILE, b1 = t_end * RED_TILE < n ? t_end * RED_TILE : n;
-            const uint64_t h0 = in.key[0][b0], h1 = in.key[0][b1 - 1];
+            const uint64_t h0 = rec_hash<PB>(s.kc, in, b0), h1 = rec_hash<PB>(s.kc, in, b1 - 1);
             int64_t l = 0, r = nref;
             while (l < r) {
                 const int64_t m = l + (r - l) / 2;
@@ -1512,9 +1534,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
         for (int j = 0; j < RED_ITEMS; j++) {
             const int64_t idx = r0 + j;
             const bool valid = idx < tend;
-            h[j] = valid ? in.key[0][idx] : 0ull;
-            ax[j] = valid ? in.key[1][idx] : 0ull;
-            p[j] = valid ? load_pay<PB>(in, idx) : 0.0;
+            h[j] = valid ? rec_hash<PB>(s.kc, in, idx) : 0ull;
+            ax[j] = valid ? rec_aux<PB>(s.kc, s.norb, in, idx) : 0ull;
+            p[j] = valid ? hpay_at<PB>(s.kc, in, idx) : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < RED_ITEMS; j++) {
@@ -1534,11 +1556,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
         hprev = __shfl_up(h[RED_ITEMS - 1], 1);
         const bool has_prev = r0 > 0 && r0 < tend;
         if (lane == 0 && has_prev) {
-            hprev = in.key[0][r0 - 1];
+            hprev = rec_hash<PB>(s.kc, in, r0 - 1);
             if (r0 > base)
-                hash_key<WB>(ra, in.key[1][r0 - 1], kprev);
+                hash_key<WB>(ra, rec_aux<PB>(s.kc, s.norb, in, r0 - 1), kprev);
         }
-        const uint64_t hnext = r0 + RED_ITEMS < n ? in.key[0][r0 + RED_ITEMS] : 0ull;
+        const uint64_t hnext = r0 + RED_ITEMS < n ? rec_hash<PB>(s.kc, in, r0 + RED_ITEMS) : 0ull;
         const bool has_next = r0 + RED_ITEMS < n;
 
         double run[RED_ITEMS];
@@ -1668,11 +1690,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                 const int64_t idx = pos + lane;
                 bool eq = false;
                 double v = 0.0;
-                if (idx < n && in.key[0][idx] == ch) {
+                if (idx < n && rec_hash<PB>(s.kc, in, idx) == ch) {
                     eq = true;
-                    v = load_pay<PB>(in, idx);
+                    v = hpay_at<PB>(s.kc, in, idx);
                     uint64_t kk[WB];
-                    hash_key<WB>(ra, in.key[1][idx], kk);
+                    hash_key<WB>(ra, rec_aux<PB>(s.kc, s.norb, in, idx), kk);
                     col |= bits_eq<WB>(kk, k0) ? 0 : 1;
                 }
                 const uint64_t m = __ballot(eq);
@@ -1752,15 +1774,15 @@ __device__ inline void coll_segment(const DevSys &s, const Planes &in, const Pla
                                     const Planes &rh, int64_t lo, int64_t hi, const double *D0, const double *G,
                                     int64_t i, int64_t e, Acc &a, bool search)
 {
-    const uint64_t h = in.key[0][i];
+    const uint64_t h = rec_hash<PB>(s.kc, in, i);
     for (int64_t x = i; x < e; x++) {
         uint64_t kx[WB];
-        const uint64_t ax = in.key[1][x];
+        const uint64_t ax = rec_aux<PB>(s.kc, s.norb, in, x);
         hash_key<WB>(ra, ax, kx);
         bool seen = false;
         for (int64_t y = i; y < x && !seen; y++) {
             uint64_t ky[WB];
-            hash_key<WB>(ra, in.key[1][y], ky);
+            hash_key<WB>(ra, rec_aux<PB>(s.kc, s.norb, in, y), ky);
             seen = bits_eq<WB>(ky, kx);
         }
         if (seen)
@@ -1768,10 +1790,10 @@ __device__ inline void coll_segment(const DevSys &s, const Planes &in, const Pla
         double nx = 0.0;
         for (int64_t y = x; y < e; y++) {
             uint64_t ky[WB];
-            const uint64_t ay = in.key[1][y];
+            const uint64_t ay = rec_aux<PB>(s.kc, s.norb, in, y);
             hash_key<WB>(ra, ay, ky);
             if (bits_eq<WB>(ky, kx))
-                nx += PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ay) : load_pay<PB>(in, y);
+                nx += PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ay) : hpay_at<PB>(s.kc, in, y);
         }
         hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, nullptr, nullptr, false, h, kx, (int64_t)(ax >> 32), -1,
                               nx, D0, G, a, search, 0.0);
@@ -1808,9 +1830,9 @@ __device__ inline void coll_segment_wave(const DevSys &s, const Planes &in, cons
         uint64_t k[WB], ax = 0ull;
         double v = 0.0;
         if (valid) {
-            ax = in.key[1][x];
+            ax = rec_aux<PB>(s.kc, s.norb, in, x);
             hash_key<WB>(ra, ax, k);
-            v = PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ax) : load_pay<PB>(in, x);
+            v = PB == 4 ? rec_value64<WB>(s, ra, (const double *)bits.pay, ax) : hpay_at<PB>(s.kc, in, x);
         } else {
 #pragma unroll
             for (int w = 0; w < WB; w++)
@@ -1858,7 +1880,7 @@ __device__ inline void coll_segment_wave(const DevSys &s, const Planes &in, cons
             coll_segment<WB, PB>(s, in, bits, ra, rh, lo, hi, D0, G, i, e, a, search);
         return;
     }
-    const uint64_t h = in.key[0][i];
+    const uint64_t h = rec_hash<PB>(s.kc, in, i);
 #pragma unroll
     for (int d = 0; d < COLL_DETS; d++) {
         if (d >= nd)
@@ -1903,12 +1925,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash_coll(DevSys s, Plan
     acc_init(a);
     for (uint32_t e = wave; e < cl.n; e += RED_THREADS / 64) {
         const int64_t t = my_tail[e];
-        const uint64_t h = in.key[0][t];
+        const uint64_t h = rec_hash<PB>(s.kc, in, t);
         // the segment's first record: 64 records back at a time
         int64_t b = t;
         while (true) {
             const int64_t y = b - 1 - lane;
-            const bool same = y >= 0 && in.key[0][y] == h;
+            const bool same = y >= 0 && rec_hash<PB>(s.kc, in, y) == h;
             const uint64_t m = __ballot(same);  // a prefix of the lanes
             if (m != ~0ull) {
                 b -= __builtin_ctzll(~m);

@@ -400,17 +400,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
         }
     };
     // narrow tiles keep the next plane's loads in flight while one plane is
-    // staged; wide tiles load each plane when it is staged (registers)
+    // staged; wide tiles load each plane when it is staged (registers).
+    // PB == 0: no payload plane (packed records).
     constexpr bool PIPE = IT <= SORT_ITEMS || PT2_WIDE_PIPE;
+    constexpr int NPL = W + (PB ? 1 : 0);
     uint64_t cur[IT];
     if constexpr (PIPE)
         load_plane(0, cur);
 
 #pragma unroll
-    for (int w = 0; w < W + 1; w++) {
+    for (int w = 0; w < NPL; w++) {
         uint64_t nxt[IT];
         if constexpr (PIPE) {
-            if (w < W)
+            if (w + 1 < NPL)
                 load_plane(w + 1, nxt);
         } else {
             load_plane(w, cur);
@@ -441,7 +443,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scatter(Planes in, Planes out,
                 ((uint32_t *)out.pay)[dst] = (uint32_t)v;
         }
         __syncthreads();
-        if (PIPE && w < W) {
+        if (PIPE && w + 1 < NPL) {
 #pragma unroll
             for (int j = 0; j < IT; j++)
                 cur[j] = nxt[j];
@@ -594,6 +596,13 @@ hipError_t launch_radix_pass(int W, int pay_bytes, const Planes &in, const Plane
         else                                                                                                  \
             hipLaunchKernelGGL((k_scatter<WW, PB, SORT_ITEMS_WIDE>), g, b, 0, st, in, out, n, dig, coff, rel, flags); \
     } while (0)
+    if (pay_bytes == 0) {
+        // packed hash records: two 8-byte key planes, wide tiles
+        if (W != 2 || items != SORT_ITEMS_WIDE)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_scatter<2, 0, SORT_ITEMS_WIDE>), g, b, 0, st, in, out, n, dig, coff, rel, flags);
+        return hipGetLastError();
+    }
     switch (W * 2 + (pay_bytes == 8 ? 1 : 0)) {
     case 2: SC(1, 4); break;
     case 3: SC(1, 8); break;
