@@ -1310,13 +1310,13 @@ __device__ inline double rec_value64(const DevSys &s, const RefTab &ra, const do
 // more than REFINE_TOL gets its numerator again as the FP64 sum of its
 // records' FP64 payloads.  The rounding moves N by at most eps * sum |p_i|,
 // so the term by about 2 |N/d| eps sum |p_i|; the sum of |p_i| is read only
-// when |N/d| exceeds REFINE_RATIO.
+// when |N/d| exceeds REFINE_RATIO.  The single pass lists such segments with
+// the collided ones; the second kernel sums their records' FP64 values.
 constexpr double REFINE_RATIO = 1e-3;
 constexpr double REFINE_TOL = 1e-11;
 
-template <int WB>
-__device__ inline double refine_num(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
-                                    uint64_t h, int64_t tail, double num, double den, double eps)
+__device__ inline bool refine_needed(const DevSys &s, const Planes &in, uint64_t h, int64_t tail, double num,
+                                     double den, double eps)
 {
     int64_t head = tail;
     double absum = fabs((double)pay32_at(s.kc, in, tail));
@@ -1324,22 +1324,19 @@ __device__ inline double refine_num(const DevSys &s, const Planes &in, const Pla
         head--;
         absum += fabs((double)pay32_at(s.kc, in, head));
     }
-    if (2.0 * fabs(num / den) * absum * eps <= REFINE_TOL)
-        return num;
-    double n64 = 0.0;
-    for (int64_t x = head; x <= tail; x++)
-        n64 += rec_value64<WB>(s, ra, (const double *)bits.pay, aux_at(s.kc, s.norb, in, x));
-    return n64;
+    return 2.0 * fabs(num / den) * absum * eps > REFINE_TOL;
 }
 
 // One distinct determinant of a hash segment: exclusion, then the term.
-// tail: index of the segment's last record (FP32 refinement); refine < 0: the
-// numerator is already FP64.
+// tail: index of the segment's last record, for the FP32 refinement check (a
+// segment that needs it sets *defer and adds nothing: the second kernel takes
+// it); tail < 0: the numerator is already FP64.
 template <int WB, int PB>
 __device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Planes &bits, const RefTab &ra,
                                      const Planes &rh, int64_t lo, int64_t hi, const uint64_t *s_rh, const int64_t *s_ri,
                                      bool staged, uint64_t h, const uint64_t (&k)[WB], int64_t parent, int64_t tail,
-                                     double num, const double *D0, const double *G, Acc &a, bool search, double eps)
+                                     double num, const double *D0, const double *G, Acc &a, bool search, double eps,
+                                     int *defer = nullptr)
 {
     a.n_unique++;
     if (!search)
@@ -1378,8 +1375,11 @@ __device__ inline void hash_key_term(const DevSys &s, const Planes &in, const Pl
     }
     const double den = den_parent<WB>(s.T, s.Tlo, 2 * s.norb, k, ra, parent, G, D0);
     if constexpr (PB == 4) {
-        if (tail >= 0 && den != 0.0 && fabs(num / den) > REFINE_RATIO)
-            num = refine_num<WB>(s, in, bits, ra, h, tail, num, den, eps);
+        if (tail >= 0 && den != 0.0 && fabs(num / den) > REFINE_RATIO && refine_needed(s, in, h, tail, num, den, eps)) {
+            a.n_unique--;  // counted again by the second kernel
+            *defer = 1;
+            return;
+        }
     }
     a.n_ext++;
     const double ad = fabs(den);
@@ -1724,9 +1724,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
         }
         __syncthreads();
         const int qn = (int)qtot + cflag;
+        for (int e = tid; e < qn; e += RED_THREADS) {
+            if (q_c[e])
+                continue;
+            uint64_t k0[WB];
+            const uint64_t aux = q_a[e];
+            hash_key<WB>(ra, aux, k0);
+            hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32),
+                                  base + (int64_t)q_t[e], q_v[e], D0, G, a, search != 0, eps, &q_c[e]);
+            if (PB == 4 && q_c[e])
+                s_tcoll = 1;
+        }
+        __syncthreads();
         if (s_tcoll && wave == 0) {
-            // collided segments are left to k_reduce_hash_coll: wave 0 lists
-            // them in queue (record) order
+            // collided segments (and, with FP32 payloads, those to refine) are
+            // left to k_reduce_hash_coll: wave 0 lists them in queue (record)
+            // order
             const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
             for (int e0 = 0; e0 < qn; e0 += 64) {
                 const int e = e0 + lane;
@@ -1736,15 +1749,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_hash(DevSys s, Planes in
                     my_tail[ncoll + (uint32_t)__popcll(m & lt)] = base + (int64_t)q_t[e];
                 ncoll += (uint32_t)__popcll(m);
             }
-        }
-        for (int e = tid; e < qn; e += RED_THREADS) {
-            if (q_c[e])
-                continue;
-            uint64_t k0[WB];
-            const uint64_t aux = q_a[e];
-            hash_key<WB>(ra, aux, k0);
-            hash_key_term<WB, PB>(s, in, bits, ra, rh, lo, hi, s_rh, s_ri, staged, q_h[e], k0, (int64_t)(aux >> 32),
-                                  base + (int64_t)q_t[e], q_v[e], D0, G, a, search != 0, eps);
         }
         __syncthreads();
     }
