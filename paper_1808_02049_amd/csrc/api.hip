@@ -1775,19 +1775,10 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     // the table is small beside the integrals' own footprint
     const size_t npair = (size_t)norb * (norb - 1) / 2;
     if (o.precision != PT2_FP32_ARITH && npair > 0 && npair * npair * 8 <= ((size_t)1 << 30)) {
-        std::vector<double> A2(npair * npair);
-        auto pidx = [&](size_t i, size_t j) { return i * (2 * norb - i - 1) / 2 + j - i - 1; };
-        for (size_t r = 0; r < (size_t)norb; r++)
-            for (size_t q = r + 1; q < (size_t)norb; q++) {
-                double *row = A2.data() + pidx(r, q) * npair;
-                for (size_t a = 0; a < (size_t)norb; a++)
-                    for (size_t b = a + 1; b < (size_t)norb; b++)
-                        row[pidx(a, b)] = eri[((r * norb + a) * norb + q) * norb + b] -
-                                          eri[((r * norb + b) * norb + q) * norb + a];
-            }
         if ((rc = buf_alloc(c->A, c->A2, npair * npair * 8)))
             return rc;
-        HIPCHK(hipMemcpy(c->A2.p, A2.data(), npair * npair * 8, hipMemcpyHostToDevice));
+        HIPCHK(launch_build_a2((const double *)c->V.p, norb, (double *)c->A2.p, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
     }
     if (o.precision == PT2_FP32_ARITH) {
         std::vector<float> h32(n2), V32(n4);

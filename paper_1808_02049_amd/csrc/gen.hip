@@ -1701,6 +1701,31 @@ hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes
 
 int64_t gen_bucket_words(const ExcLayout &L, int log2p) { return bucket_table_words(L, log2p); }
 
+// A2[pair(r, q) * npair + pair(a, b)] = (ra|qb) - (rb|qa) for r < q, a < b
+// (the FP64 subtraction the terms would make).
+__global__ __launch_bounds__(256) void k_build_a2(const double *V, int n, double *A2)
+{
+    const int64_t np = (int64_t)n * (n - 1) / 2;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < np * np;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = x / np, v = x - u * np;
+        int r, q, a, b;
+        pair_decode((int)u, n, r, q);
+        pair_decode((int)v, n, a, b);
+        A2[x] = V[eidx(n, r, a, q, b)] - V[eidx(n, r, b, q, a)];
+    }
+}
+
+hipError_t launch_build_a2(const double *V, int norb, double *A2, hipStream_t st)
+{
+    const int64_t np = (int64_t)norb * (norb - 1) / 2;
+    if (np <= 0)
+        return hipSuccess;
+    const int64_t blocks = (np * np + 255) / 256;
+    hipLaunchKernelGGL(k_build_a2, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, V, norb, A2);
+    return hipGetLastError();
+}
+
 bool gen_buckets_ok(const ExcLayout &L, int log2p)
 {
     // u16 ends and indices

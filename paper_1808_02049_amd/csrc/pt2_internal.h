@@ -513,6 +513,8 @@ hipError_t launch_count_target(const DevSys &s, const ExcLayout &L, const Planes
 // words per determinant: gen_bucket_words), read by launch_count_target and
 // launch_gen_target when passed (bk == nullptr: they build their own).
 int64_t gen_bucket_words(const ExcLayout &L, int log2p);
+// The same-spin integral differences of DevSys::A2 from the device integrals V.
+hipError_t launch_build_a2(const double *V, int norb, double *A2, hipStream_t st);
 bool gen_buckets_ok(const ExcLayout &L, int log2p);
 hipError_t launch_gen_buckets(const DevSys &s, const ExcLayout &L, const Planes &refs, int64_t nref, int log2p,
                               uint16_t *bk, hipStream_t st);
