@@ -588,7 +588,8 @@ hipError_t launch_refs_rank(const DevSys &s, const Planes &bits, int64_t n, cons
 // E0 minus its energy (D0) and its g vector G (nref x 2 norb), double-double;
 // the single pass.
 hipError_t launch_refs_hash(const DevSys &s, const Planes &bits, int64_t n, const Planes &out, hipStream_t st);
-// D0[p] = E0 - H_pp and G[p][x] as double-double pairs (hi, lo).
+// D0[p] = E0 - H_pp and G[p][x] (g_x, plus D0[p]/2 for x occupied in p) as
+// double-double pairs (hi, lo).
 hipError_t launch_parent_g(const DevSys &s, const Planes &bits, int64_t n, double e0, double *D0, double *G,
                            hipStream_t st);
 // The references' bitstrings record by record, 2^ceil(log2 W) words each.

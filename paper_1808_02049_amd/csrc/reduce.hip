@@ -985,17 +985,20 @@ __global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t
 {
     __shared__ uint64_t s_k[WB];
     __shared__ double s_row[256 / 64], s_rowl[256 / 64];
+    __shared__ double s_d0[2];
     const int nso = 2 * s.norb, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
         if (tid < WB)
             s_k[tid] = pl_get<WB>(bits, tid, p);
         __syncthreads();
         DD ex = {0.0, 0.0};
+        DD gx = {0.0, 0.0};
+        bool occ = false;
         if (tid < nso) {
             const int bx = tid;
-            const bool occ = (s_k[bx >> 6] >> (bx & 63)) & 1ull;
+            occ = (s_k[bx >> 6] >> (bx & 63)) & 1ull;
             const double hx = s.T[tri_row(bx, nso) + bx];
-            DD gx = {hx, 0.0};
+            gx = {hx, 0.0};
 #pragma unroll
             for (int w = 0; w < WB; w++) {
                 uint64_t m = s_k[w];
@@ -1006,9 +1009,10 @@ __global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t
                         dd_add_pair(gx, s.T, s.Tlo, nso, bx, c, 1.0);
                 }
             }
-            G[2 * (p * nso + bx)] = gx.hi;
-            G[2 * (p * nso + bx) + 1] = gx.lo;
-            if (occ) {
+            if (!occ) {
+                G[2 * (p * nso + bx)] = gx.hi;
+                G[2 * (p * nso + bx) + 1] = gx.lo;
+            } else {
                 ex = gx;
                 dd_add(ex, hx, 0.0);
             }
@@ -1031,6 +1035,14 @@ __global__ __launch_bounds__(256) void k_parent_g(DevSys s, Planes bits, int64_t
             dd_add(d, -0.5 * e2.hi, -0.5 * e2.lo);
             D0[2 * p] = d.hi;
             D0[2 * p + 1] = d.lo;
+            s_d0[0] = d.hi, s_d0[1] = d.lo;
+        }
+        __syncthreads();
+        if (occ) {
+            // occupied entries carry half of D0 (den_parent)
+            dd_add(gx, 0.5 * s_d0[0], 0.5 * s_d0[1]);
+            G[2 * (p * nso + tid)] = gx.hi;
+            G[2 * (p * nso + tid) + 1] = gx.lo;
         }
         __syncthreads();
     }
@@ -1196,9 +1208,15 @@ __device__ inline double den_parent(const double *Tp, const double *Tl, int nso,
             }
         }
     }
+    // G holds g_x + D0/2 for the parent's occupied x (k_parent_g), so a
+    // double's two removed orbitals bring D0 = E0 - E(parent) with them; a
+    // single reads the other half
     const double2 *g = (const double2 *)G + p * nso;
-    const double2 d0 = ((const double2 *)D0)[p];
-    DD d = {d0.x, d0.y};
+    DD d = {0.0, 0.0};
+    if (nr < 2) {
+        const double2 d0 = ((const double2 *)D0)[p];
+        d.hi = nr == 1 ? 0.5 * d0.x : d0.x, d.lo = nr == 1 ? 0.5 * d0.y : d0.y;
+    }
     for (int i = 0; i < nr && i < 2; i++) {
         const double2 v = g[rm[i]];
         dd_add(d, v.x, v.y);
