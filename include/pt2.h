@@ -121,7 +121,10 @@ typedef struct {
                                       and separates determinants whose hashes
                                       collide.  The automatic choice takes the form
                                       that moves the fewest bytes through the digit
-                                      passes if it saves 30% or more               */
+                                      passes if it saves 30% or more (hash records
+                                      priced as 16-byte records of six passes with
+                                      FP32 payloads and hash_bits 0; a tie keeps
+                                      rank keys)                                   */
     int exclusion;                 /* PT2_EXCLUDE_SEARCH (default): drop reference
                                       determinants by a search of the sorted
                                       reference (Section V, direct check);

@@ -1841,6 +1841,11 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
         const bool hash_ok = 2 * norb <= 254;
         if (hash_ok)
             cost_hash = 2.0 * record_bytes(2, pb, 8) * 8;
+        // FP32 payloads with the default hash width: the packed 16-byte
+        // records with at most HC_KEPT_BITS kept bits (rec_layout; assumed
+        // here for a reference list of fewer than HC_MAX_REFS determinants)
+        if (hash_ok && pb == 4 && o.hash_bits == 0 && norb <= HC_MAX_NORB)
+            cost_hash = 2.0 * 16.0 * (HC_KEPT_BITS / 8);
         int mode = 0;  // 0 bitstring, 1 rank, 2 hash
         if (o.compress_keys == 1 && rank_ok)
             mode = 1;
@@ -1852,9 +1857,14 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
             // generation and the single pass.  Measured: (10a,10b)/40 rank
             // keys (8 passes against 10) 224 ms against 192 ms; (14a,14b)/76
             // rank keys (13 against 19) 36.1 s against 39.8 s.
+            // A served FP32 request of 54 orbitals (2.1e9 contributions):
+            // rank keys (78 bits, ten 14-byte passes) 366 ms, sort 187 ms
+            // and single pass 145 ms of it; packed hash records (40 kept
+            // bits, five 16-byte passes) 214 ms, 87 ms and 110 ms.  Equal
+            // costs keep rank keys.
             const double best = std::min(cost_rank, cost_hash);
             if (best <= 0.7 * cost_bits)
-                mode = cost_hash <= cost_rank ? 2 : 1;
+                mode = cost_hash < cost_rank ? 2 : 1;
         }
         if (mode == 1) {
             std::vector<uint64_t> C64(C.size());

@@ -117,6 +117,43 @@ def test_served_results_match_oracle(pt2, reqs):
             ctx.close()
 
 
+def test_served_fp32_packed_hash_records(pt2):
+    """A served FP32 request of 45 orbitals (11 alpha and 11 beta electrons),
+    for which the automatic key form is the packed 16-byte hash record: its
+    first 60 references against the FP64 oracle (1e-6 Eh; counts and key
+    checksums exact), and served twice beside a rank-key request, each result
+    equal to the request evaluated alone."""
+    e0s = {x["index"]: x["e0"] for x in json.load(open(os.path.join(HERE, "golden", "serving_requests.json")))}
+    byidx = {x.index: x for x in synth.serving_requests()}
+    r = byidx[186]
+    assert (r.norb, r.nalpha) == (45, 11)
+    h, eri, dets, c = synth.request_inputs(r)
+    dets, c = dets[:60], c[:60]
+    ref, _ = oracle.Oracle(h, eri, r.norb, r.nalpha, r.nalpha).pt2(dets, c, e0s[186])
+    ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha, precision="fp32", n_streams=4)
+    alone = ctx.evaluate(dets, c, e0s[186])
+    print("fp32 hash", alone["e_pt2"] - ref["e_pt2"], alone["record_bytes"], alone["key_bits"], flush=True)
+    assert alone["record_bytes"] == 16 and alone["key_bits"] <= 48
+    assert abs(alone["e_pt2"] - ref["e_pt2"]) <= 1e-6
+    for k in KEYS[1:]:
+        assert alone[k] == ref[k], (k, alone[k], ref[k])
+    # a rank-key request (the smallest) served beside it
+    q, hq, eq, dq, cq, e0q = small_requests(1)[0]
+    other = pt2.Context(hq, eq, q.norb, q.nalpha, q.nalpha, precision="fp32", n_streams=4)
+    other_alone = other.evaluate(dq, cq, e0q)
+    assert other_alone["record_bytes"] != 16
+    ids = []
+    for rep in range(2):
+        ids.append((ctx, alone, ctx.submit(dets, c, e0s[186])))
+        ids.append((other, other_alone, other.submit(dq, cq, e0q)))
+    for cx, want, rid in ids:
+        got = cx.wait(rid)
+        for k in KEYS + PLAN:
+            assert got[k] == want[k], (k, got[k], want[k])
+    ctx.close()
+    other.close()
+
+
 def test_poll_semantics_and_busy_destroy(pt2, reqs):
     r, h, eri, dets, c, e0 = reqs[-1]
     ctx = pt2.Context(h, eri, r.norb, r.nalpha, r.nalpha)
