@@ -123,8 +123,8 @@ typedef struct {
                                       that moves the fewest bytes through the digit
                                       passes if it saves 30% or more (hash records
                                       priced as 16-byte records of six passes with
-                                      FP32 payloads and hash_bits 0; a tie keeps
-                                      rank keys)                                   */
+                                      FP32 payloads and hash_bits 0; a tie takes
+                                      hash records)                                */
     int exclusion;                 /* PT2_EXCLUDE_SEARCH (default): drop reference
                                       determinants by a search of the sorted
                                       reference (Section V, direct check);

@@ -1861,10 +1861,12 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
             // rank keys (78 bits, ten 14-byte passes) 366 ms, sort 187 ms
             // and single pass 145 ms of it; packed hash records (40 kept
             // bits, five 16-byte passes) 214 ms, 87 ms and 110 ms.  Equal
-            // costs keep rank keys.
+            // costs take hash records, whose FP32 rounding is bounded: at
+            // (10a,10b)/40 with FP32 payloads (60-bit ranks, eight 12-byte
+            // passes) 141.9 ms and 2e-10 Eh off against 162.2 ms and 7e-9.
             const double best = std::min(cost_rank, cost_hash);
             if (best <= 0.7 * cost_bits)
-                mode = cost_hash < cost_rank ? 2 : 1;
+                mode = cost_hash <= cost_rank ? 2 : 1;
         }
         if (mode == 1) {
             std::vector<uint64_t> C64(C.size());
