@@ -225,6 +225,17 @@ void pt2_default_options(pt2_options *opt);
 int pt2_key_words(int norb);
 
 /*
+ * The record form pt2_create takes for these sizes and options (opt may be
+ * NULL: the defaults).  Host only; no device is touched.  *form = 0 bitstring
+ * keys, 1 combinatorial rank keys, 2 hash records (Section V, compression
+ * with hash functions), the values compress_keys forces; *key_bits = the bits
+ * of that key: 2*norb, the two spin ranks' bits, or 64 for hash records, of
+ * which an evaluation keeps 32-64 (hash_bits).  PT2_E_INVALID for a NULL
+ * output, sizes out of range, or an option pt2_create rejects for its value.
+ */
+int pt2_key_form(int norb, int nalpha, int nbeta, const pt2_options *opt, int *form, int *key_bits);
+
+/*
  * Create a context for one Hamiltonian; integrals stay resident on the device.
  *   h    host, norb*norb FP64, row-major, symmetric
  *   eri  host, norb^4 FP64, row-major (pq|rs) at ((p*norb+q)*norb+r)*norb+s,

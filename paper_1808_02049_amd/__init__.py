@@ -73,6 +73,8 @@ _CTX = C.c_void_p
 _SIGS = {
     "pt2_default_options": (None, [C.POINTER(Options)]),
     "pt2_key_words": (C.c_int, [C.c_int]),
+    "pt2_key_form": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(Options), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int)]),
     "pt2_create": (C.c_int, [_f64p, _f64p, C.c_int, C.c_int, C.c_int, C.POINTER(Options),
                              C.POINTER(_CTX)]),
     "pt2_evaluate": (C.c_int, [_CTX, _vp, _vp, C.c_int64, C.c_double, C.POINTER(Result)]),
@@ -107,6 +109,9 @@ class PT2Error(RuntimeError):
         self.code = code
 
 
+_PRECISIONS = {"fp64": PT2_FP64, "fp32": PT2_FP32_PAYLOAD, "fp32-arith": PT2_FP32_ARITH}
+
+
 def _check(rc):
     if rc not in (PT2_OK, PT2_NOT_READY):
         raise PT2Error(rc, (_lib.pt2_last_error() or b"").decode(errors="replace"))
@@ -115,6 +120,21 @@ def _check(rc):
 
 def key_words(norb: int) -> int:
     return _lib.pt2_key_words(norb)
+
+
+KEY_FORMS = ("bitstring", "rank", "hash")
+
+
+def key_form(norb, nalpha, nbeta, precision="fp64", compress_keys=-1, hash_bits=0):
+    """(form, key bits) of the records a context of these sizes and options
+    takes (``pt2_key_form``; host only)."""
+    o = default_options()
+    o.precision = _PRECISIONS[precision]
+    o.compress_keys = int(compress_keys)
+    o.hash_bits = int(hash_bits)
+    form, bits = C.c_int(), C.c_int()
+    _check(_lib.pt2_key_form(int(norb), int(nalpha), int(nbeta), C.byref(o), C.byref(form), C.byref(bits)))
+    return KEY_FORMS[form.value], bits.value
 
 
 def default_options() -> Options:
@@ -176,8 +196,7 @@ class Context:
         self.norb, self.nalpha, self.nbeta = int(norb), int(nalpha), int(nbeta)
         self.W = key_words(self.norb)
         o = default_options()
-        o.precision = {"fp64": PT2_FP64, "fp32": PT2_FP32_PAYLOAD,
-                       "fp32-arith": PT2_FP32_ARITH}[precision]
+        o.precision = _PRECISIONS[precision]
         o.cutoff = float(cutoff)
         o.log2_partitions = int(log2_partitions)
         o.device = int(device)

@@ -1642,6 +1642,117 @@ PT2_API int pt2_key_words(int norb) { return (2 * norb + 63) / 64; }
 
 PT2_API const char *pt2_last_error(void) { return g_err.c_str(); }
 
+// The record form of a context: compress_keys forces one where it applies;
+// the automatic choice (-1) prices each form by the bytes its records move
+// through the digit passes and takes a compressed form only if it saves 30%
+// or more against the bitstring.  Host only.
+struct KeyForm {
+    int mode = 0;  // 0 bitstring, 1 rank, 2 hash
+    int kw = 0, kbits = 0, bb = 0, stride = 0, ktop = 0;
+    std::vector<uint64_t> binom;  // C(x, j), x <= norb, j <= max(na, nb), for rank keys
+};
+
+KeyForm key_form(int norb, int nalpha, int nbeta, const pt2_options &o)
+{
+    KeyForm f;
+    const int pb = o.precision != PT2_FP64 ? 4 : 8;
+    const int W = pt2_key_words(norb);
+    const double cost_bits = 2.0 * record_bytes(W, pb, top_bytes(norb)) * ((2 * norb + 7) / 8);
+    double cost_rank = 1e300, cost_hash = 1e300;
+    // ranks: exact binomials C(x, j), x <= norb, j <= max(na, nb)
+    const int nmax = std::max(nalpha, nbeta), stride = nmax + 1;
+    std::vector<unsigned __int128> C((size_t)(norb + 1) * stride, 0);
+    bool fits = true;
+    for (int x = 0; x <= norb; x++)
+        for (int j = 0; j < stride; j++) {
+            unsigned __int128 v = j == 0 ? 1 : (x == 0 ? 0 : C[(size_t)(x - 1) * stride + j - 1] +
+                                                                 C[(size_t)(x - 1) * stride + j]);
+            C[(size_t)x * stride + j] = v;
+            if (v > (unsigned __int128)UINT64_MAX)
+                fits = false;
+        }
+    auto bits_for = [](unsigned __int128 count) {  // bits of values 0 .. count-1
+        int b = 0;
+        while (count > ((unsigned __int128)1 << b))
+            b++;
+        return b;
+    };
+    const int ba = bits_for(C[(size_t)norb * stride + nalpha]);
+    const int bb = bits_for(C[(size_t)norb * stride + nbeta]);
+    const int kbits = ba + bb;
+    const int kw = std::max(1, (kbits + 63) / 64);
+    const int tb = kbits - 64 * (kw - 1);
+    const int ktop = tb <= 16 ? 2 : (tb <= 32 ? 4 : 8);
+    const bool rank_ok = fits && kw <= 2;
+    if (rank_ok)
+        cost_rank = 2.0 * record_bytes(kw, pb, ktop) * ((kbits + 7) / 8);
+    // hash records: a spin-orbital index per byte, 0xFF marks an unused flip
+    const bool hash_ok = 2 * norb <= 254;
+    if (hash_ok)
+        cost_hash = 2.0 * record_bytes(2, pb, 8) * 8;
+    // FP32 payloads with the default hash width: the packed 16-byte
+    // records with at most HC_KEPT_BITS kept bits (rec_layout; assumed
+    // here for a reference list of fewer than HC_MAX_REFS determinants)
+    if (hash_ok && pb == 4 && o.hash_bits == 0 && norb <= HC_MAX_NORB)
+        cost_hash = 2.0 * 16.0 * (HC_KEPT_BITS / 8);
+    if (o.compress_keys == 1 && rank_ok)
+        f.mode = 1;
+    else if (o.compress_keys == 2 && hash_ok)
+        f.mode = 2;
+    else if (o.compress_keys == -1) {
+        // only a clear saving pays: compressed digits are dense, so a
+        // scatter tile writes shorter runs, and both forms cost time in
+        // generation and the single pass.  Measured: (10a,10b)/40 rank
+        // keys (8 passes against 10) 224 ms against 192 ms; (14a,14b)/76
+        // rank keys (13 against 19) 36.1 s against 39.8 s.
+        // A served FP32 request of 54 orbitals (2.1e9 contributions):
+        // rank keys (78 bits, ten 14-byte passes) 366 ms, sort 187 ms
+        // and single pass 145 ms of it; packed hash records (40 kept
+        // bits, five 16-byte passes) 214 ms, 87 ms and 110 ms.  Equal
+        // costs take hash records, whose FP32 rounding is bounded: at
+        // (10a,10b)/40 with FP32 payloads (60-bit ranks, eight 12-byte
+        // passes) 141.9 ms and 2e-10 Eh off against 162.2 ms and 7e-9.
+        const double best = std::min(cost_rank, cost_hash);
+        if (best <= 0.7 * cost_bits)
+            f.mode = cost_hash <= cost_rank ? 2 : 1;
+    }
+    if (f.mode == 1) {
+        f.kw = kw, f.kbits = kbits, f.bb = bb, f.stride = stride, f.ktop = ktop;
+        f.binom.resize(C.size());
+        for (size_t i = 0; i < C.size(); i++)
+            f.binom[i] = (uint64_t)C[i];
+    }
+    return f;
+}
+
+PT2_API int pt2_key_form(int norb, int nalpha, int nbeta, const pt2_options *opt, int *form, int *key_bits)
+{
+    g_err.clear();
+    if (!form || !key_bits)
+        return fail(PT2_E_INVALID, "form or key_bits is NULL");
+    if (norb < 1 || norb > MAXORB)
+        return fail(PT2_E_INVALID, "norb must be in [1, %d]", MAXORB);
+    if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb)
+        return fail(PT2_E_INVALID, "electron counts out of range");
+    pt2_options o;
+    pt2_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(pt2_options))
+            return fail(PT2_E_INVALID, "pt2_options.struct_size mismatch");
+        o = *opt;
+    }
+    if (o.precision != PT2_FP64 && o.precision != PT2_FP32_PAYLOAD && o.precision != PT2_FP32_ARITH)
+        return fail(PT2_E_INVALID, "unknown precision %d", o.precision);
+    if (o.hash_bits < 0 || o.hash_bits > 64)
+        return fail(PT2_E_INVALID, "hash_bits must be in [0, 64]");
+    if (o.compress_keys < -1 || o.compress_keys > 2)
+        return fail(PT2_E_INVALID, "compress_keys must be -1, 0, 1 or 2");
+    const KeyForm kf = key_form(norb, nalpha, nbeta, o);
+    *form = kf.mode;
+    *key_bits = kf.mode == 1 ? kf.kbits : (kf.mode == 2 ? 64 : 2 * norb);
+    return PT2_OK;
+}
+
 PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha, int nbeta, const pt2_options *opt,
                        pt2_ctx **out)
 {
@@ -1803,83 +1914,19 @@ PT2_API int pt2_create(const double *h, const double *eri, int norb, int nalpha,
     c->sys.z2 = o.spin_flip;
 
     // record keys: the bitstring, the combinatorial rank, or the Zobrist hash
-    // (with the parent and the flips); cost = bytes moved per record by the
-    // digit passes
+    // (with the parent and the flips)
     memset(&c->sys.kc, 0, sizeof c->sys.kc);
     {
-        const int pb = o.precision != PT2_FP64 ? 4 : 8;
-        const double cost_bits = 2.0 * record_bytes(c->W, pb, c->topb) * ((2 * norb + 7) / 8);
-        double cost_rank = 1e300, cost_hash = 1e300;
-        // ranks: exact binomials C(x, j), x <= norb, j <= max(na, nb)
-        const int nmax = std::max(nalpha, nbeta), stride = nmax + 1;
-        std::vector<unsigned __int128> C((size_t)(norb + 1) * stride, 0);
-        bool fits = true;
-        for (int x = 0; x <= norb; x++)
-            for (int j = 0; j < stride; j++) {
-                unsigned __int128 v = j == 0 ? 1 : (x == 0 ? 0 : C[(size_t)(x - 1) * stride + j - 1] +
-                                                                     C[(size_t)(x - 1) * stride + j]);
-                C[(size_t)x * stride + j] = v;
-                if (v > (unsigned __int128)UINT64_MAX)
-                    fits = false;
-            }
-        auto bits_for = [](unsigned __int128 count) {  // bits of values 0 .. count-1
-            int b = 0;
-            while (count > ((unsigned __int128)1 << b))
-                b++;
-            return b;
-        };
-        const int ba = bits_for(C[(size_t)norb * stride + nalpha]);
-        const int bb = bits_for(C[(size_t)norb * stride + nbeta]);
-        const int kbits = ba + bb;
-        const int kw = std::max(1, (kbits + 63) / 64);
-        const int tb = kbits - 64 * (kw - 1);
-        const int ktop = tb <= 16 ? 2 : (tb <= 32 ? 4 : 8);
-        const bool rank_ok = fits && kw <= 2;
-        if (rank_ok)
-            cost_rank = 2.0 * record_bytes(kw, pb, ktop) * ((kbits + 7) / 8);
-        // hash records: a spin-orbital index per byte, 0xFF marks an unused flip
-        const bool hash_ok = 2 * norb <= 254;
-        if (hash_ok)
-            cost_hash = 2.0 * record_bytes(2, pb, 8) * 8;
-        // FP32 payloads with the default hash width: the packed 16-byte
-        // records with at most HC_KEPT_BITS kept bits (rec_layout; assumed
-        // here for a reference list of fewer than HC_MAX_REFS determinants)
-        if (hash_ok && pb == 4 && o.hash_bits == 0 && norb <= HC_MAX_NORB)
-            cost_hash = 2.0 * 16.0 * (HC_KEPT_BITS / 8);
-        int mode = 0;  // 0 bitstring, 1 rank, 2 hash
-        if (o.compress_keys == 1 && rank_ok)
-            mode = 1;
-        else if (o.compress_keys == 2 && hash_ok)
-            mode = 2;
-        else if (o.compress_keys == -1) {
-            // only a clear saving pays: compressed digits are dense, so a
-            // scatter tile writes shorter runs, and both forms cost time in
-            // generation and the single pass.  Measured: (10a,10b)/40 rank
-            // keys (8 passes against 10) 224 ms against 192 ms; (14a,14b)/76
-            // rank keys (13 against 19) 36.1 s against 39.8 s.
-            // A served FP32 request of 54 orbitals (2.1e9 contributions):
-            // rank keys (78 bits, ten 14-byte passes) 366 ms, sort 187 ms
-            // and single pass 145 ms of it; packed hash records (40 kept
-            // bits, five 16-byte passes) 214 ms, 87 ms and 110 ms.  Equal
-            // costs take hash records, whose FP32 rounding is bounded: at
-            // (10a,10b)/40 with FP32 payloads (60-bit ranks, eight 12-byte
-            // passes) 141.9 ms and 2e-10 Eh off against 162.2 ms and 7e-9.
-            const double best = std::min(cost_rank, cost_hash);
-            if (best <= 0.7 * cost_bits)
-                mode = cost_hash <= cost_rank ? 2 : 1;
-        }
-        if (mode == 1) {
-            std::vector<uint64_t> C64(C.size());
-            for (size_t i = 0; i < C.size(); i++)
-                C64[i] = (uint64_t)C[i];
-            if ((rc = buf_alloc(c->A, c->binom, C64.size() * 8)))
+        const KeyForm kf = key_form(norb, nalpha, nbeta, o);
+        if (kf.mode == 1) {
+            if ((rc = buf_alloc(c->A, c->binom, kf.binom.size() * 8)))
                 return rc;
-            HIPCHK(hipMemcpy(c->binom.p, C64.data(), C64.size() * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(c->binom.p, kf.binom.data(), kf.binom.size() * 8, hipMemcpyHostToDevice));
             KeyCodec &k = c->sys.kc;
-            k.on = 1, k.kw = kw, k.kbits = kbits, k.bb = bb, k.stride = stride, k.ktop = ktop;
+            k.on = 1, k.kw = kf.kw, k.kbits = kf.kbits, k.bb = kf.bb, k.stride = kf.stride, k.ktop = kf.ktop;
             k.binom = (const uint64_t *)c->binom.p;
             c->L.rank = 1;
-        } else if (mode == 2) {
+        } else if (kf.mode == 2) {
             c->sys.kc.hash = 1;
             c->sys.kc.hash_mask = o.hash_bits == 0 || o.hash_bits >= 64 ? ~0ull : ((1ull << o.hash_bits) - 1);
         }

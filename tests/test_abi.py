@@ -80,6 +80,41 @@ def test_key_words():
     assert [pt2.key_words(n) for n in (1, 12, 32, 33, 40, 64, 76, 100, 128)] == [1, 1, 1, 2, 2, 2, 3, 4, 4]
 
 
+def test_key_form_rule():
+    """The record form a context takes (pt2_key_form, host only): each form is
+    priced by the bytes its records move through the digit passes, and a
+    compressed form is taken only when it saves 30% against the bitstring."""
+    import paper_1808_02049_amd as pt2
+    kf = pt2.key_form
+    # (4a,4b)/12: 18-bit ranks sort in as many passes as the 24-bit strings
+    assert kf(12, 4, 4) == ("bitstring", 24) and kf(12, 4, 4, "fp32") == ("bitstring", 24)
+    # (10a,10b)/40, FP64: 16-byte rank records in 8 passes save 29% of ten
+    # 18-byte bitstring passes; FP32: 60-bit ranks (eight 12-byte passes) tie
+    # with six packed 16-byte hash passes, and a tie takes hash records
+    assert kf(40, 10, 10) == ("bitstring", 80)
+    assert kf(40, 10, 10, "fp32") == ("hash", 64)
+    # an explicit hash width leaves the unpacked 20-byte FP32 records
+    assert kf(40, 10, 10, "fp32", hash_bits=40) == ("rank", 60)
+    # (14a,14b)/76 and (18a,18b)/100: hash records in both precisions
+    for norb, n in ((76, 14), (100, 18)):
+        for prec in ("fp64", "fp32", "fp32-arith"):
+            assert kf(norb, n, n, prec) == ("hash", 64)
+    # served shapes
+    assert kf(24, 5, 5, "fp32") == ("rank", 32)
+    assert kf(28, 6, 6, "fp32") == ("bitstring", 56)
+    assert kf(54, 12, 12, "fp32") == ("hash", 64)
+    assert kf(54, 12, 12) == ("rank", 78)
+    # forced forms, and rank keys where the ranks do not fit 64 bits
+    assert kf(40, 10, 10, compress_keys=0) == ("bitstring", 80)
+    assert kf(40, 10, 10, compress_keys=1) == ("rank", 60)
+    assert kf(40, 10, 10, compress_keys=2) == ("hash", 64)
+    assert kf(100, 18, 18, compress_keys=1) == ("bitstring", 200)
+    for bad in (dict(norb=0, nalpha=0, nbeta=0), dict(norb=12, nalpha=13, nbeta=0),
+                dict(norb=12, nalpha=4, nbeta=4, compress_keys=3), dict(norb=12, nalpha=4, nbeta=4, hash_bits=65)):
+        with pytest.raises(pt2.PT2Error):
+            kf(**bad)
+
+
 def _sys(norb=4):
     import synth
     h, eri, _ = synth.make_integrals(norb, 4, 1)

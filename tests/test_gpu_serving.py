@@ -134,6 +134,7 @@ def test_served_fp32_packed_hash_records(pt2):
     alone = ctx.evaluate(dets, c, e0s[186])
     print("fp32 hash", alone["e_pt2"] - ref["e_pt2"], alone["record_bytes"], alone["key_bits"], flush=True)
     assert alone["record_bytes"] == 16 and alone["key_bits"] <= 48
+    assert pt2.key_form(r.norb, r.nalpha, r.nalpha, "fp32") == ("hash", 64)
     assert abs(alone["e_pt2"] - ref["e_pt2"]) <= 1e-6
     for k in KEYS[1:]:
         assert alone[k] == ref[k], (k, alone[k], ref[k])
@@ -142,6 +143,7 @@ def test_served_fp32_packed_hash_records(pt2):
     other = pt2.Context(hq, eq, q.norb, q.nalpha, q.nalpha, precision="fp32", n_streams=4)
     other_alone = other.evaluate(dq, cq, e0q)
     assert other_alone["record_bytes"] != 16
+    assert pt2.key_form(q.norb, q.nalpha, q.nalpha, "fp32") == ("rank", other_alone["key_bits"])
     ids = []
     for rep in range(2):
         ids.append((ctx, alone, ctx.submit(dets, c, e0s[186])))
