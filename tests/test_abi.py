@@ -115,6 +115,21 @@ def test_key_form_rule():
             kf(**bad)
 
 
+def test_key_forms_of_the_served_workload():
+    """The 200 served requests (FP32 payloads): 83 take packed hash records
+    (83% of the contributions), 73 rank keys and 44 bitstrings."""
+    import collections
+    import paper_1808_02049_amd as pt2
+    import synth
+    count, share = collections.Counter(), collections.Counter()
+    for r in synth.serving_requests():
+        form, _ = pt2.key_form(r.norb, r.nalpha, r.nalpha, "fp32")
+        count[form] += 1
+        share[form] += r.n_ref * synth.n_excitations_per_det(r.norb, r.nalpha, r.nalpha)
+    assert count == {"hash": 83, "rank": 73, "bitstring": 44}
+    assert 0.82 < share["hash"] / sum(share.values()) < 0.84
+
+
 def _sys(norb=4):
     import synth
     h, eri, _ = synth.make_integrals(norb, 4, 1)
